@@ -1,0 +1,1023 @@
+// Test infrastructure only: a plain, slow CPU reference for exact geodesic
+// distance on triangle meshes (Ying, Xin, He: "Parallel Chen-Han (PCH)
+// Algorithm for Discrete Geodesics"). Only the test suite, the smoke check and
+// the benchmark's CPU-baseline leg load this library. The GPU library shares
+// no code with it.
+//
+// Three computations live here:
+//   * ich      - sequential Chen-Han with Xin-Wang's priority queue and window
+//                filter (ICH, Section 2 and the "Comparison to the ICH
+//                algorithm" paragraph of Section 6). Windows are kept in the
+//                paper's 6-tuple form (d, A, B, d0, d1, e) of Section 3
+//                (Figure 2); the pseudo-source is rebuilt from d0, d1 each time
+//                a window is propagated. Updates of geod_dist and angle_split
+//                are applied immediately.
+//   * replica  - the round-based PCH method (Algorithm 1) run sequentially:
+//                select all windows whose key is at or below a cutoff,
+//                propagate them against the round-start state (delayed update,
+//                Remark 3), then apply the distance and angle events by
+//                minimum (Algorithm 4). Windows keep their pseudo-source as
+//                (px, py) in the edge frame. It logs per-round integer counts.
+//   * dijkstra - shortest paths along mesh edges (an upper bound).
+//
+// Floating point: built with -ffp-contract=off and no fast-math. sqrt and
+// division are IEEE correctly rounded; atan2, sin and cos used per window are
+// this file's own (stated below), so results do not depend on the libm build.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+const double kTwoPi = 2.0 * 3.14159265358979323846;
+const double kHalfPi = 0.5 * 3.14159265358979323846;
+const double kQuarterPi = 0.25 * 3.14159265358979323846;
+// Relative tolerance for "A = v0", "B = v1" and "w occupies v2" (Algorithm 2).
+const double kTau = 1e-12;
+// A distance event is raised only when it lowers geod_dist by more than a
+// relative 1e-12 (d < g * kEv), so rounding noise cannot re-trigger a vertex.
+const double kEv = 1.0 - 1e-12;
+// Interior vertices with total angle above 2 pi + kSaddle are saddles.
+const double kSaddle = 1e-10;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+
+enum { OK = 0, EINVAL_ = -1, EMESH = -2 };
+
+// --------------------------------------------------------------------------
+// own elementary functions (only + - * / sqrt, fixed order)
+// --------------------------------------------------------------------------
+
+// atan on [0, 1]: two half-angle steps, atan(t) = 2 atan(t / (1 + sqrt(1 + t^2))),
+// bring the argument to at most tan(pi/16); then the Maclaurin series of atan
+// with 13 terms, summed by Horner in u^2.
+double orc_atan01(double t) {
+  double u = t / (1.0 + std::sqrt(1.0 + t * t));
+  u = u / (1.0 + std::sqrt(1.0 + u * u));
+  double u2 = u * u;
+  double p = 0.0;
+  for (int i = 12; i >= 0; --i) {
+    double c = 1.0 / (double)(2 * i + 1);
+    if (i & 1) c = -c;
+    p = p * u2 + c;
+  }
+  return 4.0 * (u * p);
+}
+
+double orc_atan2(double y, double x) {
+  double ax = std::fabs(x), ay = std::fabs(y);
+  if (ax == 0.0 && ay == 0.0) return 0.0;
+  double r;
+  if (ay > ax) {
+    r = kHalfPi - orc_atan01(ax / ay);
+  } else {
+    r = orc_atan01(ay / ax);
+  }
+  if (x < 0.0) r = kPi - r;
+  if (y < 0.0) r = -r;
+  return r;
+}
+
+// sin and cos of t in [0, pi]: fold to [0, pi/4] by symmetry, then nested
+// Maclaurin series (11 factors each).
+void orc_sincos01(double u, double* s, double* c) {
+  double u2 = u * u;
+  double ps = 1.0, pc = 1.0;
+  for (int n = 11; n >= 1; --n) {
+    double ds = (double)(2 * n) * (double)(2 * n + 1);
+    double dc = (double)(2 * n - 1) * (double)(2 * n);
+    ps = 1.0 - (u2 / ds) * ps;
+    pc = 1.0 - (u2 / dc) * pc;
+  }
+  *s = u * ps;
+  *c = pc;
+}
+
+void orc_sincos(double t, double* s, double* c) {
+  double sgn_c = 1.0;
+  if (t > kHalfPi) {
+    t = kPi - t;
+    sgn_c = -1.0;
+  }
+  double ss, cc;
+  if (t > kQuarterPi) {
+    orc_sincos01(kHalfPi - t, &cc, &ss);
+  } else {
+    orc_sincos01(t, &ss, &cc);
+  }
+  *s = ss;
+  *c = sgn_c * cc;
+}
+
+// --------------------------------------------------------------------------
+// mesh (Section 4.1: he[3|F|], face of j = j/3, next = 3(j/3) + (j+1)%3)
+// --------------------------------------------------------------------------
+
+inline int32_t nxt(int32_t j) { return 3 * (j / 3) + (j + 1) % 3; }
+inline int32_t prv(int32_t j) { return 3 * (j / 3) + (j + 2) % 3; }
+
+struct OMesh {
+  int64_t nv = 0, nf = 0;
+  std::vector<int32_t> F;      // start vertex of half-edge j
+  std::vector<double> L;       // length of half-edge j
+  std::vector<int32_t> twin;   // opposite half-edge or -1
+  std::vector<double> ax, ay;  // opposite vertex in j's frame (start at 0, end at (L,0))
+  std::vector<double> alpha;   // corner angle at the start of j inside face(j)
+  std::vector<double> phi;     // angular position of j around its start vertex
+  std::vector<double> theta;   // total angle per vertex
+  std::vector<uint8_t> bnd, pseudo;
+  std::vector<int32_t> coff, corner;  // CCW list of outgoing half-edges per vertex
+};
+
+// Kahan's stable form of Heron's formula: 16 area^2 with sides a >= b >= c.
+double kahan16(double p, double q, double r) {
+  double a = p, b = q, c = r;
+  if (a < b) std::swap(a, b);
+  if (b < c) std::swap(b, c);
+  if (a < b) std::swap(a, b);
+  return (a + (b + c)) * (c - (a - b)) * (c + (a - b)) * (a + (b - c));
+}
+
+int build_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* len, OMesh& M) {
+  if (nf <= 0 || nv <= 0) return fail(EINVAL_, "empty mesh");
+  if (3 * nf > (int64_t)INT32_MAX) return fail(EINVAL_, "too many faces");
+  M.nv = nv;
+  M.nf = nf;
+  const int64_t nh = 3 * nf;
+  M.F.assign(faces, faces + nh);
+  M.L.assign(len, len + nh);
+  for (int64_t f = 0; f < nf; ++f) {
+    int32_t a = faces[3 * f], b = faces[3 * f + 1], c = faces[3 * f + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) return fail(EINVAL_, "face index out of range");
+    if (a == b || b == c || a == c) return fail(EMESH, "face with a repeated vertex");
+  }
+  for (int64_t j = 0; j < nh; ++j)
+    if (!(M.L[j] > 0.0) || !std::isfinite(M.L[j])) return fail(EINVAL_, "edge length not positive and finite");
+  // twins by (min, max) vertex pair
+  M.twin.assign(nh, -1);
+  std::unordered_map<uint64_t, int32_t> first;
+  first.reserve(nh * 2);
+  std::vector<uint8_t> paired(nh, 0);
+  for (int64_t j = 0; j < nh; ++j) {
+    uint32_t a = (uint32_t)M.F[j], b = (uint32_t)M.F[nxt((int32_t)j)];
+    uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+    auto it = first.find(key);
+    if (it == first.end()) {
+      first.emplace(key, (int32_t)j);
+    } else {
+      int32_t o = it->second;
+      if (o < 0) return fail(EMESH, "non-manifold edge (more than two faces)");
+      if (M.F[o] == M.F[j]) return fail(EMESH, "inconsistent face orientation");
+      M.twin[j] = o;
+      M.twin[o] = (int32_t)j;
+      it->second = -1;
+    }
+  }
+  for (int64_t j = 0; j < nh; ++j) {
+    int32_t t = M.twin[j];
+    if (t >= 0 && std::fabs(M.L[j] - M.L[t]) > 1e-9 * M.L[j]) return fail(EINVAL_, "twin half-edges differ in length");
+  }
+  // apex coordinates and corner angles
+  M.ax.resize(nh);
+  M.ay.resize(nh);
+  M.alpha.resize(nh);
+  for (int64_t j = 0; j < nh; ++j) {
+    double Lj = M.L[j], lp = M.L[prv((int32_t)j)], ln = M.L[nxt((int32_t)j)];
+    double P = kahan16(Lj, lp, ln);
+    if (!(P > 0.0)) return fail(EMESH, "zero-area face (triangle inequality not strict)");
+    M.ax[j] = ((Lj * Lj + lp * lp) - ln * ln) / (2.0 * Lj);
+    M.ay[j] = std::sqrt(P) / (2.0 * Lj);
+    M.alpha[j] = std::atan2(M.ay[j], M.ax[j]);
+  }
+  // CCW order of outgoing half-edges around every vertex
+  std::vector<int32_t> cnt(nv, 0), bstart(nv, -1), mn(nv, INT32_MAX);
+  for (int64_t j = 0; j < nh; ++j) {
+    int32_t v = M.F[j];
+    cnt[v]++;
+    if (j < mn[v]) mn[v] = (int32_t)j;
+    if (M.twin[j] < 0) {
+      if (bstart[v] >= 0) return fail(EMESH, "non-manifold vertex (two boundary fans)");
+      bstart[v] = (int32_t)j;
+    }
+  }
+  M.coff.assign(nv + 1, 0);
+  for (int64_t v = 0; v < nv; ++v) M.coff[v + 1] = M.coff[v] + cnt[v];
+  M.corner.assign(nh, -1);
+  M.phi.assign(nh, 0.0);
+  M.theta.assign(nv, 0.0);
+  M.bnd.assign(nv, 0);
+  M.pseudo.assign(nv, 0);
+  for (int64_t v = 0; v < nv; ++v) {
+    if (cnt[v] == 0) continue;
+    int32_t h0 = bstart[v] >= 0 ? bstart[v] : mn[v];
+    M.bnd[v] = bstart[v] >= 0;
+    int32_t h = h0, k = 0;
+    double acc = 0.0;
+    while (true) {
+      if (k >= cnt[v]) return fail(EMESH, "non-manifold vertex");
+      M.corner[M.coff[v] + k] = h;
+      M.phi[h] = acc;
+      acc = acc + M.alpha[h];
+      ++k;
+      int32_t t = M.twin[prv(h)];
+      if (t < 0 || t == h0) break;
+      h = t;
+    }
+    if (k != cnt[v]) return fail(EMESH, "non-manifold vertex (several fans)");
+    M.theta[v] = acc;
+    M.pseudo[v] = M.bnd[v] || (acc > kTwoPi + kSaddle);
+  }
+  return OK;
+}
+
+// --------------------------------------------------------------------------
+// window geometry shared by the two loops (Section 3, Algorithm 2)
+// --------------------------------------------------------------------------
+
+struct Ev {
+  int32_t v;
+  double d, th;  // distance, angular position of the incoming ray's back direction
+};
+struct AEv {
+  int32_t e;
+  double D, X;
+};
+struct Cand {
+  int32_t e, src;
+  double b0, b1, px, py, sg, key, d0, d1;
+};
+struct Cnt {
+  int64_t tiny = 0, ich = 0, notwin = 0, kept = 0, dist_ev = 0, ang_ev = 0, fans = 0, fan_kept = 0, deferred = 0;
+};
+
+double key_of(double b0, double b1, double px, double py, double sg) {
+  double dseg;
+  if (px < b0) {
+    double dx = b0 - px;
+    dseg = std::sqrt(dx * dx + py * py);
+  } else if (px > b1) {
+    double dx = px - b1;
+    dseg = std::sqrt(dx * dx + py * py);
+  } else {
+    dseg = -py;
+  }
+  return sg + dseg;
+}
+
+// Distances of a child's endpoints are tested against the endpoint vertices
+// (u0 at c1, u1 at c0) and, for children made by crossing a face, against the
+// third vertex r at the endpoint next to the shared vertex (Figure 4(b)).
+bool child_filter(double c0, double c1, double cpx, double cpy, double sg, double lc, double gu0, double gu1,
+                  bool rtest, bool r_at_c0, double gr, double rdist, double eps_tiny, bool ich_on, Cnt& C) {
+  if (!(c1 - c0 > eps_tiny * lc)) {
+    C.tiny++;
+    return false;
+  }
+  if (!ich_on) return true;
+  double dx1 = c1 - cpx;
+  double f1 = sg + std::sqrt(dx1 * dx1 + cpy * cpy);
+  if (f1 > gu0 + c1) {
+    C.ich++;
+    return false;
+  }
+  double dx0 = c0 - cpx;
+  double f0 = sg + std::sqrt(dx0 * dx0 + cpy * cpy);
+  if (f0 > gu1 + (lc - c0)) {
+    C.ich++;
+    return false;
+  }
+  if (rtest) {
+    double lhs = r_at_c0 ? f0 : f1;
+    if (lhs > gr + rdist) {
+      C.ich++;
+      return false;
+    }
+  }
+  return true;
+}
+
+// Propagate one window (pseudo-source (px, py) in the frame of half-edge e)
+// across face(e) against the state (g, AD, AX). Children are appended to kids,
+// events to dev and aev; nothing in the state is written.
+void propagate(const OMesh& M, double b0, double b1, double px, double py, double sg, int32_t e, int32_t src,
+               const double* g, const double* AD, const double* AX, bool ch_on, bool ich_on, double eps_tiny,
+               std::vector<Ev>& dev, std::vector<AEv>& aev, std::vector<Cand>& kids, Cnt& C) {
+  const int32_t en = nxt(e), ep = prv(e);
+  const double L = M.L[e], x2 = M.ax[e], y2 = M.ay[e];
+  const double l02 = M.L[ep], l12 = M.L[en];
+  const int32_t v0 = M.F[e], v1 = M.F[en], v2 = M.F[ep];
+  const int32_t tl = M.twin[ep], tr = M.twin[en];
+  const double g0 = g[v0], g1 = g[v1], g2 = g[v2];
+  const double tol = kTau * L;
+
+  const double den = y2 - py;
+  const double t = (-py) / den;
+  const double X = px + (x2 - px) * t;
+  const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
+
+  if (b0 <= tol) {
+    double d = sg + std::sqrt(px * px + py * py);
+    if (d < g0 * kEv) {
+      double th = M.pseudo[v0] ? M.phi[e] - orc_atan2(-py, px) : 0.0;
+      dev.push_back({v0, d, th});
+      C.dist_ev++;
+    }
+  }
+  if (b1 >= L - tol) {
+    double dx = px - L;
+    double d = sg + std::sqrt(dx * dx + py * py);
+    if (d < g1 * kEv) {
+      double th = M.pseudo[v1] ? (M.phi[en] + M.alpha[en]) + orc_atan2(-py, L - px) : 0.0;
+      dev.push_back({v1, d, th});
+      C.dist_ev++;
+    }
+  }
+  bool doL = false, doR = false;
+  if (occ) {
+    double dx = x2 - px, dy = y2 - py;
+    double d2 = sg + std::sqrt(dx * dx + dy * dy);
+    if (d2 < g2 * kEv) {
+      double th = 0.0;
+      if (M.pseudo[v2]) {
+        double ux = -x2, uy = -y2, wx = px - x2, wy = py - y2;
+        double cr = ux * wy - uy * wx;
+        double dt = ux * wx + uy * wy;
+        th = M.phi[ep] + orc_atan2(cr, dt);
+      }
+      dev.push_back({v2, d2, th});
+      C.dist_ev++;
+    }
+    if (!ch_on) {
+      doL = doR = true;
+    } else {
+      double Ds = AD[e], Xs = AX[e];
+      if (d2 < Ds) {
+        aev.push_back({e, d2, X});
+        C.ang_ev++;
+        doL = doR = true;
+      } else if (X < Xs - tol) {
+        doL = true;
+      } else if (X > Xs + tol) {
+        doR = true;
+      } else {
+        doL = doR = true;
+      }
+    }
+  } else if (X > b1) {
+    doL = true;
+  } else {
+    doR = true;
+  }
+
+  if (doL) {
+    if (tl < 0) {
+      C.notwin++;
+    } else {
+      double s0, s1;
+      if (b0 == 0.0) {
+        s0 = 0.0;
+      } else {
+        double dn0 = x2 * py + y2 * (b0 - px);
+        s0 = (py * b0) / dn0;
+      }
+      if (occ) {
+        s1 = 1.0;
+      } else {
+        double dn1 = x2 * py + y2 * (b1 - px);
+        s1 = (py * b1) / dn1;
+      }
+      double c0 = s0 * l02, c1 = s1 * l02;
+      if (c0 < 0.0) c0 = 0.0;
+      if (c1 > l02) c1 = l02;
+      double ux = x2 / l02, uy = y2 / l02;
+      double cpx = ux * px + uy * py;
+      double cpy = ux * py - uy * px;
+      if (cpy > 0.0) cpy = 0.0;
+      double rx = ux * c0 - L, ry = uy * c0;
+      double rdist = std::sqrt(rx * rx + ry * ry);
+      if (child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, eps_tiny, ich_on, C)) {
+        Cand k;
+        k.e = tl;
+        k.src = src;
+        k.b0 = c0;
+        k.b1 = c1;
+        k.px = cpx;
+        k.py = cpy;
+        k.sg = sg;
+        k.key = key_of(c0, c1, cpx, cpy, sg);
+        k.d0 = std::sqrt(px * px + py * py);
+        double qx = x2 - px, qy = y2 - py;
+        k.d1 = std::sqrt(qx * qx + qy * qy);
+        kids.push_back(k);
+        C.kept++;
+      }
+    }
+  }
+  if (doR) {
+    if (tr < 0) {
+      C.notwin++;
+    } else {
+      const double ex = L - x2;
+      double r0, r1;
+      if (occ) {
+        r0 = 0.0;
+      } else {
+        double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
+        double dn0 = y2 * (b0 - px) - ex * py;
+        r0 = nm0 / dn0;
+      }
+      if (b1 == L) {
+        r1 = 1.0;
+      } else {
+        double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
+        double dn1 = y2 * (b1 - px) - ex * py;
+        r1 = nm1 / dn1;
+      }
+      double c0 = r0 * l12, c1 = r1 * l12;
+      if (c0 < 0.0) c0 = 0.0;
+      if (c1 > l12) c1 = l12;
+      double ux = ex / l12, uy = (-y2) / l12;
+      double qx = px - x2, qy = py - y2;
+      double cpx = ux * qx + uy * qy;
+      double cpy = ux * qy - uy * qx;
+      if (cpy > 0.0) cpy = 0.0;
+      double rx = x2 + ux * c1, ry = y2 + uy * c1;
+      double rdist = std::sqrt(rx * rx + ry * ry);
+      if (child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, eps_tiny, ich_on, C)) {
+        Cand k;
+        k.e = tr;
+        k.src = src;
+        k.b0 = c0;
+        k.b1 = c1;
+        k.px = cpx;
+        k.py = cpy;
+        k.sg = sg;
+        k.key = key_of(c0, c1, cpx, cpy, sg);
+        double wx = x2 - px, wy = y2 - py;
+        k.d0 = std::sqrt(wx * wx + wy * wy);
+        double zx = L - px;
+        k.d1 = std::sqrt(zx * zx + py * py);
+        kids.push_back(k);
+        C.kept++;
+      }
+    }
+  }
+}
+
+// Windows from a pseudo-source vertex v reached at distance d (Figure 3(c)):
+// one window on the far side of every face edge opposite v whose corner meets
+// the sector of directions that keep an angle of at least pi to the incoming
+// ray on both sides (the MMP theorem, Section 3). full = every direction
+// (used for sources). Endpoint vertices in the sector get deferred events.
+void fan(const OMesh& M, int32_t v, double d, double th, bool full, const double* g, double eps_tiny, bool ich_on,
+         std::vector<Cand>& wins, std::vector<Ev>& deferred, Cnt& C) {
+  const double Th = M.theta[v];
+  const bool bd = M.bnd[v];
+  C.fans++;
+  for (int32_t q = M.coff[v]; q < M.coff[v + 1]; ++q) {
+    const int32_t j = M.corner[q];
+    const double al = M.alpha[j];
+    double t0, t1;
+    if (full) {
+      t0 = 0.0;
+      t1 = al;
+    } else if (!bd) {
+      double rel = M.phi[j] - th;
+      if (!std::isfinite(rel)) continue;
+      while (rel < 0.0) rel += Th;
+      while (rel >= Th) rel -= Th;
+      double lo = kPi - rel;
+      double hi = (Th - kPi) - rel;
+      t0 = lo > 0.0 ? lo : 0.0;
+      t1 = hi < al ? hi : al;
+      if (!(t0 <= t1)) continue;
+    } else {
+      double rel = M.phi[j] - th;
+      double hiA = -kPi - rel;
+      double loB = kPi - rel;
+      if (hiA >= 0.0) {
+        t0 = 0.0;
+        t1 = hiA < al ? hiA : al;
+      } else if (loB <= al) {
+        t0 = loB > 0.0 ? loB : 0.0;
+        t1 = al;
+      } else {
+        continue;
+      }
+    }
+    const int32_t n = nxt(j), pj = prv(j);
+    const int32_t a = M.F[n], b = M.F[pj];
+    if (t0 <= 0.0) {
+      double da = d + M.L[j];
+      if (da < g[a] * kEv) {
+        deferred.push_back({a, da, M.phi[n] + M.alpha[n]});
+        C.deferred++;
+      }
+    }
+    if (t1 >= al && M.twin[pj] < 0) {
+      double db = d + M.L[pj];
+      if (db < g[b] * kEv) {
+        deferred.push_back({b, db, M.phi[pj]});
+        C.deferred++;
+      }
+    }
+    const int32_t tw = M.twin[n];
+    if (tw < 0) {
+      C.notwin++;
+      continue;
+    }
+    const double Ln = M.L[n], x2n = M.ax[n], y2n = M.ay[n];
+    const double ipx = Ln - x2n, ipy = -y2n;
+    double c0, c1;
+    if (t1 >= al) {
+      c0 = 0.0;
+    } else {
+      double s, c;
+      orc_sincos(t1, &s, &c);
+      double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+      c0 = ipx - ipy * (dx / dy);
+    }
+    if (t0 <= 0.0) {
+      c1 = Ln;
+    } else {
+      double s, c;
+      orc_sincos(t0, &s, &c);
+      double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+      c1 = ipx - ipy * (dx / dy);
+    }
+    if (c0 < 0.0) c0 = 0.0;
+    if (c1 > Ln) c1 = Ln;
+    // endpoints: tw runs from b (u0) to a (u1)
+    if (!child_filter(c0, c1, ipx, ipy, d, Ln, g[b], g[a], false, false, 0.0, 0.0, eps_tiny, ich_on, C)) continue;
+    Cand k;
+    k.e = tw;
+    k.src = v;
+    k.b0 = c0;
+    k.b1 = c1;
+    k.px = ipx;
+    k.py = ipy;
+    k.sg = d;
+    k.key = key_of(c0, c1, ipx, ipy, d);
+    k.d0 = M.L[pj];
+    k.d1 = M.L[j];
+    wins.push_back(k);
+    C.fan_kept++;
+  }
+}
+
+// --------------------------------------------------------------------------
+// ICH: priority queue, immediate updates, paper's (d0, d1) window form
+// --------------------------------------------------------------------------
+
+struct IWin {
+  double key;
+  int64_t seq;
+  double sg, b0, b1, d0, d1;
+  int32_t e, src;
+};
+struct IWinCmp {
+  bool operator()(const IWin& a, const IWin& b) const {
+    if (a.key != b.key) return a.key > b.key;
+    return a.seq > b.seq;
+  }
+};
+
+// Pseudo-source in the edge frame from the distances to the edge endpoints
+// (Figure 2(b)); it lies on the side away from face(e).
+void rebuild(double L, double d0, double d1, double* px, double* py) {
+  double x = ((L * L + d0 * d0) - d1 * d1) / (2.0 * L);
+  double t = d0 * d0 - x * x;
+  *px = x;
+  *py = -std::sqrt(t > 0.0 ? t : 0.0);
+}
+
+int run_ich(const OMesh& M, const int32_t* src, int32_t m, double eps_tiny, int32_t filters, double* dist,
+            int64_t* stats) {
+  const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
+  const int64_t nh = 3 * M.nf;
+  std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
+  std::priority_queue<IWin, std::vector<IWin>, IWinCmp> pq;
+  int64_t seq = 0, created = 0, processed = 0, stale = 0, peak = 0, updates = 0, ang_updates = 0;
+  Cnt C;
+  std::vector<Cand> wins;
+  std::vector<Ev> stack, dev;
+  std::vector<AEv> aev;
+
+  auto push_all = [&](std::vector<Cand>& ws) {
+    for (const Cand& k : ws) {
+      double px, py;
+      double Lk = M.L[k.e];
+      rebuild(Lk, k.d0, k.d1, &px, &py);
+      IWin w;
+      w.key = key_of(k.b0, k.b1, px, py, k.sg);
+      w.seq = seq++;
+      w.sg = k.sg;
+      w.b0 = k.b0;
+      w.b1 = k.b1;
+      w.d0 = k.d0;
+      w.d1 = k.d1;
+      w.e = k.e;
+      w.src = k.src;
+      pq.push(w);
+      created++;
+    }
+    ws.clear();
+    if ((int64_t)pq.size() > peak) peak = (int64_t)pq.size();
+  };
+  // apply distance updates immediately, expanding fans at pseudo-sources
+  auto drain = [&]() {
+    while (!stack.empty()) {
+      Ev ev = stack.back();
+      stack.pop_back();
+      if (!(ev.d < g[ev.v] * kEv)) continue;
+      g[ev.v] = ev.d;
+      updates++;
+      if (M.pseudo[ev.v]) {
+        std::vector<Ev> dfr;
+        fan(M, ev.v, ev.d, ev.th, full_fan, g.data(), eps_tiny, ich_on, wins, dfr, C);
+        for (const Ev& x : dfr) stack.push_back(x);
+      }
+    }
+    push_all(wins);
+  };
+
+  for (int32_t i = 0; i < m; ++i) g[src[i]] = 0.0;
+  for (int32_t i = 0; i < m; ++i) {
+    std::vector<Ev> dfr;
+    fan(M, src[i], 0.0, 0.0, true, g.data(), eps_tiny, ich_on, wins, dfr, C);
+    for (const Ev& x : dfr) stack.push_back(x);
+  }
+  drain();
+  while (!pq.empty()) {
+    IWin w = pq.top();
+    pq.pop();
+    if (w.sg > g[w.src]) {
+      stale++;
+      continue;
+    }
+    processed++;
+    double px, py;
+    rebuild(M.L[w.e], w.d0, w.d1, &px, &py);
+    dev.clear();
+    aev.clear();
+    std::vector<Cand> kids;
+    propagate(M, w.b0, w.b1, px, py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, eps_tiny, dev,
+              aev, kids, C);
+    for (const AEv& a : aev) {
+      if (a.D < AD[a.e] || (a.D == AD[a.e] && a.X < AX[a.e])) {
+        AD[a.e] = a.D;
+        AX[a.e] = a.X;
+        ang_updates++;
+      }
+    }
+    for (const Ev& x : dev) stack.push_back(x);
+    drain();
+    push_all(kids);
+  }
+  for (int64_t v = 0; v < M.nv; ++v) dist[v] = g[v];
+  if (stats) {
+    int64_t s[16] = {created, processed, stale, C.tiny, C.ich, updates, ang_updates, C.fans, C.fan_kept, 0, peak,
+                     C.notwin, C.deferred, 0, 0, 0};
+    std::memcpy(stats, s, sizeof(s));
+  }
+  return OK;
+}
+
+// --------------------------------------------------------------------------
+// replica: round-based PCH with delayed updates
+// --------------------------------------------------------------------------
+
+inline uint64_t bits_of(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, 8);
+  return u;
+}
+
+// Round cutoff: keys (non-negative doubles) compared as uint64 bit patterns.
+// With mn, mx the smallest and largest pattern and p the highest bit where they
+// differ, patterns are truncated by s = max(p + 1 - 36, 0) bits; the cutoff is
+// the k-th smallest truncated value T (1-based) and a window is selected when
+// its truncated key is <= T. If N <= k every window is selected.
+struct Cut {
+  bool all;
+  int shift;
+  uint64_t T;
+};
+
+Cut pick_cutoff(const std::vector<double>& keys, int64_t k) {
+  Cut c{true, 0, 0};
+  const int64_t N = (int64_t)keys.size();
+  if (N <= k) return c;
+  uint64_t mn = UINT64_MAX, mx = 0;
+  for (double x : keys) {
+    uint64_t u = bits_of(x);
+    mn = std::min(mn, u);
+    mx = std::max(mx, u);
+  }
+  c.all = false;
+  uint64_t dif = mn ^ mx;
+  if (dif == 0) {
+    c.shift = 0;
+    c.T = mx;
+    return c;
+  }
+  int p = 63 - __builtin_clzll(dif);
+  int s = p + 1 - 36;
+  if (s < 0) s = 0;
+  std::vector<uint64_t> t(N);
+  for (int64_t i = 0; i < N; ++i) t[i] = bits_of(keys[i]) >> s;
+  std::nth_element(t.begin(), t.begin() + (k - 1), t.end());
+  c.shift = s;
+  c.T = t[k - 1];
+  return c;
+}
+
+struct RWin {
+  double b0, b1, px, py, sg, key;
+  int32_t e, src;
+};
+
+// round log record (int64 each)
+enum {
+  RL_N = 0, RL_CUTBITS, RL_SHIFT, RL_SEL, RL_STALE, RL_KIDS, RL_TINY, RL_ICH, RL_DEV, RL_AEV, RL_FANS, RL_FANWIN,
+  RL_DEFER, RL_NEND, RL_WIDTH
+};
+
+int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double eps_tiny, int32_t filters,
+                const double* cut_table, int64_t n_cut, double* dist, int64_t* stats, int64_t* rlog,
+                int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
+  const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
+  const int64_t nh = 3 * M.nf;
+  std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
+  std::vector<RWin> pool, nextp;
+  std::vector<Ev> pending, dev, dfr;
+  std::vector<AEv> aev;
+  std::vector<Cand> kids, fw;
+  std::vector<double> fan_th(M.nv, INFINITY);
+  std::vector<int32_t> touched;
+  Cnt Ctot;
+  int64_t created = 0, processed = 0, stale_tot = 0, peak = 0, rounds = 0, updates = 0, ang_updates = 0;
+
+  auto add = [&](std::vector<RWin>& P, const std::vector<Cand>& ks) {
+    for (const Cand& c : ks) P.push_back({c.b0, c.b1, c.px, c.py, c.sg, c.key, c.e, c.src});
+    created += (int64_t)ks.size();
+  };
+
+  for (int32_t i = 0; i < m; ++i) g[src[i]] = 0.0;
+  {
+    Cnt C;
+    for (int32_t i = 0; i < m; ++i) fan(M, src[i], 0.0, 0.0, true, g.data(), eps_tiny, ich_on, fw, pending, C);
+    add(pool, fw);
+    fw.clear();
+  }
+  while (!pool.empty() || !pending.empty()) {
+    Cnt C;
+    const int64_t N = (int64_t)pool.size();
+    peak = std::max(peak, N);
+    std::vector<double> keys(N);
+    for (int64_t i = 0; i < N; ++i) keys[i] = pool[i].key;
+    bool ext = cut_table != nullptr && rounds < n_cut;
+    Cut cut{true, 0, 0};
+    double cval = INFINITY;
+    if (ext) {
+      cval = cut_table[rounds];
+    } else {
+      cut = pick_cutoff(keys, k);
+    }
+    nextp.clear();
+    dev.clear();
+    aev.clear();
+    kids.clear();
+    int64_t nsel = 0, nstale = 0;
+    // snapshot semantics: every selected window reads the same g, AD, AX
+    for (int64_t i = 0; i < N; ++i) {
+      const RWin& w = pool[i];
+      if (w.sg > g[w.src]) {
+        nstale++;
+        continue;
+      }
+      bool sel;
+      if (ext) {
+        sel = w.key <= cval;
+      } else {
+        sel = cut.all || ((bits_of(w.key) >> cut.shift) <= cut.T);
+      }
+      if (!sel) {
+        nextp.push_back(w);
+        continue;
+      }
+      nsel++;
+      propagate(M, w.b0, w.b1, w.px, w.py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, eps_tiny,
+                dev, aev, kids, C);
+    }
+    add(nextp, kids);
+    const int64_t ndev_prop = (int64_t)dev.size();
+    for (const Ev& x : pending) dev.push_back(x);
+    pending.clear();
+    // Algorithm 4: the smallest value per key wins
+    for (const Ev& x : dev) {
+      if (x.d < g[x.v]) {
+        g[x.v] = x.d;
+      }
+    }
+    for (const AEv& a : aev) {
+      if (a.D < AD[a.e] || (a.D == AD[a.e] && a.X < AX[a.e])) {
+        AD[a.e] = a.D;
+        AX[a.e] = a.X;
+      }
+    }
+    ang_updates += (int64_t)aev.size();
+    // One fan per pseudo-source vertex whose distance this round's events
+    // lowered: among the winning events (d equal to the new geod_dist) the one
+    // with the smallest incoming angle. Arrivals with equal distance from other
+    // directions need no fan of their own: a direction outside the chosen
+    // sector bends by less than pi against the chosen arrival, so a shorter
+    // path exists.
+    fw.clear();
+    int64_t nfans = 0;
+    touched.clear();
+    for (const Ev& x : dev) {
+      if (x.d != g[x.v]) continue;
+      if (fan_th[x.v] == INFINITY) touched.push_back(x.v);
+      if (x.th < fan_th[x.v]) fan_th[x.v] = x.th;
+    }
+    for (int32_t v : touched) {
+      updates++;
+      if (vupd) vupd[v]++;
+      if (M.pseudo[v]) {
+        fan(M, v, g[v], fan_th[v], full_fan, g.data(), eps_tiny, ich_on, fw, pending, C);
+        nfans++;
+      }
+      fan_th[v] = INFINITY;
+    }
+    add(nextp, fw);
+    if (rlog && rounds < max_log) {
+      int64_t* r = rlog + rounds * RL_WIDTH;
+      r[RL_N] = N;
+      r[RL_CUTBITS] = ext ? (int64_t)bits_of(cval) : (cut.all ? -1 : (int64_t)cut.T);
+      r[RL_SHIFT] = ext ? -2 : cut.shift;
+      r[RL_SEL] = nsel;
+      r[RL_STALE] = nstale;
+      r[RL_KIDS] = C.kept;
+      r[RL_TINY] = C.tiny;
+      r[RL_ICH] = C.ich;
+      r[RL_DEV] = ndev_prop;
+      r[RL_AEV] = (int64_t)aev.size();
+      r[RL_FANS] = nfans;
+      r[RL_FANWIN] = C.fan_kept;
+      r[RL_DEFER] = (int64_t)pending.size();
+      r[RL_NEND] = (int64_t)nextp.size();
+    }
+    processed += nsel;
+    stale_tot += nstale;
+    Ctot.tiny += C.tiny;
+    Ctot.ich += C.ich;
+    Ctot.fans += C.fans;
+    Ctot.fan_kept += C.fan_kept;
+    Ctot.notwin += C.notwin;
+    Ctot.deferred += C.deferred;
+    pool.swap(nextp);
+    rounds++;
+  }
+  for (int64_t v = 0; v < M.nv; ++v) dist[v] = g[v];
+  if (n_rounds) *n_rounds = rounds;
+  if (stats) {
+    int64_t s[16] = {created, processed, stale_tot, Ctot.tiny, Ctot.ich, updates, ang_updates, Ctot.fans,
+                     Ctot.fan_kept, rounds, peak, Ctot.notwin, Ctot.deferred, 0, 0, 0};
+    std::memcpy(stats, s, sizeof(s));
+  }
+  return OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// C entry points (ctypes)
+// --------------------------------------------------------------------------
+extern "C" {
+
+const char* orc_last_error(void) { return g_err.c_str(); }
+
+// Half-edge lengths from coordinates: sqrt((dx*dx + dy*dy) + dz*dz), with
+// d = xyz[end] - xyz[start].
+int orc_lengths(const double* xyz, int64_t nv, const int32_t* faces, int64_t nf, double* he_len) {
+  for (int64_t f = 0; f < nf; ++f) {
+    for (int i = 0; i < 3; ++i) {
+      int32_t a = faces[3 * f + i], b = faces[3 * f + (i + 1) % 3];
+      if (a < 0 || b < 0 || a >= nv || b >= nv) return fail(EINVAL_, "face index out of range");
+      double dx = xyz[3 * b] - xyz[3 * a];
+      double dy = xyz[3 * b + 1] - xyz[3 * a + 1];
+      double dz = xyz[3 * b + 2] - xyz[3 * a + 2];
+      he_len[3 * f + i] = std::sqrt((dx * dx + dy * dy) + dz * dz);
+    }
+  }
+  return OK;
+}
+
+// Mesh tables for tests: twin[3nf], ax/ay/alpha/phi[3nf], theta[nv], flags[nv]
+// (bit 0 boundary, bit 1 pseudo-source).
+int orc_mesh_info(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, int32_t* twin, double* ax,
+                  double* ay, double* alpha, double* phi, double* theta, uint8_t* flags) {
+  OMesh M;
+  int rc = build_mesh(faces, nf, nv, he_len, M);
+  if (rc) return rc;
+  const int64_t nh = 3 * nf;
+  for (int64_t j = 0; j < nh; ++j) {
+    twin[j] = M.twin[j];
+    ax[j] = M.ax[j];
+    ay[j] = M.ay[j];
+    alpha[j] = M.alpha[j];
+    phi[j] = M.phi[j];
+  }
+  for (int64_t v = 0; v < nv; ++v) {
+    theta[v] = M.theta[v];
+    flags[v] = (uint8_t)(M.bnd[v] | (M.pseudo[v] << 1));
+  }
+  return OK;
+}
+
+static int check_sources(const int32_t* src, int32_t m, int64_t nv) {
+  if (m <= 0) return fail(EINVAL_, "no source vertex");
+  for (int32_t i = 0; i < m; ++i)
+    if (src[i] < 0 || src[i] >= nv) return fail(EINVAL_, "source vertex out of range");
+  return OK;
+}
+
+int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
+            double eps_tiny, int32_t filters, double* dist, int64_t* stats) {
+  OMesh M;
+  int rc = build_mesh(faces, nf, nv, he_len, M);
+  if (rc) return rc;
+  rc = check_sources(src, m, nv);
+  if (rc) return rc;
+  std::vector<int32_t> s(src, src + m);
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  return run_ich(M, s.data(), (int32_t)s.size(), eps_tiny, filters, dist, stats);
+}
+
+int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
+                int64_t k, double eps_tiny, int32_t filters, const double* cut_table, int64_t n_cut, double* dist,
+                int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
+  OMesh M;
+  int rc = build_mesh(faces, nf, nv, he_len, M);
+  if (rc) return rc;
+  rc = check_sources(src, m, nv);
+  if (rc) return rc;
+  if (k < 1 && cut_table == nullptr) return fail(EINVAL_, "k must be >= 1");
+  std::vector<int32_t> s(src, src + m);
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  return run_replica(M, s.data(), (int32_t)s.size(), k, eps_tiny, filters, cut_table, n_cut, dist, stats, rlog,
+                     max_log, n_rounds, vupd);
+}
+
+// Dijkstra along mesh edges (length of the best edge path).
+int orc_dijkstra(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
+                 double* dist) {
+  int rc = check_sources(src, m, nv);
+  if (rc) return rc;
+  std::vector<std::vector<std::pair<int32_t, double>>> adj(nv);
+  for (int64_t j = 0; j < 3 * nf; ++j) {
+    int32_t a = faces[j], b = faces[nxt((int32_t)j)];
+    adj[a].push_back({b, he_len[j]});
+    adj[b].push_back({a, he_len[j]});
+  }
+  for (int64_t v = 0; v < nv; ++v) dist[v] = INFINITY;
+  typedef std::pair<double, int32_t> QE;
+  std::priority_queue<QE, std::vector<QE>, std::greater<QE>> q;
+  for (int32_t i = 0; i < m; ++i) {
+    dist[src[i]] = 0.0;
+    q.push({0.0, src[i]});
+  }
+  while (!q.empty()) {
+    QE t = q.top();
+    q.pop();
+    if (t.first > dist[t.second]) continue;
+    for (auto& e : adj[t.second]) {
+      double nd = t.first + e.second;
+      if (nd < dist[e.first]) {
+        dist[e.first] = nd;
+        q.push({nd, e.first});
+      }
+    }
+  }
+  return OK;
+}
+
+// Own elementary functions, exported so tests can check them against libm.
+double orc_fn_atan2(double y, double x) { return orc_atan2(y, x); }
+void orc_fn_sincos(double t, double* s, double* c) { orc_sincos(t, s, c); }
+
+}  // extern "C"
