@@ -1,0 +1,139 @@
+/*
+ * pch.h - exact geodesic distance on triangle meshes with the Parallel
+ * Chen-Han (PCH) method on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Algorithm 1, "Require"/"Ensure"): given a triangle mesh
+ * M = (V, E, F) and source vertices S, compute for every vertex the length of
+ * the shortest path to S on the polyhedral surface. Only edge lengths are
+ * needed (Section 4.1), so a mesh can be given by coordinates or by
+ * per-half-edge lengths.
+ *
+ * Each round of the method (Section 4.2) runs as device kernels: window
+ * selection, window propagation (Algorithm 2), data organization
+ * (Algorithm 3) and event processing (Algorithm 4). All state stays in device
+ * memory; the host only enqueues rounds.
+ *
+ * Conventions
+ *  - Every call returns pch_status: PCH_OK (0) or a negative error code. The
+ *    message of the last error on the calling thread is pch_last_error().
+ *  - Faces are int32 [nf][3], counter-clockwise; half-edge j = 3 f + i runs
+ *    from faces[f][i] to faces[f][(i + 1) % 3] (Section 4.1).
+ *  - Host arrays passed in are read during the call and not kept (the
+ *    library copies what it needs). Output arrays marked "device" must be
+ *    device memory (e.g. a torch tensor's data_ptr()) of at least the stated
+ *    size; the caller owns them.
+ *  - hip_stream is a hipStream_t (NULL = the default stream). Work is
+ *    ordered on that stream; calls return after the result is complete.
+ *  - Unreachable vertices get +infinity; sources get 0.
+ *  - The library keeps no global mutable state apart from the thread-local
+ *    error text; a mesh handle must not be used by two threads at once.
+ */
+#ifndef PCH_H
+#define PCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCH_OK = 0,
+  PCH_EINVAL = -1,    /* bad argument: null pointer, size, source index, option */
+  PCH_EMESH = -2,     /* non-manifold edge or vertex, inconsistent orientation,
+                         zero-area face */
+  PCH_ENOMEM = -3,    /* device or host allocation failed */
+  PCH_EDEVICE = -4,   /* a HIP call failed (message has the HIP error) */
+  PCH_EOVERFLOW = -5, /* window pool would exceed options.pool_limit */
+  PCH_ENUMERIC = -6   /* non-finite value in window geometry */
+} pch_status;
+
+typedef struct pch_mesh_s* pch_mesh;
+
+/* Mesh from vertex coordinates.
+ *  xyz    host double [nv][3]
+ *  faces  host int32  [nf][3], CCW, indices in [0, nv)
+ * Edge lengths are sqrt((dx*dx + dy*dy) + dz*dz). The handle owns device
+ * copies of the half-edge geometry (Section 4.1 and Table 1) until
+ * pch_mesh_destroy. Errors: PCH_EINVAL (sizes, indices), PCH_EMESH. */
+pch_status pch_mesh_create(const double* xyz, int64_t nv, const int32_t* faces, int64_t nf,
+                           void* hip_stream, pch_mesh* out);
+
+/* Mesh from the metric only (Section 4.1: "it needs only the metric").
+ *  he_len host double [3 nf]: length of half-edge j; the two half-edges of
+ *         an interior edge must agree to 1e-9 relative. */
+pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv,
+                                        const double* he_len, void* hip_stream, pch_mesh* out);
+
+void pch_mesh_destroy(pch_mesh mesh);
+
+/* Sizes and classification: counts of vertices, faces, boundary half-edges
+ * and pseudo-source vertices (boundary or saddle, Section 3). Any output
+ * pointer may be NULL. */
+pch_status pch_mesh_info(pch_mesh mesh, int64_t* nv, int64_t* nf, int64_t* n_boundary_he,
+                         int64_t* n_pseudo);
+
+/* Host copies of the per-vertex tables: total angle (double [nv]) and flags
+ * (uint8 [nv]: bit 0 boundary, bit 1 pseudo-source). Either may be NULL. */
+pch_status pch_mesh_vertex_tables(pch_mesh mesh, double* theta, uint8_t* flags);
+
+/* Selection rules (Section 4.2 step 1 and Section 5.1). */
+enum {
+  PCH_SELECT_KTH = 0,   /* the k smallest keys, to 36 bits below the top
+                           differing bit of the pool's key range; ties kept */
+  PCH_SELECT_TABLE = 2  /* per-round cutoff values from options.cutoff_table
+                           (select key <= cutoff); after the table, KTH */
+};
+
+typedef struct {
+  int32_t select_mode;        /* PCH_SELECT_* (default PCH_SELECT_KTH) */
+  int32_t filters;            /* bit 0 CH one-angle-one-split, bit 1 ICH window
+                                 filter, bit 2 full fans (default 3) */
+  int64_t k;                  /* windows per round for PCH_SELECT_KTH (default 16384) */
+  double eps_tiny;            /* drop children narrower than eps_tiny * edge
+                                 length (Section 5.3 uses 1e-6; default 0) */
+  int64_t pool_capacity;      /* initial window capacity; 0 = from mesh size */
+  int64_t pool_limit;         /* growth cap in windows; 0 = no cap */
+  int32_t collect_stats;      /* 1 = per-round counts (see pch_round_log) */
+  int32_t rounds_per_sync;    /* rounds enqueued between host polls (default 16) */
+  const double* cutoff_table; /* host, n_cutoff values, PCH_SELECT_TABLE */
+  int64_t n_cutoff;
+} pch_options;
+
+/* Fill opts with the defaults above. */
+void pch_options_default(pch_options* opts);
+
+typedef struct {
+  int64_t rounds, created, processed, stale, tiny, ich_dropped, dist_events, angle_events,
+      fans, fan_windows, deferred, peak_pool, restarts;
+  double ms_total;
+} pch_stats;
+
+/* Exact geodesic distance from the sources (Algorithm 1).
+ *  sources  host int32 [m]; m > 1 gives the min field over all sources
+ *           (Section 4.2); duplicates are allowed
+ *  dist     device double [nv], written in full
+ *  opts     NULL = defaults; stats may be NULL
+ * If the window pool outgrows its capacity the run restarts with twice the
+ * capacity (stats->restarts counts them); PCH_EOVERFLOW if that would pass
+ * opts->pool_limit. Errors: PCH_EINVAL (source out of range, m < 1, bad
+ * option), PCH_ENOMEM, PCH_EDEVICE, PCH_ENUMERIC. */
+pch_status pch_geodesic(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist,
+                        void* hip_stream, const pch_options* opts, pch_stats* stats);
+
+/* Per-round integer log of the last pch_geodesic call on this mesh that had
+ * opts->collect_stats set, one int64 [14] record per round:
+ *   pool size at round start, cutoff (bit pattern >> shift, -1 = all),
+ *   shift, selected, stale dropped, children kept, tiny dropped, ICH
+ *   dropped, distance events from propagation, angle events, fans,
+ *   fan windows kept, deferred fan events, pool size at round end.
+ * Writes min(max_rounds, rounds) records to out (host); *n_rounds = rounds. */
+pch_status pch_round_log(pch_mesh mesh, int64_t* out, int64_t max_rounds, int64_t* n_rounds);
+
+const char* pch_status_string(pch_status s);
+const char* pch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCH_H */

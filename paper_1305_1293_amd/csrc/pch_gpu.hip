@@ -1,0 +1,1474 @@
+// PCH round pipeline on gfx950: device kernels, the host round driver and the
+// C ABI of include/pch.h.
+//
+// One round (Section 4.2, Algorithm 1) is a fixed sequence of kernels on one
+// stream; counts live in device memory, so rounds are enqueued back to back
+// and the host only polls a done flag every few rounds:
+//   begin      - close the previous round's log record, set up selection
+//   hist/scan  - three 12-bit histogram passes give the k-th smallest key
+//                (selection, step 1)
+//   partition  - drop stale windows, split the pool into selected windows and
+//                survivors (the gap-free pool of Section 4.1 and Algorithm 3)
+//   propagate  - Algorithm 2 for every selected window against the round-start
+//                state; children and events are appended with one atomic per
+//                wavefront (Algorithm 3's prefix sum, done per wave)
+//   events 1-3 - Algorithm 4: per-vertex minimum of distance events, per-corner
+//                lexicographic minimum of angle events, then one fan of
+//                windows per improved pseudo-source vertex (Figure 3(c))
+//
+// All window geometry is FP64; the file is compiled with FP contraction off so
+// results do not depend on instruction selection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pch.h"
+#include "pch_internal.h"
+
+using u64 = unsigned long long;
+using u32 = unsigned int;
+
+namespace {
+
+thread_local std::string t_err;
+
+pch_status set_err(pch_status s, const std::string& m) {
+  t_err = m;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_err(e_ == hipErrorOutOfMemory ? PCH_ENOMEM : PCH_EDEVICE,              \
+                     std::string(#expr) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kHistBins = 4096;
+constexpr u64 kAllOnes = ~0ull;
+constexpr int64_t kMaxRounds = 1 << 24;
+
+// constants of the window arithmetic (same values as the method description)
+constexpr double kTau = 1e-12;             // endpoint / occupancy tolerance, relative to L
+constexpr double kEv = 1.0 - 1e-12;        // event raised when d < g * kEv
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHalfPi = 0.5 * 3.14159265358979323846;
+constexpr double kQuarterPi = 0.25 * 3.14159265358979323846;
+
+// per-round counters (also the per-round log record layout, see pch.h)
+enum {
+  C_N = 0, C_CUT, C_SHIFT, C_SEL, C_STALE, C_KIDS, C_TINY, C_ICH, C_DEV, C_AEV, C_FANS, C_FANWIN, C_DEFER,
+  C_NEND, C_NUM
+};
+// extra counters (not in the log)
+enum { X_NOTWIN = 0, X_NUM = 4 };
+
+struct Ctl {
+  u64 npool[2];
+  u64 ndev[2];
+  u64 nsel;
+  u64 naev;
+  u64 kmin[2], kmax[2];
+  u64 overflow;
+  u64 nonfinite;
+  u64 round;        // rounds run so far
+  u64 active;       // 1 while the current round has work
+  u64 done;
+  u64 sel_all;      // current round selects every window
+  u64 shift;        // key bits dropped before comparing
+  u64 want;         // selected truncated-key prefix after the histogram passes
+  u64 rank;         // remaining rank inside the current histogram bin
+  u64 use_table;    // current round uses a cutoff value
+  double cutval;
+  u64 cnt[C_NUM];   // current round
+  u64 xcnt[X_NUM];
+  u64 tot[C_NUM];   // totals over all rounds
+  u64 peak;
+  u64 pad[8];
+};
+
+struct Pool {
+  double *b0, *b1, *px, *py, *sg, *key;
+  int32_t *e, *src;
+};
+
+struct DistEv {
+  int32_t* v;
+  double *d, *th;
+};
+
+struct AngEv {
+  int32_t* e;
+  double *D, *X;
+};
+
+struct DevMesh {
+  const pch::HalfEdge* he;
+  const double* phi;
+  const double* alpha;
+  const int32_t* twin;
+  const int32_t* hv;
+  const double* theta;
+  const uint8_t* flags;
+  const int32_t* coff;
+  const int32_t* corner;
+};
+
+struct DevState {
+  u64* g;      // geod_dist as bit patterns (non-negative doubles order as u64)
+  u64* AD;     // angle_split distance to the apex (bit pattern)
+  u64* AX;     // angle_split apex crossing (order-preserving key)
+  u64* fanth;  // smallest incoming angle key among this round's winning events
+  u32* claim;  // round stamp of the last fan expanded at a vertex
+};
+
+struct RoundArgs {
+  DevMesh m;
+  DevState s;
+  Pool pool[2];
+  Pool sel;
+  DistEv ev[2];
+  AngEv aev;
+  Ctl* ctl;
+  u32* hist;
+  int64_t* log;    // [max_log][C_NUM] or null
+  int64_t max_log;
+  int64_t cap;     // windows per pool buffer
+  int64_t ecap;    // distance events per buffer
+  int64_t acap;    // angle events
+  int64_t k;
+  double eps;
+  int32_t ch_on, ich_on, full_fan;
+  const double* table;  // device cutoff table or null
+  int64_t n_table;
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ u64 bits(double x) { return (u64)__double_as_longlong(x); }
+__device__ __forceinline__ double from_bits(u64 u) { return __longlong_as_double((long long)u); }
+__device__ __forceinline__ u64 ordkey(double x) {
+  const u64 u = bits(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordkey(u64 k) {
+  return (k >> 63) ? from_bits(k & 0x7fffffffffffffffull) : from_bits(~k);
+}
+__device__ __forceinline__ int he_next(int j) { return j - j % 3 + (j % 3 + 1) % 3; }
+__device__ __forceinline__ int he_prev(int j) { return j - j % 3 + (j % 3 + 2) % 3; }
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 shfl64(u64 x, int src) {
+  u32 lo = __shfl((u32)x, src, kWave);
+  u32 hi = __shfl((u32)(x >> 32), src, kWave);
+  return ((u64)hi << 32) | lo;
+}
+
+// Exclusive prefix sum of n over the wavefront and one atomicAdd by the last
+// lane: returns this lane's first slot in the buffer counted by ctr. Every lane
+// of the wavefront must call it.
+__device__ __forceinline__ u64 wave_reserve(u64* ctr, u32 n, u32* total_out = nullptr) {
+  const int lane = lane_id();
+  u32 incl = n;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    u32 y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const u32 total = __shfl(incl, kWave - 1, kWave);
+  u64 base = 0;
+  if (lane == kWave - 1 && total) base = atomicAdd(ctr, (u64)total);
+  base = shfl64(base, kWave - 1);
+  if (total_out) *total_out = total;
+  return base + (incl - n);
+}
+
+__device__ __forceinline__ u32 wave_sum(u32 x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_min64(u64 x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    u64 y = shfl64(x, lane_id() ^ o);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ u64 wave_max64(u64 x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    u64 y = shfl64(x, lane_id() ^ o);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// atan on [0, 1]: two half-angle reductions atan(t) = 2 atan(t / (1 + sqrt(1 + t^2)))
+// bring the argument below tan(pi/16); then 13 terms of the Maclaurin series
+// (Horner in u^2). Uses only + - * / sqrt, so it rounds the same everywhere.
+__device__ double dev_atan01(double t) {
+  double u = t / (1.0 + sqrt(1.0 + t * t));
+  u = u / (1.0 + sqrt(1.0 + u * u));
+  const double u2 = u * u;
+  double p = 0.0;
+  for (int i = 12; i >= 0; --i) {
+    double c = 1.0 / (double)(2 * i + 1);
+    if (i & 1) c = -c;
+    p = p * u2 + c;
+  }
+  return 4.0 * (u * p);
+}
+
+__device__ double dev_atan2(double y, double x) {
+  const double ax = fabs(x), ay = fabs(y);
+  if (ax == 0.0 && ay == 0.0) return 0.0;
+  double r = ay > ax ? kHalfPi - dev_atan01(ax / ay) : dev_atan01(ay / ax);
+  if (x < 0.0) r = kPi - r;
+  if (y < 0.0) r = -r;
+  return r;
+}
+
+// sin/cos on [0, pi/4] from 11 nested Maclaurin factors; [0, pi] folded by
+// symmetry.
+__device__ void dev_sincos_small(double u, double* s, double* c) {
+  const double u2 = u * u;
+  double ps = 1.0, pc = 1.0;
+  for (int n = 11; n >= 1; --n) {
+    const double ds = (double)(2 * n) * (double)(2 * n + 1);
+    const double dc = (double)(2 * n - 1) * (double)(2 * n);
+    ps = 1.0 - (u2 / ds) * ps;
+    pc = 1.0 - (u2 / dc) * pc;
+  }
+  *s = u * ps;
+  *c = pc;
+}
+
+__device__ void dev_sincos(double t, double* s, double* c) {
+  double sc = 1.0;
+  if (t > kHalfPi) {
+    t = kPi - t;
+    sc = -1.0;
+  }
+  double ss, cc;
+  if (t > kQuarterPi)
+    dev_sincos_small(kHalfPi - t, &cc, &ss);
+  else
+    dev_sincos_small(t, &ss, &cc);
+  *s = ss;
+  *c = sc * cc;
+}
+
+// Selection key: distance from the source to the nearest point of the window
+// (the pseudo-source's distance plus its distance to the interval).
+__device__ __forceinline__ double window_key(double b0, double b1, double px, double py, double sg) {
+  double dseg;
+  if (px < b0) {
+    const double dx = b0 - px;
+    dseg = sqrt(dx * dx + py * py);
+  } else if (px > b1) {
+    const double dx = px - b1;
+    dseg = sqrt(dx * dx + py * py);
+  } else {
+    dseg = -py;
+  }
+  return sg + dseg;
+}
+
+// Tiny-window trim and the Xin-Wang filter of Figure 4(b). u0/u1 are the
+// start/end vertices of the child's edge; the third test (vertex r of the
+// face just crossed) is made at the endpoint next to the shared vertex.
+// Returns 0 keep, 1 tiny, 2 filtered.
+__device__ __forceinline__ int child_filter(double c0, double c1, double cpx, double cpy, double sg, double lc,
+                                            double gu0, double gu1, bool rtest, bool r_at_c0, double gr,
+                                            double rdist, double eps, bool ich_on) {
+  if (!(c1 - c0 > eps * lc)) return 1;
+  if (!ich_on) return 0;
+  const double dx1 = c1 - cpx;
+  const double f1 = sg + sqrt(dx1 * dx1 + cpy * cpy);
+  if (f1 > gu0 + c1) return 2;
+  const double dx0 = c0 - cpx;
+  const double f0 = sg + sqrt(dx0 * dx0 + cpy * cpy);
+  if (f0 > gu1 + (lc - c0)) return 2;
+  if (rtest) {
+    const double lhs = r_at_c0 ? f0 : f1;
+    if (lhs > gr + rdist) return 2;
+  }
+  return 0;
+}
+
+__device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, double b1, double px, double py,
+                                             double sg, double key, int32_t e, int32_t src) {
+  P.b0[i] = b0;
+  P.b1[i] = b1;
+  P.px[i] = px;
+  P.py[i] = py;
+  P.sg[i] = sg;
+  P.key[i] = key;
+  P.e[i] = e;
+  P.src[i] = src;
+}
+
+__device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1ull); }
+
+// Fan of windows from pseudo-source vertex v reached at distance d with the
+// incoming ray's back direction at angular position th (Figure 3(c)): every
+// corner meeting the sector of directions at least pi away from th on both
+// sides gets a window on the far side of its opposite edge, clipped to the
+// sector; endpoints inside the sector get deferred distance events.
+// Windows go to P (counter pc), events to E (counter ec).
+__device__ void expand_fan(const RoundArgs& a, int v, double d, double th, bool full, int qi, int ei, u32* kept,
+                           u32* tiny, u32* ich, u32* defer, u32* notwin) {
+  const DevMesh& m = a.m;
+  const Pool& P = a.pool[qi];
+  u64* pc = &a.ctl->npool[qi];
+  const DistEv& E = a.ev[ei];
+  u64* ec = &a.ctl->ndev[ei];
+  const u64* g = a.s.g;
+  const double Th = m.theta[v];
+  const bool bd = m.flags[v] & pch::VF_BOUNDARY;
+  const int q1 = m.coff[v + 1];
+  for (int q = m.coff[v]; q < q1; ++q) {
+    const int j = m.corner[q];
+    const double al = m.alpha[j];
+    double t0, t1;
+    if (full) {
+      t0 = 0.0;
+      t1 = al;
+    } else if (!bd) {
+      double rel = m.phi[j] - th;
+      if (!isfinite(rel)) continue;
+      while (rel < 0.0) rel += Th;
+      while (rel >= Th) rel -= Th;
+      const double lo = kPi - rel;
+      const double hi = (Th - kPi) - rel;
+      t0 = lo > 0.0 ? lo : 0.0;
+      t1 = hi < al ? hi : al;
+      if (!(t0 <= t1)) continue;
+    } else {
+      const double rel = m.phi[j] - th;
+      const double hiA = -kPi - rel;
+      const double loB = kPi - rel;
+      if (hiA >= 0.0) {
+        t0 = 0.0;
+        t1 = hiA < al ? hiA : al;
+      } else if (loB <= al) {
+        t0 = loB > 0.0 ? loB : 0.0;
+        t1 = al;
+      } else {
+        continue;
+      }
+    }
+    const int n = he_next(j), pj = he_prev(j);
+    const pch::HalfEdge hj = m.he[j];
+    const pch::HalfEdge hn = m.he[n];
+    const int va = hn.v0;  // end of j
+    const int vb = hn.v1;  // start of prev(j)
+    if (t0 <= 0.0) {
+      const double da = d + hj.L;
+      if (da < from_bits(g[va]) * kEv) {
+        const u64 i = atomicAdd(ec, 1ull);
+        if (i < (u64)a.ecap) {
+          E.v[i] = va;
+          E.d[i] = da;
+          E.th[i] = m.phi[n] + m.alpha[n];
+        } else {
+          flag_overflow(a.ctl);
+        }
+        (*defer)++;
+      }
+    }
+    if (t1 >= al && m.twin[pj] < 0) {
+      const double db = d + hj.l02;
+      if (db < from_bits(g[vb]) * kEv) {
+        const u64 i = atomicAdd(ec, 1ull);
+        if (i < (u64)a.ecap) {
+          E.v[i] = vb;
+          E.d[i] = db;
+          E.th[i] = m.phi[pj];
+        } else {
+          flag_overflow(a.ctl);
+        }
+        (*defer)++;
+      }
+    }
+    const int tw = m.twin[n];
+    if (tw < 0) {
+      (*notwin)++;
+      continue;
+    }
+    const double Ln = hn.L, x2n = hn.x2, y2n = hn.y2;
+    const double ipx = Ln - x2n, ipy = -y2n;
+    double c0, c1;
+    if (t1 >= al) {
+      c0 = 0.0;
+    } else {
+      double s, c;
+      dev_sincos(t1, &s, &c);
+      const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+      c0 = ipx - ipy * (dx / dy);
+    }
+    if (t0 <= 0.0) {
+      c1 = Ln;
+    } else {
+      double s, c;
+      dev_sincos(t0, &s, &c);
+      const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+      c1 = ipx - ipy * (dx / dy);
+    }
+    if (c0 < 0.0) c0 = 0.0;
+    if (c1 > Ln) c1 = Ln;
+    const int r = child_filter(c0, c1, ipx, ipy, d, Ln, from_bits(g[vb]), from_bits(g[va]), false, false, 0.0, 0.0,
+                               a.eps, a.ich_on);
+    if (r == 1) {
+      (*tiny)++;
+      continue;
+    }
+    if (r == 2) {
+      (*ich)++;
+      continue;
+    }
+    const double key = window_key(c0, c1, ipx, ipy, d);
+    const u64 i = atomicAdd(pc, 1ull);
+    if (i < (u64)a.cap) {
+      store_window(P, i, c0, c1, ipx, ipy, d, key, tw, v);
+      atomicMin(&a.ctl->kmin[qi], bits(key));
+      atomicMax(&a.ctl->kmax[qi], bits(key));
+    } else {
+      flag_overflow(a.ctl);
+    }
+    (*kept)++;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u64(u64* p, int64_t n, u64 v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u32(u32* p, int64_t n, u32 v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_set_sources(u64* g, const int32_t* src, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) g[src[i]] = 0ull;
+}
+
+// Initialization (Algorithm 1, lines 1-2): every source gets a full fan into
+// pool 0 and deferred events for its one-ring into event buffer 0.
+__global__ void k_init_fans(RoundArgs a, const int32_t* src, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
+  expand_fan(a, src[i], 0.0, 0.0, true, 0, 0, &kept, &tiny, &ich, &defer, &notwin);
+}
+
+// Round set-up (single thread): log the previous round, stop when nothing is
+// left, otherwise reset the output buffers of this round and prepare the
+// cutoff search.
+__global__ void k_begin(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (c->done) return;
+  if (c->active) {
+    const u64 r = c->round - 1;
+    c->cnt[C_NEND] = c->npool[p];
+    c->cnt[C_DEFER] = c->ndev[p];
+    if (a.log && (int64_t)r < a.max_log)
+      for (int f = 0; f < C_NUM; ++f) a.log[r * C_NUM + f] = (int64_t)c->cnt[f];
+    for (int f = 0; f < C_NUM; ++f) c->tot[f] += c->cnt[f];
+    c->active = 0;
+  }
+  if (c->overflow) {
+    c->done = 1;
+    return;
+  }
+  const u64 N = c->npool[p];
+  const u64 nd = c->ndev[p];
+  if (N == 0 && nd == 0) {
+    c->done = 1;
+    return;
+  }
+  c->active = 1;
+  c->round += 1;
+  if (N > c->peak) c->peak = N;
+  for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
+  c->cnt[C_N] = N;
+  c->npool[1 - p] = 0;
+  c->ndev[1 - p] = 0;
+  c->nsel = 0;
+  c->naev = 0;
+  c->kmin[1 - p] = kAllOnes;
+  c->kmax[1 - p] = 0;
+  c->use_table = 0;
+  c->sel_all = 0;
+  const u64 r = c->round - 1;
+  if (a.table && (int64_t)r < a.n_table) {
+    c->use_table = 1;
+    c->cutval = a.table[r];
+    c->cnt[C_CUT] = bits(c->cutval);
+    c->cnt[C_SHIFT] = (u64)(int64_t)-2;
+    c->rank = 0;
+    return;
+  }
+  if (N <= (u64)a.k) {
+    c->sel_all = 1;
+    c->cnt[C_CUT] = (u64)(int64_t)-1;
+    c->cnt[C_SHIFT] = 0;
+    c->rank = 0;
+    return;
+  }
+  const u64 mn = c->kmin[p], mx = c->kmax[p];
+  const u64 dif = mn ^ mx;
+  if (dif == 0) {
+    c->shift = 0;
+    c->want = mx;
+    c->rank = 0;  // no histogram pass needed
+    return;
+  }
+  const int hb = 63 - __clzll((long long)dif);
+  int s = hb + 1 - 36;
+  if (s < 0) s = 0;
+  c->shift = (u64)s;
+  c->want = (mn >> s) >> 36;  // common prefix above the 36 bits searched
+  c->rank = (u64)a.k;
+}
+
+// One 12-bit radix-select pass over the truncated keys t = key_bits >> shift.
+// pass 0 bins bits 35..24, pass 1 bits 23..12, pass 2 bits 11..0, counting
+// only keys whose higher bits equal the prefix chosen so far.
+__global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
+  __shared__ u32 h[kHistBins];
+  Ctl* c = a.ctl;
+  if (!c->active || c->use_table || c->sel_all || c->rank == 0) return;
+  for (int i = threadIdx.x; i < kHistBins; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const u64 N = min(c->npool[p], (u64)a.cap);
+  const int s = (int)c->shift;
+  const int lo = 24 - 12 * pass;
+  const u64 want = c->want;
+  const double* key = a.pool[p].key;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+    const u64 t = bits(key[i]) >> s;
+    if ((t >> (lo + 12)) == want) atomicAdd(&h[(t >> lo) & (kHistBins - 1)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistBins; i += kBlock)
+    if (h[i]) atomicAdd(&a.hist[i], h[i]);
+}
+
+// Finds the bin holding the remaining rank, extends the prefix, clears the
+// histogram. One block.
+__global__ void __launch_bounds__(kBlock) k_hist_scan(RoundArgs a) {
+  __shared__ u32 part[kBlock];
+  __shared__ u32 pick_bin, pick_before;
+  Ctl* c = a.ctl;
+  if (!c->active || c->use_table || c->sel_all || c->rank == 0) return;
+  if (threadIdx.x == 0) {
+    pick_bin = 0;
+    pick_before = 0;
+  }
+  constexpr int per = kHistBins / kBlock;  // 16 bins per thread
+  u32 loc[per];
+  u32 sum = 0;
+  for (int i = 0; i < per; ++i) {
+    loc[i] = a.hist[threadIdx.x * per + i];
+    sum += loc[i];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  // inclusive scan of part[] (Hillis-Steele in LDS)
+  for (int o = 1; o < kBlock; o <<= 1) {
+    u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  const u64 rank = c->rank;
+  const u32 incl = part[threadIdx.x];
+  const u32 excl = incl - sum;
+  if (excl < rank && rank <= incl) {
+    u32 run = excl;
+    for (int i = 0; i < per; ++i) {
+      if (run + loc[i] >= rank) {
+        pick_bin = threadIdx.x * per + i;
+        pick_before = run;
+        break;
+      }
+      run += loc[i];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistBins; i += kBlock) a.hist[i] = 0;
+  if (threadIdx.x == 0) {
+    c->want = (c->want << 12) | pick_bin;
+    c->rank = rank - pick_before;
+  }
+}
+
+// Split the pool: stale windows (sigma > geod_dist of their pseudo-source) are
+// dropped, selected windows go to the selection buffer, the rest to the other
+// pool buffer. Appends are reserved per wavefront.
+__global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 N = min(c->npool[p], (u64)a.cap);
+  const Pool P = a.pool[p];
+  const Pool Q = a.pool[1 - p];
+  const Pool S = a.sel;
+  const int s = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
+  u32 stale_n = 0;
+  u64 kmn = kAllOnes, kmx = 0;
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < N; i += stride) {
+    const bool valid = i < N;
+    bool sel = false, keep = false;
+    double b0 = 0, b1 = 0, px = 0, py = 0, sg = 0, key = 0;
+    int32_t e = 0, src = 0;
+    if (valid) {
+      sg = P.sg[i];
+      src = P.src[i];
+      key = P.key[i];
+      const bool stale = sg > from_bits(a.s.g[src]);
+      if (stale) {
+        stale_n++;
+      } else {
+        sel = tab ? (key <= cv) : (all || ((bits(key) >> s) <= T));
+        keep = !sel;
+        b0 = P.b0[i];
+        b1 = P.b1[i];
+        px = P.px[i];
+        py = P.py[i];
+        e = P.e[i];
+      }
+    }
+    const u64 js = wave_reserve(&c->nsel, sel ? 1u : 0u);
+    const u64 jk = wave_reserve(&c->npool[1 - p], keep ? 1u : 0u);
+    if (sel) {
+      if (js < (u64)a.cap)
+        store_window(S, js, b0, b1, px, py, sg, key, e, src);
+      else
+        flag_overflow(c);
+    }
+    if (keep) {
+      if (jk < (u64)a.cap) {
+        store_window(Q, jk, b0, b1, px, py, sg, key, e, src);
+        const u64 kb = bits(key);
+        kmn = kb < kmn ? kb : kmn;
+        kmx = kb > kmx ? kb : kmx;
+      } else {
+        flag_overflow(c);
+      }
+    }
+  }
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
+  stale_n = wave_sum(stale_n);
+  if (lane_id() == 0) {
+    if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
+    if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
+    if (stale_n) atomicAdd(&c->cnt[C_STALE], (u64)stale_n);
+  }
+}
+
+// Algorithm 2 for every selected window, against the round-start geod_dist
+// and angle_split (delayed update, Remark 3).
+__global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 N = min(c->nsel, (u64)a.cap);
+  const Pool S = a.sel;
+  const Pool Q = a.pool[1 - p];
+  const DistEv E = a.ev[p];
+  const DevMesh& m = a.m;
+  const u64* g = a.s.g;
+  u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
+  u64 kmn = kAllOnes, kmx = 0;
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < N; i += stride) {
+    // outputs of this lane
+    int nk = 0;
+    double kb0[2], kb1[2], kpx[2], kpy[2], kkey[2];
+    int32_t ke[2];
+    int nd = 0;
+    int32_t dv[3];
+    double dd[3], dth[3];
+    bool has_aev = false;
+    double aD = 0, aX = 0;
+    double sg = 0;
+    int32_t src = 0, e = 0;
+    if (i < N) {
+      const double b0 = S.b0[i], b1 = S.b1[i], px = S.px[i], py = S.py[i];
+      sg = S.sg[i];
+      e = S.e[i];
+      src = S.src[i];
+      const pch::HalfEdge h = m.he[e];
+      const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
+      const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
+      const double g0 = from_bits(g[v0]), g1 = from_bits(g[v1]), g2 = from_bits(g[v2]);
+      const double tol = kTau * L;
+      const double den = y2 - py;
+      const double t = (-py) / den;
+      const double X = px + (x2 - px) * t;
+      if (!isfinite(X)) n_nonfin++;
+      const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
+      const int en = he_next(e), ep = he_prev(e);
+      if (b0 <= tol) {
+        const double d = sg + sqrt(px * px + py * py);
+        if (d < g0 * kEv) {
+          dv[nd] = v0;
+          dd[nd] = d;
+          dth[nd] = (m.flags[v0] & pch::VF_PSEUDO) ? m.phi[e] - dev_atan2(-py, px) : 0.0;
+          nd++;
+        }
+      }
+      if (b1 >= L - tol) {
+        const double dx = px - L;
+        const double d = sg + sqrt(dx * dx + py * py);
+        if (d < g1 * kEv) {
+          dv[nd] = v1;
+          dd[nd] = d;
+          dth[nd] = (m.flags[v1] & pch::VF_PSEUDO) ? (m.phi[en] + m.alpha[en]) + dev_atan2(-py, L - px) : 0.0;
+          nd++;
+        }
+      }
+      bool doL = false, doR = false;
+      if (occ) {
+        const double dx = x2 - px, dy = y2 - py;
+        const double d2 = sg + sqrt(dx * dx + dy * dy);
+        if (d2 < g2 * kEv) {
+          double th = 0.0;
+          if (m.flags[v2] & pch::VF_PSEUDO) {
+            const double ux = -x2, uy = -y2, wx = px - x2, wy = py - y2;
+            const double cr = ux * wy - uy * wx;
+            const double dt = ux * wx + uy * wy;
+            th = m.phi[ep] + dev_atan2(cr, dt);
+          }
+          dv[nd] = v2;
+          dd[nd] = d2;
+          dth[nd] = th;
+          nd++;
+        }
+        if (!a.ch_on) {
+          doL = doR = true;
+        } else {
+          const double Ds = from_bits(a.s.AD[e]);
+          const double Xs = from_ordkey(a.s.AX[e]);
+          if (d2 < Ds) {
+            has_aev = true;
+            aD = d2;
+            aX = X;
+            doL = doR = true;
+          } else if (X < Xs - tol) {
+            doL = true;
+          } else if (X > Xs + tol) {
+            doR = true;
+          } else {
+            doL = doR = true;
+          }
+        }
+      } else if (X > b1) {
+        doL = true;
+      } else {
+        doR = true;
+      }
+      if (doL) {
+        if (h.tl < 0) {
+          n_notwin++;
+        } else {
+          double s0, s1;
+          if (b0 == 0.0) {
+            s0 = 0.0;
+          } else {
+            const double dn0 = x2 * py + y2 * (b0 - px);
+            s0 = (py * b0) / dn0;
+          }
+          if (occ) {
+            s1 = 1.0;
+          } else {
+            const double dn1 = x2 * py + y2 * (b1 - px);
+            s1 = (py * b1) / dn1;
+          }
+          double c0 = s0 * l02, c1 = s1 * l02;
+          if (c0 < 0.0) c0 = 0.0;
+          if (c1 > l02) c1 = l02;
+          const double ux = x2 / l02, uy = y2 / l02;
+          const double cpx = ux * px + uy * py;
+          double cpy = ux * py - uy * px;
+          if (cpy > 0.0) cpy = 0.0;
+          const double rx = ux * c0 - L, ry = uy * c0;
+          const double rdist = sqrt(rx * rx + ry * ry);
+          const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
+          if (r == 1) {
+            n_tiny++;
+          } else if (r == 2) {
+            n_ich++;
+          } else {
+            kb0[nk] = c0;
+            kb1[nk] = c1;
+            kpx[nk] = cpx;
+            kpy[nk] = cpy;
+            kkey[nk] = window_key(c0, c1, cpx, cpy, sg);
+            ke[nk] = h.tl;
+            nk++;
+          }
+        }
+      }
+      if (doR) {
+        if (h.tr < 0) {
+          n_notwin++;
+        } else {
+          const double ex = L - x2;
+          double r0, r1;
+          if (occ) {
+            r0 = 0.0;
+          } else {
+            const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
+            const double dn0 = y2 * (b0 - px) - ex * py;
+            r0 = nm0 / dn0;
+          }
+          if (b1 == L) {
+            r1 = 1.0;
+          } else {
+            const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
+            const double dn1 = y2 * (b1 - px) - ex * py;
+            r1 = nm1 / dn1;
+          }
+          double c0 = r0 * l12, c1 = r1 * l12;
+          if (c0 < 0.0) c0 = 0.0;
+          if (c1 > l12) c1 = l12;
+          const double ux = ex / l12, uy = (-y2) / l12;
+          const double qx = px - x2, qy = py - y2;
+          const double cpx = ux * qx + uy * qy;
+          double cpy = ux * qy - uy * qx;
+          if (cpy > 0.0) cpy = 0.0;
+          const double rx = x2 + ux * c1, ry = y2 + uy * c1;
+          const double rdist = sqrt(rx * rx + ry * ry);
+          const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
+          if (r == 1) {
+            n_tiny++;
+          } else if (r == 2) {
+            n_ich++;
+          } else {
+            kb0[nk] = c0;
+            kb1[nk] = c1;
+            kpx[nk] = cpx;
+            kpy[nk] = cpy;
+            kkey[nk] = window_key(c0, c1, cpx, cpy, sg);
+            ke[nk] = h.tr;
+            nk++;
+          }
+        }
+      }
+    }
+    // append children, distance events and angle events (one reservation per
+    // wavefront each)
+    u32 tk, td, ta;
+    const u64 jk = wave_reserve(&c->npool[1 - p], (u32)nk, &tk);
+    const u64 jd = wave_reserve(&c->ndev[p], (u32)nd, &td);
+    const u64 ja = wave_reserve(&c->naev, has_aev ? 1u : 0u, &ta);
+    for (int q = 0; q < nk; ++q) {
+      const u64 j = jk + q;
+      if (j < (u64)a.cap) {
+        store_window(Q, j, kb0[q], kb1[q], kpx[q], kpy[q], sg, kkey[q], ke[q], src);
+        const u64 kb = bits(kkey[q]);
+        kmn = kb < kmn ? kb : kmn;
+        kmx = kb > kmx ? kb : kmx;
+      } else {
+        flag_overflow(c);
+      }
+    }
+    for (int q = 0; q < nd; ++q) {
+      const u64 j = jd + q;
+      if (j < (u64)a.ecap) {
+        E.v[j] = dv[q];
+        E.d[j] = dd[q];
+        E.th[j] = dth[q];
+      } else {
+        flag_overflow(c);
+      }
+    }
+    if (has_aev) {
+      if (ja < (u64)a.acap) {
+        a.aev.e[ja] = e;
+        a.aev.D[ja] = aD;
+        a.aev.X[ja] = aX;
+      } else {
+        flag_overflow(c);
+      }
+    }
+    if (lane_id() == 0) {
+      if (tk) atomicAdd(&c->cnt[C_KIDS], (u64)tk);
+      if (td) atomicAdd(&c->cnt[C_DEV], (u64)td);
+      if (ta) atomicAdd(&c->cnt[C_AEV], (u64)ta);
+    }
+  }
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
+  n_tiny = wave_sum(n_tiny);
+  n_ich = wave_sum(n_ich);
+  n_notwin = wave_sum(n_notwin);
+  n_nonfin = wave_sum(n_nonfin);
+  if (lane_id() == 0) {
+    if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
+    if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
+    if (n_tiny) atomicAdd(&c->cnt[C_TINY], (u64)n_tiny);
+    if (n_ich) atomicAdd(&c->cnt[C_ICH], (u64)n_ich);
+    if (n_notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)n_notwin);
+    if (n_nonfin) atomicAdd(&c->nonfinite, (u64)n_nonfin);
+  }
+}
+
+// Algorithm 4, first pass: geod_dist and the angle_split distance take the
+// minimum over this round's events (keys: vertex, oriented edge).
+__global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 nd = min(c->ndev[p], (u64)a.ecap);
+  const u64 na = min(c->naev, (u64)a.acap);
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride)
+    atomicMin(&a.s.g[a.ev[p].v[i]], bits(a.ev[p].d[i]));
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride)
+    atomicMin(&a.s.AD[a.aev.e[i]], bits(a.aev.D[i]));
+}
+
+// Second pass: corners whose distance changed forget their old crossing; each
+// improved pseudo-source vertex records the smallest incoming angle among the
+// events that reached its new distance.
+__global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 nd = min(c->ndev[p], (u64)a.ecap);
+  const u64 na = min(c->naev, (u64)a.acap);
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride) {
+    const int e = a.aev.e[i];
+    if (bits(a.aev.D[i]) == a.s.AD[e]) a.s.AX[e] = kAllOnes;
+  }
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride) {
+    const int v = a.ev[p].v[i];
+    if (bits(a.ev[p].d[i]) == a.s.g[v] && (a.m.flags[v] & pch::VF_PSEUDO))
+      atomicMin(&a.s.fanth[v], ordkey(a.ev[p].th[i]));
+  }
+}
+
+// Third pass: the winning crossing per corner; one fan per improved
+// pseudo-source vertex, windows into the next pool, deferred endpoint events
+// into the next round's event buffer.
+__global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 nd = min(c->ndev[p], (u64)a.ecap);
+  const u64 na = min(c->naev, (u64)a.acap);
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride) {
+    const int e = a.aev.e[i];
+    if (bits(a.aev.D[i]) == a.s.AD[e]) atomicMin(&a.s.AX[e], ordkey(a.aev.X[i]));
+  }
+  const u32 stamp = (u32)c->round;
+  u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride) {
+    const int v = a.ev[p].v[i];
+    const double d = a.ev[p].d[i];
+    if (bits(d) != a.s.g[v] || !(a.m.flags[v] & pch::VF_PSEUDO)) continue;
+    const u64 tk = ordkey(a.ev[p].th[i]);
+    if (tk != a.s.fanth[v]) continue;
+    if (atomicMax(&a.s.claim[v], stamp) >= stamp) continue;
+    a.s.fanth[v] = kAllOnes;
+    fans++;
+    expand_fan(a, v, d, a.ev[p].th[i], a.full_fan != 0, 1 - p, 1 - p, &kept, &tiny, &ich, &defer, &notwin);
+  }
+  kept = wave_sum(kept);
+  tiny = wave_sum(tiny);
+  ich = wave_sum(ich);
+  fans = wave_sum(fans);
+  notwin = wave_sum(notwin);
+  if (lane_id() == 0) {
+    if (kept) atomicAdd(&c->cnt[C_FANWIN], (u64)kept);
+    if (tiny) atomicAdd(&c->cnt[C_TINY], (u64)tiny);
+    if (ich) atomicAdd(&c->cnt[C_ICH], (u64)ich);
+    if (fans) atomicAdd(&c->cnt[C_FANS], (u64)fans);
+    if (notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)notwin);
+  }
+}
+
+// Records the round's selection count and cutoff in its log counters.
+__global__ void k_note_sel(RoundArgs a) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  c->cnt[C_SEL] = c->nsel;
+  if (!c->sel_all && !c->use_table) {
+    c->cnt[C_CUT] = c->want;
+    c->cnt[C_SHIFT] = c->shift;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct pch_mesh_s {
+  pch::HostMesh host;
+  int device = 0;
+  // device copies
+  pch::HalfEdge* he = nullptr;
+  double *phi = nullptr, *alpha = nullptr, *theta = nullptr;
+  int32_t *twin = nullptr, *hv = nullptr, *coff = nullptr, *corner = nullptr;
+  uint8_t* flags = nullptr;
+  // state (sized with the mesh)
+  u64 *g = nullptr, *AD = nullptr, *AX = nullptr, *fanth = nullptr;
+  u32* claim = nullptr;
+  // work buffers (grow on demand)
+  int64_t cap = 0, ecap = 0, acap = 0;
+  Pool pool[2] = {};
+  Pool sel = {};
+  DistEv ev[2] = {};
+  AngEv aev = {};
+  Ctl* ctl = nullptr;
+  u32* hist = nullptr;
+  int32_t* dsrc = nullptr;
+  int64_t dsrc_cap = 0;
+  double* dtable = nullptr;
+  int64_t dtable_cap = 0;
+  int64_t* dlog = nullptr;
+  int64_t dlog_cap = 0;
+  std::vector<int64_t> last_log;
+  int64_t last_rounds = 0;
+};
+
+namespace {
+
+u64 bits_host(double x) {
+  u64 u;
+  std::memcpy(&u, &x, sizeof(u));
+  return u;
+}
+
+template <class T>
+hipError_t dalloc(T** p, int64_t n) {
+  return hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+
+void free_pool(Pool& P) {
+  (void)hipFree(P.b0);
+  (void)hipFree(P.b1);
+  (void)hipFree(P.px);
+  (void)hipFree(P.py);
+  (void)hipFree(P.sg);
+  (void)hipFree(P.key);
+  (void)hipFree(P.e);
+  (void)hipFree(P.src);
+  P = Pool{};
+}
+
+hipError_t alloc_pool(Pool& P, int64_t n) {
+  hipError_t e;
+  if ((e = dalloc(&P.b0, n)) || (e = dalloc(&P.b1, n)) || (e = dalloc(&P.px, n)) || (e = dalloc(&P.py, n)) ||
+      (e = dalloc(&P.sg, n)) || (e = dalloc(&P.key, n)) || (e = dalloc(&P.e, n)) || (e = dalloc(&P.src, n)))
+    return e;
+  return hipSuccess;
+}
+
+void free_work(pch_mesh_s* M) {
+  for (int i = 0; i < 2; ++i) {
+    free_pool(M->pool[i]);
+    (void)hipFree(M->ev[i].v);
+    (void)hipFree(M->ev[i].d);
+    (void)hipFree(M->ev[i].th);
+    M->ev[i] = DistEv{};
+  }
+  free_pool(M->sel);
+  (void)hipFree(M->aev.e);
+  (void)hipFree(M->aev.D);
+  (void)hipFree(M->aev.X);
+  M->aev = AngEv{};
+  M->cap = M->ecap = M->acap = 0;
+}
+
+pch_status ensure_work(pch_mesh_s* M, int64_t cap) {
+  if (cap <= M->cap) return PCH_OK;
+  free_work(M);
+  const int64_t ecap = 4 * cap, acap = cap;
+  for (int i = 0; i < 2; ++i) {
+    HIP_TRY(alloc_pool(M->pool[i], cap));
+    HIP_TRY(dalloc(&M->ev[i].v, ecap));
+    HIP_TRY(dalloc(&M->ev[i].d, ecap));
+    HIP_TRY(dalloc(&M->ev[i].th, ecap));
+  }
+  HIP_TRY(alloc_pool(M->sel, cap));
+  HIP_TRY(dalloc(&M->aev.e, acap));
+  HIP_TRY(dalloc(&M->aev.D, acap));
+  HIP_TRY(dalloc(&M->aev.X, acap));
+  M->cap = cap;
+  M->ecap = ecap;
+  M->acap = acap;
+  return PCH_OK;
+}
+
+pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
+  const pch::HostMesh& H = M->host;
+  HIP_TRY(dalloc(&M->he, H.nh));
+  HIP_TRY(dalloc(&M->phi, H.nh));
+  HIP_TRY(dalloc(&M->alpha, H.nh));
+  HIP_TRY(dalloc(&M->twin, H.nh));
+  HIP_TRY(dalloc(&M->hv, H.nh));
+  HIP_TRY(dalloc(&M->corner, H.nh));
+  HIP_TRY(dalloc(&M->theta, H.nv));
+  HIP_TRY(dalloc(&M->flags, H.nv));
+  HIP_TRY(dalloc(&M->coff, H.nv + 1));
+  HIP_TRY(dalloc(&M->g, H.nv));
+  HIP_TRY(dalloc(&M->AD, H.nh));
+  HIP_TRY(dalloc(&M->AX, H.nh));
+  HIP_TRY(dalloc(&M->fanth, H.nv));
+  HIP_TRY(dalloc(&M->claim, H.nv));
+  HIP_TRY(dalloc(&M->ctl, 1));
+  HIP_TRY(dalloc(&M->hist, kHistBins));
+  HIP_TRY(hipMemcpyAsync(M->he, H.he.data(), sizeof(pch::HalfEdge) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->phi, H.phi.data(), sizeof(double) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->alpha, H.alpha.data(), sizeof(double) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->twin, H.twin.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->hv, H.hv.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->corner, H.corner.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->theta, H.theta.data(), sizeof(double) * H.nv, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->flags, H.flags.data(), H.nv, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->coff, H.coff.data(), sizeof(int32_t) * (H.nv + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(M->hist, 0, sizeof(u32) * kHistBins, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PCH_OK;
+}
+
+void free_mesh(pch_mesh_s* M) {
+  free_work(M);
+  (void)hipFree(M->he);
+  (void)hipFree(M->phi);
+  (void)hipFree(M->alpha);
+  (void)hipFree(M->twin);
+  (void)hipFree(M->hv);
+  (void)hipFree(M->corner);
+  (void)hipFree(M->theta);
+  (void)hipFree(M->flags);
+  (void)hipFree(M->coff);
+  (void)hipFree(M->g);
+  (void)hipFree(M->AD);
+  (void)hipFree(M->AX);
+  (void)hipFree(M->fanth);
+  (void)hipFree(M->claim);
+  (void)hipFree(M->ctl);
+  (void)hipFree(M->hist);
+  (void)hipFree(M->dsrc);
+  (void)hipFree(M->dtable);
+  (void)hipFree(M->dlog);
+}
+
+pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipGetDevice(&M->device));
+  pch_status s = upload_mesh(M, st);
+  if (s != PCH_OK) {
+    free_mesh(M);
+    delete M;
+    return s;
+  }
+  *out = M;
+  return PCH_OK;
+}
+
+RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
+  RoundArgs a;
+  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner};
+  a.s = DevState{M->g, M->AD, M->AX, M->fanth, M->claim};
+  a.pool[0] = M->pool[0];
+  a.pool[1] = M->pool[1];
+  a.sel = M->sel;
+  a.ev[0] = M->ev[0];
+  a.ev[1] = M->ev[1];
+  a.aev = M->aev;
+  a.ctl = M->ctl;
+  a.hist = M->hist;
+  a.log = o.collect_stats ? M->dlog : nullptr;
+  a.max_log = o.collect_stats ? M->dlog_cap : 0;
+  a.cap = M->cap;
+  a.ecap = M->ecap;
+  a.acap = M->acap;
+  a.k = o.k;
+  a.eps = o.eps_tiny;
+  a.ch_on = (o.filters & 1) != 0;
+  a.ich_on = (o.filters & 2) != 0;
+  a.full_fan = (o.filters & 4) != 0;
+  a.table = (o.select_mode == PCH_SELECT_TABLE) ? M->dtable : nullptr;
+  a.n_table = (o.select_mode == PCH_SELECT_TABLE) ? o.n_cutoff : 0;
+  return a;
+}
+
+int grid_for(int64_t work, int max_blocks) {
+  int64_t b = (work + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+// Enqueue one round with input parity p.
+void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int gblocks) {
+  k_begin<<<1, 1, 0, st>>>(a, p);
+  for (int pass = 0; pass < 3; ++pass) {
+    k_hist<<<std::min(gblocks, 512), kBlock, 0, st>>>(a, p, pass);
+    k_hist_scan<<<1, kBlock, 0, st>>>(a);
+  }
+  k_partition<<<gblocks, kBlock, 0, st>>>(a, p);
+  k_note_sel<<<1, 1, 0, st>>>(a);
+  k_propagate<<<gblocks, kBlock, 0, st>>>(a, p);
+  k_events1<<<gblocks, kBlock, 0, st>>>(a, p);
+  k_events2<<<gblocks, kBlock, 0, st>>>(a, p);
+  k_events3<<<gblocks, kBlock, 0, st>>>(a, p);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* pch_last_error(void) { return t_err.c_str(); }
+
+const char* pch_status_string(pch_status s) {
+  switch (s) {
+    case PCH_OK: return "ok";
+    case PCH_EINVAL: return "invalid argument";
+    case PCH_EMESH: return "invalid mesh";
+    case PCH_ENOMEM: return "out of memory";
+    case PCH_EDEVICE: return "device error";
+    case PCH_EOVERFLOW: return "window pool limit exceeded";
+    case PCH_ENUMERIC: return "non-finite window geometry";
+  }
+  return "unknown status";
+}
+
+void pch_options_default(pch_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->select_mode = PCH_SELECT_KTH;
+  o->filters = 3;
+  o->k = 16384;
+  o->eps_tiny = 0.0;
+  o->pool_capacity = 0;
+  o->pool_limit = 0;
+  o->collect_stats = 0;
+  o->rounds_per_sync = 16;
+  o->cutoff_table = nullptr;
+  o->n_cutoff = 0;
+}
+
+pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len,
+                                        void* hip_stream, pch_mesh* out) {
+  if (!faces || !he_len || !out) return set_err(PCH_EINVAL, "null pointer argument");
+  *out = nullptr;
+  pch_mesh_s* M = new (std::nothrow) pch_mesh_s();
+  if (!M) return set_err(PCH_ENOMEM, "host allocation failed");
+  std::string msg;
+  int rc = pch::build_host_mesh(faces, nf, nv, he_len, M->host, msg);
+  if (rc != PCH_OK) {
+    delete M;
+    return set_err((pch_status)rc, msg);
+  }
+  return finish_create(M, hip_stream, out);
+}
+
+pch_status pch_mesh_create(const double* xyz, int64_t nv, const int32_t* faces, int64_t nf, void* hip_stream,
+                           pch_mesh* out) {
+  if (!xyz || !faces || !out) return set_err(PCH_EINVAL, "null pointer argument");
+  if (nv < 1 || nf < 1) return set_err(PCH_EINVAL, "mesh needs at least one face and one vertex");
+  std::vector<double> len;
+  std::string msg;
+  int rc = pch::lengths_from_xyz(xyz, nv, faces, nf, len, msg);
+  if (rc != PCH_OK) return set_err((pch_status)rc, msg);
+  return pch_mesh_create_from_lengths(faces, nf, nv, len.data(), hip_stream, out);
+}
+
+void pch_mesh_destroy(pch_mesh M) {
+  if (!M) return;
+  free_mesh(M);
+  delete M;
+}
+
+pch_status pch_mesh_info(pch_mesh M, int64_t* nv, int64_t* nf, int64_t* nbhe, int64_t* npseudo) {
+  if (!M) return set_err(PCH_EINVAL, "null mesh");
+  if (nv) *nv = M->host.nv;
+  if (nf) *nf = M->host.nf;
+  if (nbhe) *nbhe = M->host.n_boundary_he;
+  if (npseudo) *npseudo = M->host.n_pseudo;
+  return PCH_OK;
+}
+
+pch_status pch_mesh_vertex_tables(pch_mesh M, double* theta, uint8_t* flags) {
+  if (!M) return set_err(PCH_EINVAL, "null mesh");
+  if (theta) std::memcpy(theta, M->host.theta.data(), sizeof(double) * M->host.nv);
+  if (flags) std::memcpy(flags, M->host.flags.data(), M->host.nv);
+  return PCH_OK;
+}
+
+pch_status pch_round_log(pch_mesh M, int64_t* out, int64_t max_rounds, int64_t* n_rounds) {
+  if (!M) return set_err(PCH_EINVAL, "null mesh");
+  if (n_rounds) *n_rounds = M->last_rounds;
+  if (out && max_rounds > 0) {
+    const int64_t n = std::min<int64_t>(max_rounds, (int64_t)M->last_log.size() / C_NUM);
+    std::memcpy(out, M->last_log.data(), sizeof(int64_t) * C_NUM * n);
+  }
+  return PCH_OK;
+}
+
+pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
+                        const pch_options* opts, pch_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!M || !sources || !dist) return set_err(PCH_EINVAL, "null pointer argument");
+  if (m < 1) return set_err(PCH_EINVAL, "need at least one source vertex");
+  pch_options o;
+  pch_options_default(&o);
+  if (opts) o = *opts;
+  if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_TABLE)
+    return set_err(PCH_EINVAL, "unknown select_mode");
+  if (o.k < 1) return set_err(PCH_EINVAL, "k must be >= 1");
+  if (o.select_mode == PCH_SELECT_TABLE && (o.n_cutoff < 0 || (o.n_cutoff > 0 && !o.cutoff_table)))
+    return set_err(PCH_EINVAL, "cutoff table missing");
+  if (!(o.eps_tiny >= 0.0)) return set_err(PCH_EINVAL, "eps_tiny must be >= 0");
+  if (o.rounds_per_sync < 1) o.rounds_per_sync = 16;
+  const pch::HostMesh& H = M->host;
+  std::vector<int32_t> src(sources, sources + m);
+  for (int32_t s : src)
+    if (s < 0 || s >= H.nv) return set_err(PCH_EINVAL, "source vertex out of range");
+  std::sort(src.begin(), src.end());
+  src.erase(std::unique(src.begin(), src.end()), src.end());
+  hipStream_t st = (hipStream_t)hip_stream;
+  int cur_dev = 0;
+  HIP_TRY(hipGetDevice(&cur_dev));
+  if (cur_dev != M->device) return set_err(PCH_EINVAL, "mesh was created on another device");
+
+  if ((int64_t)src.size() > M->dsrc_cap) {
+    (void)hipFree(M->dsrc);
+    M->dsrc = nullptr;
+    HIP_TRY(dalloc(&M->dsrc, (int64_t)src.size()));
+    M->dsrc_cap = (int64_t)src.size();
+  }
+  HIP_TRY(hipMemcpyAsync(M->dsrc, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice, st));
+  if (o.select_mode == PCH_SELECT_TABLE && o.n_cutoff > 0) {
+    if (o.n_cutoff > M->dtable_cap) {
+      (void)hipFree(M->dtable);
+      M->dtable = nullptr;
+      HIP_TRY(dalloc(&M->dtable, o.n_cutoff));
+      M->dtable_cap = o.n_cutoff;
+    }
+    HIP_TRY(hipMemcpyAsync(M->dtable, o.cutoff_table, sizeof(double) * o.n_cutoff, hipMemcpyHostToDevice, st));
+  }
+  int64_t cap = o.pool_capacity > 0 ? o.pool_capacity : std::max<int64_t>(1 << 18, 2 * H.nh);
+  if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
+  const int64_t log_rounds = 1 << 18;
+  if (o.collect_stats && M->dlog_cap < log_rounds) {
+    (void)hipFree(M->dlog);
+    M->dlog = nullptr;
+    HIP_TRY(dalloc(&M->dlog, log_rounds * C_NUM));
+    M->dlog_cap = log_rounds;
+  }
+  int64_t restarts = 0;
+  Ctl host_ctl, ctl_init;
+  for (;;) {
+    pch_status s = ensure_work(M, cap);
+    if (s != PCH_OK) return s;
+    RoundArgs a = make_args(M, o);
+    const int fill_blocks = 1024;
+    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->g, H.nv, bits_host(INFINITY));
+    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->AD, H.nh, bits_host(INFINITY));
+    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->AX, H.nh, kAllOnes);
+    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->fanth, H.nv, kAllOnes);
+    k_fill_u32<<<fill_blocks, kBlock, 0, st>>>(M->claim, H.nv, 0u);
+    std::memset(&ctl_init, 0, sizeof(ctl_init));
+    ctl_init.kmin[0] = ctl_init.kmin[1] = kAllOnes;
+    HIP_TRY(hipMemcpyAsync(M->ctl, &ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    const int nsrc = (int)src.size();
+    k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->dsrc, nsrc);
+    k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, M->dsrc, nsrc);
+    HIP_TRY(hipGetLastError());
+    const int gblocks = grid_for(std::max<int64_t>(cap, 1), 2048);
+    int p = 0;
+    bool overflow = false;
+    for (;;) {
+      for (int r = 0; r < o.rounds_per_sync; ++r) {
+        enqueue_round(a, p, st, gblocks);
+        p ^= 1;
+      }
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(&host_ctl, M->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (host_ctl.overflow) {
+        overflow = true;
+        break;
+      }
+      if (host_ctl.done) break;
+      if ((int64_t)host_ctl.round > kMaxRounds)
+        return set_err(PCH_EOVERFLOW, "no termination after the maximum number of rounds");
+    }
+    if (!overflow) break;
+    if (o.pool_limit > 0 && cap >= o.pool_limit)
+      return set_err(PCH_EOVERFLOW, "window pool exceeded pool_limit");
+    cap *= 2;
+    if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
+    restarts++;
+  }
+  if (host_ctl.nonfinite) return set_err(PCH_ENUMERIC, "non-finite apex crossing in a window");
+  // distances out (bit patterns are the doubles)
+  HIP_TRY(hipMemcpyAsync(dist, M->g, sizeof(double) * H.nv, hipMemcpyDeviceToDevice, st));
+  M->last_rounds = (int64_t)host_ctl.round;
+  if (o.collect_stats) {
+    const int64_t n = std::min<int64_t>(M->last_rounds, M->dlog_cap);
+    M->last_log.assign((size_t)n * C_NUM, 0);
+    if (n) HIP_TRY(hipMemcpyAsync(M->last_log.data(), M->dlog, sizeof(int64_t) * n * C_NUM, hipMemcpyDeviceToHost, st));
+  } else {
+    M->last_log.clear();
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (stats) {
+    const u64* T = host_ctl.tot;
+    stats->rounds = (int64_t)host_ctl.round;
+    stats->created = (int64_t)(T[C_KIDS] + T[C_FANWIN]);
+    stats->processed = (int64_t)T[C_SEL];
+    stats->stale = (int64_t)T[C_STALE];
+    stats->tiny = (int64_t)T[C_TINY];
+    stats->ich_dropped = (int64_t)T[C_ICH];
+    stats->dist_events = (int64_t)T[C_DEV];
+    stats->angle_events = (int64_t)T[C_AEV];
+    stats->fans = (int64_t)T[C_FANS];
+    stats->fan_windows = (int64_t)T[C_FANWIN];
+    stats->deferred = (int64_t)T[C_DEFER];
+    stats->peak_pool = (int64_t)host_ctl.peak;
+    stats->restarts = restarts;
+    stats->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return PCH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""Python binding of the PCH C ABI (include/pch.h).
+
+Argument marshalling only: meshes and sources are passed as host arrays,
+distances come back in a device tensor written by the library's kernels.
+torch supplies device memory and the stream. There is no fallback: if
+``libpch.so`` is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpch.so")
+
+PCH_SELECT_KTH = 0
+PCH_SELECT_TABLE = 2
+
+ROUND_LOG_FIELDS = ["N", "cutbits", "shift", "sel", "stale", "kids", "tiny", "ich", "dev", "aev",
+                    "fans", "fanwin", "defer", "nend"]
+
+# every entry point declared in include/pch.h
+EXPORTS = ["pch_mesh_create", "pch_mesh_create_from_lengths", "pch_mesh_destroy", "pch_mesh_info",
+           "pch_mesh_vertex_tables", "pch_options_default", "pch_geodesic", "pch_round_log",
+           "pch_status_string", "pch_last_error"]
+
+
+class PchError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pch error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("select_mode", ctypes.c_int32), ("filters", ctypes.c_int32), ("k", ctypes.c_int64),
+                ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64),
+                ("pool_limit", ctypes.c_int64), ("collect_stats", ctypes.c_int32),
+                ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
+                ("n_cutoff", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ["rounds", "created", "processed", "stale", "tiny", "ich_dropped", "dist_events",
+                 "angle_events", "fans", "fan_windows", "deferred", "peak_pool", "restarts"]] + \
+               [("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.pch_last_error.restype = ctypes.c_char_p
+        L.pch_status_string.restype = ctypes.c_char_p
+        L.pch_status_string.argtypes = [ctypes.c_int]
+        L.pch_mesh_create.argtypes = [P, i64, P, i64, P, ctypes.POINTER(P)]
+        L.pch_mesh_create_from_lengths.argtypes = [P, i64, i64, P, P, ctypes.POINTER(P)]
+        L.pch_mesh_destroy.argtypes = [P]
+        L.pch_mesh_destroy.restype = None
+        L.pch_mesh_info.argtypes = [P, P, P, P, P]
+        L.pch_mesh_vertex_tables.argtypes = [P, P, P]
+        L.pch_options_default.argtypes = [ctypes.POINTER(Options)]
+        L.pch_options_default.restype = None
+        L.pch_geodesic.argtypes = [P, P, i32, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
+        L.pch_round_log.argtypes = [P, P, i64, P]
+        for n in EXPORTS:
+            getattr(L, n)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PchError(rc, lib().pch_last_error().decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Mesh:
+    """A mesh uploaded to the current device (owns the library handle)."""
+
+    def __init__(self, faces, xyz=None, he_len=None, nv: Optional[int] = None, stream=None):
+        L = lib()
+        self.faces = np.ascontiguousarray(faces, dtype=np.int32)
+        nf = self.faces.shape[0]
+        h = ctypes.c_void_p()
+        if xyz is not None:
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+            self.nv = xyz.shape[0]
+            rc = L.pch_mesh_create(xyz.ctypes.data, self.nv, self.faces.ctypes.data, nf,
+                                   _stream_handle(stream), ctypes.byref(h))
+        else:
+            he_len = np.ascontiguousarray(he_len, dtype=np.float64)
+            self.nv = int(nv if nv is not None else self.faces.max() + 1)
+            rc = L.pch_mesh_create_from_lengths(self.faces.ctypes.data, nf, self.nv, he_len.ctypes.data,
+                                                _stream_handle(stream), ctypes.byref(h))
+        _check(rc)
+        self.handle = h
+        self.nf = nf
+
+    @classmethod
+    def from_generated(cls, m, stream=None) -> "Mesh":
+        if m.xyz is not None:
+            return cls(m.faces, xyz=m.xyz, stream=stream)
+        return cls(m.faces, he_len=m.he_len, nv=m.nv, stream=stream)
+
+    def info(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().pch_mesh_info(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["nv", "nf", "n_boundary_he", "n_pseudo"], [x.value for x in v]))
+
+    def vertex_tables(self):
+        th = np.empty(self.nv, np.float64)
+        fl = np.empty(self.nv, np.uint8)
+        _check(lib().pch_mesh_vertex_tables(self.handle, th.ctypes.data, fl.ctypes.data))
+        return th, fl
+
+    def round_log(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        _check(lib().pch_round_log(self.handle, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 0), len(ROUND_LOG_FIELDS)), np.int64)
+        if n.value:
+            _check(lib().pch_round_log(self.handle, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pch_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().pch_options_default(ctypes.byref(o))
+    table = kw.pop("cutoff_table", None)
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    if table is not None:
+        arr = np.ascontiguousarray(table, dtype=np.float64)
+        o._table = arr  # keep alive
+        o.cutoff_table = arr.ctypes.data
+        o.n_cutoff = arr.size
+        o.select_mode = PCH_SELECT_TABLE
+    return o
+
+
+def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_stats: bool = False, **opts):
+    """Exact geodesic distance from ``sources`` at every vertex (device float64 tensor)."""
+    import torch
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    if out is None:
+        out = torch.empty(mesh.nv, dtype=torch.float64, device="cuda")
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < mesh.nv or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 CUDA tensor with nv elements")
+    o = options(**opts)
+    st = Stats()
+    _check(lib().pch_geodesic(mesh.handle, src.ctypes.data, src.size, out.data_ptr(), _stream_handle(stream),
+                              ctypes.byref(o), ctypes.byref(st)))
+    return (out, st.as_dict()) if return_stats else out

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol include/pch.h declares.
+
+No compute calls: mesh validation errors are reported before any device work,
+so they are checked here without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pch.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:pch_status|void|const char\*)\s+(pch_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def pch():
+    from paper_1305_1293_amd import pch as P
+    P.lib()
+    return P
+
+
+def test_every_declared_symbol_is_exported(pch):
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    L = ctypes.CDLL(pch.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(pch.EXPORTS) == syms
+
+
+def test_status_strings_and_defaults(pch):
+    L = pch.lib()
+    assert L.pch_status_string(0) == b"ok"
+    assert L.pch_status_string(-2) == b"invalid mesh"
+    o = pch.Options()
+    L.pch_options_default(ctypes.byref(o))
+    assert o.k == 16384 and o.filters == 3 and o.select_mode == 0 and o.eps_tiny == 0.0
+
+
+def _code(pch, faces, xyz=None, he_len=None, nv=None):
+    with pytest.raises(pch.PchError) as e:
+        pch.Mesh(np.asarray(faces), xyz=None if xyz is None else np.asarray(xyz, float), he_len=he_len,
+                 nv=nv, stream=0)
+    return e.value.code
+
+
+def test_invalid_meshes_rejected_before_device_work(pch):
+    xyz = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]]
+    assert _code(pch, [[0, 1, 2], [1, 0, 3], [0, 1, 4]], xyz) == -2       # edge with three faces
+    assert _code(pch, [[0, 1, 2], [0, 1, 3]], xyz) == -2                   # flipped neighbour
+    assert _code(pch, [[0, 1, 2]], [[0, 0, 0], [1, 0, 0], [2, 0, 0]]) == -2  # zero area
+    assert _code(pch, [[0, 1, 9]], xyz) == -1                              # index out of range
+    bow = [[0, 0, 0], [1, 0, 0], [1, 1, 0], [-1, 0, 0], [-1, -1, 0]]
+    assert _code(pch, [[0, 1, 2], [0, 3, 4]], bow) == -2                   # two fans at a vertex
+    assert _code(pch, [[0, 1, 2]], he_len=np.array([1.0, 1.0, 3.0]), nv=3) == -2  # lengths violate triangle ineq.
+    assert _code(pch, [[0, 1, 2]], he_len=np.array([1.0, -1.0, 1.0]), nv=3) == -1
