@@ -81,6 +81,9 @@ pch_status pch_mesh_vertex_tables(pch_mesh mesh, double* theta, uint8_t* flags);
 enum {
   PCH_SELECT_KTH = 0,   /* the k smallest keys, to 36 bits below the top
                            differing bit of the pool's key range; ties kept */
+  PCH_SELECT_DELTA = 1, /* keys up to the pool's smallest key plus a step that
+                           starts at delta0 and is scaled after each round by
+                           k / selected (clamped to [1/2, 2]); no histogram */
   PCH_SELECT_TABLE = 2  /* per-round cutoff values from options.cutoff_table
                            (select key <= cutoff); after the table, KTH */
 };
@@ -98,6 +101,12 @@ typedef struct {
   int32_t rounds_per_sync;    /* rounds enqueued between host polls (default 16) */
   const double* cutoff_table; /* host, n_cutoff values, PCH_SELECT_TABLE */
   int64_t n_cutoff;
+  int32_t collect_timing;     /* n > 0: time the propagation launch of every
+                                 n-th round with HIP events on hip_stream
+                                 (pch_stats.ms_propagate) */
+  int32_t reserved;
+  double delta0;              /* first step of PCH_SELECT_DELTA; 0 = twice the
+                                 mean edge length */
 } pch_options;
 
 /* Fill opts with the defaults above. */
@@ -106,7 +115,10 @@ void pch_options_default(pch_options* opts);
 typedef struct {
   int64_t rounds, created, processed, stale, tiny, ich_dropped, dist_events, angle_events,
       fans, fan_windows, deferred, peak_pool, restarts;
-  double ms_total;
+  double ms_total;           /* host wall time of the call */
+  double ms_propagate;       /* summed time of the timed propagation launches */
+  int64_t propagate_launches; /* launches timed in ms_propagate (rounds with work) */
+  double delta0;             /* first step used by PCH_SELECT_DELTA */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).

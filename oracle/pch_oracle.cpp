@@ -45,6 +45,11 @@ const double kTau = 1e-12;
 const double kEv = 1.0 - 1e-12;
 // Interior vertices with total angle above 2 pi + kSaddle are saddles.
 const double kSaddle = 1e-10;
+// Filters drop a window only when the dominating path is shorter by more than
+// a relative 1e-12: near-ties are left to rounding otherwise, and a window
+// grazing a nearly straight convex boundary vertex (the only one carrying rays
+// past it) can lose a tie it wins in exact arithmetic.
+const double kFm = 1.0 + 1e-12;
 
 thread_local std::string g_err;
 
@@ -90,15 +95,15 @@ double orc_atan2(double y, double x) {
 }
 
 // sin and cos of t in [0, pi]: fold to [0, pi/4] by symmetry, then nested
-// Maclaurin series (11 factors each).
+// Maclaurin series (11 factors each, multiplying by the factors' reciprocals).
 void orc_sincos01(double u, double* s, double* c) {
   double u2 = u * u;
   double ps = 1.0, pc = 1.0;
   for (int n = 11; n >= 1; --n) {
-    double ds = (double)(2 * n) * (double)(2 * n + 1);
-    double dc = (double)(2 * n - 1) * (double)(2 * n);
-    ps = 1.0 - (u2 / ds) * ps;
-    pc = 1.0 - (u2 / dc) * pc;
+    double rs = 1.0 / ((double)(2 * n) * (double)(2 * n + 1));
+    double rc = 1.0 / ((double)(2 * n - 1) * (double)(2 * n));
+    ps = 1.0 - (u2 * rs) * ps;
+    pc = 1.0 - (u2 * rc) * pc;
   }
   *s = u * ps;
   *c = pc;
@@ -287,19 +292,19 @@ bool child_filter(double c0, double c1, double cpx, double cpy, double sg, doubl
   if (!ich_on) return true;
   double dx1 = c1 - cpx;
   double f1 = sg + std::sqrt(dx1 * dx1 + cpy * cpy);
-  if (f1 > gu0 + c1) {
+  if (f1 > (gu0 + c1) * kFm) {
     C.ich++;
     return false;
   }
   double dx0 = c0 - cpx;
   double f0 = sg + std::sqrt(dx0 * dx0 + cpy * cpy);
-  if (f0 > gu1 + (lc - c0)) {
+  if (f0 > (gu1 + (lc - c0)) * kFm) {
     C.ich++;
     return false;
   }
   if (rtest) {
     double lhs = r_at_c0 ? f0 : f1;
-    if (lhs > gr + rdist) {
+    if (lhs > (gr + rdist) * kFm) {
       C.ich++;
       return false;
     }
@@ -366,6 +371,8 @@ void propagate(const OMesh& M, double b0, double b1, double px, double py, doubl
         aev.push_back({e, d2, X});
         C.ang_ev++;
         doL = doR = true;
+      } else if (d2 <= Ds * kFm) {
+        doL = doR = true;  // a near-tie keeps both children
       } else if (X < Xs - tol) {
         doL = true;
       } else if (X > Xs + tol) {
@@ -754,9 +761,14 @@ enum {
   RL_DEFER, RL_NEND, RL_WIDTH
 };
 
+// Selection rules of the replica: 0 = k-th smallest key (pick_cutoff);
+// 1 = adaptive step: with m the smallest key in the pool, select keys <= m + delta;
+// after a round that did not take the whole pool, delta is multiplied by
+// k / selected clamped to [1/2, 2]. A cutoff table overrides either rule for
+// its rounds.
 int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double eps_tiny, int32_t filters,
-                const double* cut_table, int64_t n_cut, double* dist, int64_t* stats, int64_t* rlog,
-                int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
+                int32_t mode, double delta0, const double* cut_table, int64_t n_cut, double* dist, int64_t* stats,
+                int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
   const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
   const int64_t nh = 3 * M.nf;
   std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
@@ -768,6 +780,7 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
   std::vector<int32_t> touched;
   Cnt Ctot;
   int64_t created = 0, processed = 0, stale_tot = 0, peak = 0, rounds = 0, updates = 0, ang_updates = 0;
+  double delta = delta0;
 
   auto add = [&](std::vector<RWin>& P, const std::vector<Cand>& ks) {
     for (const Cand& c : ks) P.push_back({c.b0, c.b1, c.px, c.py, c.sg, c.key, c.e, c.src});
@@ -788,10 +801,17 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
     std::vector<double> keys(N);
     for (int64_t i = 0; i < N; ++i) keys[i] = pool[i].key;
     bool ext = cut_table != nullptr && rounds < n_cut;
+    const bool dmode = !ext && mode == 1 && N > k;
     Cut cut{true, 0, 0};
     double cval = INFINITY;
     if (ext) {
       cval = cut_table[rounds];
+    } else if (dmode) {
+      double mn = INFINITY;
+      for (double x : keys) mn = x < mn ? x : mn;
+      cval = mn + delta;
+    } else if (mode == 1) {
+      cut.all = true;
     } else {
       cut = pick_cutoff(keys, k);
     }
@@ -808,7 +828,7 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
         continue;
       }
       bool sel;
-      if (ext) {
+      if (ext || dmode) {
         sel = w.key <= cval;
       } else {
         sel = cut.all || ((bits_of(w.key) >> cut.shift) <= cut.T);
@@ -865,8 +885,8 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
     if (rlog && rounds < max_log) {
       int64_t* r = rlog + rounds * RL_WIDTH;
       r[RL_N] = N;
-      r[RL_CUTBITS] = ext ? (int64_t)bits_of(cval) : (cut.all ? -1 : (int64_t)cut.T);
-      r[RL_SHIFT] = ext ? -2 : cut.shift;
+      r[RL_CUTBITS] = (ext || dmode) ? (int64_t)bits_of(cval) : (cut.all ? -1 : (int64_t)cut.T);
+      r[RL_SHIFT] = ext ? -2 : (dmode ? -3 : cut.shift);
       r[RL_SEL] = nsel;
       r[RL_STALE] = nstale;
       r[RL_KIDS] = C.kept;
@@ -878,6 +898,11 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
       r[RL_FANWIN] = C.fan_kept;
       r[RL_DEFER] = (int64_t)pending.size();
       r[RL_NEND] = (int64_t)nextp.size();
+    }
+    if (dmode) {
+      double ratio = (double)k / (double)(nsel > 0 ? nsel : 1);
+      double f = ratio < 0.5 ? 0.5 : (ratio > 2.0 ? 2.0 : ratio);
+      delta = delta * f;
     }
     processed += nsel;
     stale_tot += nstale;
@@ -968,19 +993,22 @@ int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, 
 }
 
 int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
-                int64_t k, double eps_tiny, int32_t filters, const double* cut_table, int64_t n_cut, double* dist,
-                int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
+                int64_t k, double eps_tiny, int32_t filters, int32_t mode, double delta0, const double* cut_table,
+                int64_t n_cut, double* dist, int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds,
+                int64_t* vupd) {
   OMesh M;
   int rc = build_mesh(faces, nf, nv, he_len, M);
   if (rc) return rc;
   rc = check_sources(src, m, nv);
   if (rc) return rc;
-  if (k < 1 && cut_table == nullptr) return fail(EINVAL_, "k must be >= 1");
+  if (k < 1) return fail(EINVAL_, "k must be >= 1");
+  if (mode != 0 && mode != 1) return fail(EINVAL_, "unknown selection mode");
+  if (mode == 1 && !(delta0 > 0.0)) return fail(EINVAL_, "delta0 must be > 0");
   std::vector<int32_t> s(src, src + m);
   std::sort(s.begin(), s.end());
   s.erase(std::unique(s.begin(), s.end()), s.end());
-  return run_replica(M, s.data(), (int32_t)s.size(), k, eps_tiny, filters, cut_table, n_cut, dist, stats, rlog,
-                     max_log, n_rounds, vupd);
+  return run_replica(M, s.data(), (int32_t)s.size(), k, eps_tiny, filters, mode, delta0, cut_table, n_cut, dist,
+                     stats, rlog, max_log, n_rounds, vupd);
 }
 
 // Dijkstra along mesh edges (length of the best edge path).

@@ -53,12 +53,18 @@ pch_status set_err(pch_status s, const std::string& m) {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kHistBins = 4096;
+constexpr int kSmallGrid = 128;
 constexpr u64 kAllOnes = ~0ull;
 constexpr int64_t kMaxRounds = 1 << 24;
 
 // constants of the window arithmetic (same values as the method description)
 constexpr double kTau = 1e-12;             // endpoint / occupancy tolerance, relative to L
 constexpr double kEv = 1.0 - 1e-12;        // event raised when d < g * kEv
+// Filters drop a window only when the dominating path is shorter by more than
+// a relative 1e-12, so near-ties are never decided by rounding (a window that
+// grazes a nearly straight convex boundary vertex can be the only one carrying
+// rays past it).
+constexpr double kFm = 1.0 + 1e-12;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHalfPi = 0.5 * 3.14159265358979323846;
 constexpr double kQuarterPi = 0.25 * 3.14159265358979323846;
@@ -86,8 +92,11 @@ struct Ctl {
   u64 shift;        // key bits dropped before comparing
   u64 want;         // selected truncated-key prefix after the histogram passes
   u64 rank;         // remaining rank inside the current histogram bin
-  u64 use_table;    // current round uses a cutoff value
+  u64 use_table;    // current round selects key <= cutval
   double cutval;
+  u64 dmode;        // current round uses the adaptive step
+  double delta;     // adaptive step
+  u64 ticket;       // last-block detection
   u64 cnt[C_NUM];   // current round
   u64 xcnt[X_NUM];
   u64 tot[C_NUM];   // totals over all rounds
@@ -145,6 +154,7 @@ struct RoundArgs {
   int64_t ecap;    // distance events per buffer
   int64_t acap;    // angle events
   int64_t k;
+  int32_t mode;
   double eps;
   int32_t ch_on, ich_on, full_fan;
   const double* table;  // device cutoff table or null
@@ -224,6 +234,8 @@ __device__ double dev_atan01(double t) {
   u = u / (1.0 + sqrt(1.0 + u * u));
   const double u2 = u * u;
   double p = 0.0;
+  // unrolled: the coefficients 1/(2i+1) fold to correctly rounded constants
+#pragma unroll
   for (int i = 12; i >= 0; --i) {
     double c = 1.0 / (double)(2 * i + 1);
     if (i & 1) c = -c;
@@ -246,11 +258,14 @@ __device__ double dev_atan2(double y, double x) {
 __device__ void dev_sincos_small(double u, double* s, double* c) {
   const double u2 = u * u;
   double ps = 1.0, pc = 1.0;
+  // unrolled: the reciprocals 1/((2n)(2n+1)) and 1/((2n-1)(2n)) fold to
+  // correctly rounded constants
+#pragma unroll
   for (int n = 11; n >= 1; --n) {
-    const double ds = (double)(2 * n) * (double)(2 * n + 1);
-    const double dc = (double)(2 * n - 1) * (double)(2 * n);
-    ps = 1.0 - (u2 / ds) * ps;
-    pc = 1.0 - (u2 / dc) * pc;
+    const double rs = 1.0 / ((double)(2 * n) * (double)(2 * n + 1));
+    const double rc = 1.0 / ((double)(2 * n - 1) * (double)(2 * n));
+    ps = 1.0 - (u2 * rs) * ps;
+    pc = 1.0 - (u2 * rc) * pc;
   }
   *s = u * ps;
   *c = pc;
@@ -298,13 +313,13 @@ __device__ __forceinline__ int child_filter(double c0, double c1, double cpx, do
   if (!ich_on) return 0;
   const double dx1 = c1 - cpx;
   const double f1 = sg + sqrt(dx1 * dx1 + cpy * cpy);
-  if (f1 > gu0 + c1) return 2;
+  if (f1 > (gu0 + c1) * kFm) return 2;
   const double dx0 = c0 - cpx;
   const double f0 = sg + sqrt(dx0 * dx0 + cpy * cpy);
-  if (f0 > gu1 + (lc - c0)) return 2;
+  if (f0 > (gu1 + (lc - c0)) * kFm) return 2;
   if (rtest) {
     const double lhs = r_at_c0 ? f0 : f1;
-    if (lhs > gr + rdist) return 2;
+    if (lhs > (gr + rdist) * kFm) return 2;
   }
   return 0;
 }
@@ -323,134 +338,300 @@ __device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, do
 
 __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1ull); }
 
-// Fan of windows from pseudo-source vertex v reached at distance d with the
-// incoming ray's back direction at angular position th (Figure 3(c)): every
-// corner meeting the sector of directions at least pi away from th on both
-// sides gets a window on the far side of its opposite edge, clipped to the
-// sector; endpoints inside the sector get deferred distance events.
-// Windows go to P (counter pc), events to E (counter ec).
-__device__ void expand_fan(const RoundArgs& a, int v, double d, double th, bool full, int qi, int ei, u32* kept,
-                           u32* tiny, u32* ich, u32* defer, u32* notwin) {
+// One corner of a fan of windows from pseudo-source vertex v reached at
+// distance d, the incoming ray's back direction at angular position th
+// (Figure 3(c)). A corner that meets the sector of directions at least pi away
+// from th on both sides (all directions when full) yields a window on the far
+// side of its opposite edge, clipped to the sector, and distance events for its
+// endpoints that lie in the sector (the straight edge path).
+struct FanOut {
+  bool win;
+  double b0, b1, px, py, key;
+  int32_t e;
+  int nev;
+  int32_t ev_v[2];
+  double ev_d[2], ev_th[2];
+};
+
+__device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool full, int q, FanOut& o,
+                           u32& tiny, u32& ich, u32& notwin) {
+  o.win = false;
+  o.nev = 0;
   const DevMesh& m = a.m;
-  const Pool& P = a.pool[qi];
-  u64* pc = &a.ctl->npool[qi];
-  const DistEv& E = a.ev[ei];
-  u64* ec = &a.ctl->ndev[ei];
   const u64* g = a.s.g;
-  const double Th = m.theta[v];
-  const bool bd = m.flags[v] & pch::VF_BOUNDARY;
-  const int q1 = m.coff[v + 1];
-  for (int q = m.coff[v]; q < q1; ++q) {
-    const int j = m.corner[q];
-    const double al = m.alpha[j];
-    double t0, t1;
-    if (full) {
+  const int j = m.corner[q];
+  const double al = m.alpha[j];
+  double t0, t1;
+  if (full) {
+    t0 = 0.0;
+    t1 = al;
+  } else if (!(m.flags[v] & pch::VF_BOUNDARY)) {
+    const double Th = m.theta[v];
+    double rel = m.phi[j] - th;
+    if (!isfinite(rel)) return;
+    while (rel < 0.0) rel += Th;
+    while (rel >= Th) rel -= Th;
+    const double lo = kPi - rel;
+    const double hi = (Th - kPi) - rel;
+    t0 = lo > 0.0 ? lo : 0.0;
+    t1 = hi < al ? hi : al;
+    if (!(t0 <= t1)) return;
+  } else {
+    const double rel = m.phi[j] - th;
+    const double hiA = -kPi - rel;
+    const double loB = kPi - rel;
+    if (hiA >= 0.0) {
       t0 = 0.0;
+      t1 = hiA < al ? hiA : al;
+    } else if (loB <= al) {
+      t0 = loB > 0.0 ? loB : 0.0;
       t1 = al;
-    } else if (!bd) {
-      double rel = m.phi[j] - th;
-      if (!isfinite(rel)) continue;
-      while (rel < 0.0) rel += Th;
-      while (rel >= Th) rel -= Th;
-      const double lo = kPi - rel;
-      const double hi = (Th - kPi) - rel;
-      t0 = lo > 0.0 ? lo : 0.0;
-      t1 = hi < al ? hi : al;
-      if (!(t0 <= t1)) continue;
     } else {
-      const double rel = m.phi[j] - th;
-      const double hiA = -kPi - rel;
-      const double loB = kPi - rel;
-      if (hiA >= 0.0) {
-        t0 = 0.0;
-        t1 = hiA < al ? hiA : al;
-      } else if (loB <= al) {
-        t0 = loB > 0.0 ? loB : 0.0;
-        t1 = al;
-      } else {
-        continue;
-      }
+      return;
     }
-    const int n = he_next(j), pj = he_prev(j);
-    const pch::HalfEdge hj = m.he[j];
-    const pch::HalfEdge hn = m.he[n];
-    const int va = hn.v0;  // end of j
-    const int vb = hn.v1;  // start of prev(j)
-    if (t0 <= 0.0) {
-      const double da = d + hj.L;
-      if (da < from_bits(g[va]) * kEv) {
-        const u64 i = atomicAdd(ec, 1ull);
-        if (i < (u64)a.ecap) {
-          E.v[i] = va;
-          E.d[i] = da;
-          E.th[i] = m.phi[n] + m.alpha[n];
-        } else {
-          flag_overflow(a.ctl);
-        }
-        (*defer)++;
-      }
-    }
-    if (t1 >= al && m.twin[pj] < 0) {
-      const double db = d + hj.l02;
-      if (db < from_bits(g[vb]) * kEv) {
-        const u64 i = atomicAdd(ec, 1ull);
-        if (i < (u64)a.ecap) {
-          E.v[i] = vb;
-          E.d[i] = db;
-          E.th[i] = m.phi[pj];
-        } else {
-          flag_overflow(a.ctl);
-        }
-        (*defer)++;
-      }
-    }
-    const int tw = m.twin[n];
-    if (tw < 0) {
-      (*notwin)++;
-      continue;
-    }
-    const double Ln = hn.L, x2n = hn.x2, y2n = hn.y2;
-    const double ipx = Ln - x2n, ipy = -y2n;
-    double c0, c1;
-    if (t1 >= al) {
-      c0 = 0.0;
-    } else {
-      double s, c;
-      dev_sincos(t1, &s, &c);
-      const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
-      c0 = ipx - ipy * (dx / dy);
-    }
-    if (t0 <= 0.0) {
-      c1 = Ln;
-    } else {
-      double s, c;
-      dev_sincos(t0, &s, &c);
-      const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
-      c1 = ipx - ipy * (dx / dy);
-    }
-    if (c0 < 0.0) c0 = 0.0;
-    if (c1 > Ln) c1 = Ln;
-    const int r = child_filter(c0, c1, ipx, ipy, d, Ln, from_bits(g[vb]), from_bits(g[va]), false, false, 0.0, 0.0,
-                               a.eps, a.ich_on);
-    if (r == 1) {
-      (*tiny)++;
-      continue;
-    }
-    if (r == 2) {
-      (*ich)++;
-      continue;
-    }
-    const double key = window_key(c0, c1, ipx, ipy, d);
-    const u64 i = atomicAdd(pc, 1ull);
-    if (i < (u64)a.cap) {
-      store_window(P, i, c0, c1, ipx, ipy, d, key, tw, v);
-      atomicMin(&a.ctl->kmin[qi], bits(key));
-      atomicMax(&a.ctl->kmax[qi], bits(key));
-    } else {
-      flag_overflow(a.ctl);
-    }
-    (*kept)++;
   }
+  const int n = he_next(j), pj = he_prev(j);
+  const pch::HalfEdge hj = m.he[j];
+  const pch::HalfEdge hn = m.he[n];
+  const int va = hn.v0;  // end of j
+  const int vb = hn.v1;  // start of prev(j)
+  if (t0 <= 0.0) {
+    const double da = d + hj.L;
+    if (da < from_bits(g[va]) * kEv) {
+      o.ev_v[o.nev] = va;
+      o.ev_d[o.nev] = da;
+      o.ev_th[o.nev] = m.phi[n] + m.alpha[n];
+      o.nev++;
+    }
+  }
+  if (t1 >= al && m.twin[pj] < 0) {
+    const double db = d + hj.l02;
+    if (db < from_bits(g[vb]) * kEv) {
+      o.ev_v[o.nev] = vb;
+      o.ev_d[o.nev] = db;
+      o.ev_th[o.nev] = m.phi[pj];
+      o.nev++;
+    }
+  }
+  const int tw = m.twin[n];
+  if (tw < 0) {
+    notwin++;
+    return;
+  }
+  const double Ln = hn.L, x2n = hn.x2, y2n = hn.y2;
+  const double ipx = Ln - x2n, ipy = -y2n;
+  double c0, c1;
+  if (t1 >= al) {
+    c0 = 0.0;
+  } else {
+    double s, c;
+    dev_sincos(t1, &s, &c);
+    const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+    c0 = ipx - ipy * (dx / dy);
+  }
+  if (t0 <= 0.0) {
+    c1 = Ln;
+  } else {
+    double s, c;
+    dev_sincos(t0, &s, &c);
+    const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+    c1 = ipx - ipy * (dx / dy);
+  }
+  if (c0 < 0.0) c0 = 0.0;
+  if (c1 > Ln) c1 = Ln;
+  const int r = child_filter(c0, c1, ipx, ipy, d, Ln, from_bits(g[vb]), from_bits(g[va]), false, false, 0.0, 0.0,
+                             a.eps, a.ich_on);
+  if (r == 1) {
+    tiny++;
+    return;
+  }
+  if (r == 2) {
+    ich++;
+    return;
+  }
+  o.win = true;
+  o.b0 = c0;
+  o.b1 = c1;
+  o.px = ipx;
+  o.py = ipy;
+  o.key = window_key(c0, c1, ipx, ipy, d);
+  o.e = tw;
+}
+
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int y = __shfl_xor(x, o, kWave);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double shfl_d(double x, int src) {
+  return from_bits(shfl64(bits(x), src));
+}
+
+// Fans of the lanes of one wavefront (has = this lane expands a fan of vertex
+// v at distance d). The wavefront's (fan, corner) pairs are spread over its
+// lanes: an exclusive prefix sum of the fan degrees numbers the pairs and each
+// lane finds the owner of its pair by binary search over the lanes. Windows
+// and events are reserved once per wavefront and step; windows go to pool qi,
+// events to event buffer qi. Every lane of the wavefront must call it.
+__device__ void wave_fans(const RoundArgs& a, bool has, int v, double d, double th, bool full, int qi, u64& kmn,
+                          u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer, u32& notwin) {
+  Ctl* c = a.ctl;
+  const int lane = lane_id();
+  const int q0 = has ? a.m.coff[v] : 0;
+  const int deg = has ? a.m.coff[v + 1] - q0 : 0;
+  int incl = deg;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, kWave - 1, kWave);
+  const int base = incl - deg;
+  const Pool& P = a.pool[qi];
+  const DistEv& E = a.ev[qi];
+  for (int t0 = 0; t0 < total; t0 += kWave) {
+    const int t = t0 + lane;
+    // owner: the largest lane whose base is <= t (lanes with deg 0 share the
+    // base of the next lane, so the largest such lane owns the pair)
+    int lo = 0, hi = kWave - 1;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi + 1) >> 1;
+      const int bm = __shfl(base, mid, kWave);
+      if (bm <= t) lo = mid; else hi = mid - 1;
+    }
+    const int owner = lo;
+    const int ov = __shfl(v, owner, kWave);
+    const int oq = __shfl(q0, owner, kWave) + (t - __shfl(base, owner, kWave));
+    const double od = shfl_d(d, owner);
+    const double oth = shfl_d(th, owner);
+    FanOut o;
+    o.win = false;
+    o.nev = 0;
+    if (t < total) fan_corner(a, ov, od, oth, full, oq, o, tiny, ich, notwin);
+    const u64 jw = wave_reserve(&c->npool[qi], o.win ? 1u : 0u);
+    const u64 je = wave_reserve(&c->ndev[qi], (u32)o.nev);
+    if (o.win) {
+      if (jw < (u64)a.cap) {
+        store_window(P, jw, o.b0, o.b1, o.px, o.py, od, o.key, o.e, ov);
+        const u64 kb = bits(o.key);
+        kmn = kb < kmn ? kb : kmn;
+        kmx = kb > kmx ? kb : kmx;
+      } else {
+        flag_overflow(c);
+      }
+      kept++;
+    }
+    for (int q = 0; q < o.nev; ++q) {
+      if (je + q < (u64)a.ecap) {
+        E.v[je + q] = o.ev_v[q];
+        E.d[je + q] = o.ev_d[q];
+        E.th[je + q] = o.ev_th[q];
+      } else {
+        flag_overflow(c);
+      }
+    }
+    defer += (u32)o.nev;
+  }
+}
+
+// relaxed agent-scope load of a counter that other workgroups update atomically
+__device__ __forceinline__ u64 ld(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Round set-up for input parity p (one thread): log and total the previous
+// round, stop when nothing is left, reset this round's output buffers and set
+// up the selection rule.
+__device__ void round_begin(const RoundArgs& a, int p) {
+  Ctl* c = a.ctl;
+  if (ld(&c->done)) return;
+  if (ld(&c->active)) {
+    const u64 r = ld(&c->round) - 1;
+    u64 rec[C_NUM];
+    for (int f = 0; f < C_NUM; ++f) rec[f] = ld(&c->cnt[f]);
+    rec[C_NEND] = ld(&c->npool[p]);
+    rec[C_DEFER] = ld(&c->ndev[p]);
+    for (int f = 0; f < C_NUM; ++f) {
+      if (a.log && (int64_t)r < a.max_log) a.log[r * C_NUM + f] = (int64_t)rec[f];
+      c->tot[f] = ld(&c->tot[f]) + rec[f];
+    }
+    // adaptive step: steer the next cutoff toward k selected windows
+    if (ld(&c->dmode)) {
+      const u64 ns = rec[C_SEL];
+      const double ratio = (double)a.k / (double)(ns > 0 ? ns : 1ull);
+      const double f = ratio < 0.5 ? 0.5 : (ratio > 2.0 ? 2.0 : ratio);
+      c->delta = c->delta * f;
+    }
+    c->active = 0;
+  }
+  if (ld(&c->overflow)) {
+    c->done = 1;
+    return;
+  }
+  const u64 N = ld(&c->npool[p]);
+  const u64 nd = ld(&c->ndev[p]);
+  if (N == 0 && nd == 0) {
+    c->done = 1;
+    return;
+  }
+  c->active = 1;
+  const u64 round = ld(&c->round) + 1;
+  c->round = round;
+  if (N > ld(&c->peak)) c->peak = N;
+  for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
+  c->cnt[C_N] = N;
+  c->npool[1 - p] = 0;
+  c->ndev[1 - p] = 0;
+  c->nsel = 0;
+  c->naev = 0;
+  c->kmin[1 - p] = kAllOnes;
+  c->kmax[1 - p] = 0;
+  c->use_table = 0;
+  c->sel_all = 0;
+  c->dmode = 0;
+  c->rank = 0;
+  const u64 r = round - 1;
+  if (a.table && (int64_t)r < a.n_table) {
+    c->use_table = 1;
+    c->cutval = a.table[r];
+    c->cnt[C_CUT] = bits(c->cutval);
+    c->cnt[C_SHIFT] = (u64)(int64_t)-2;
+    return;
+  }
+  if (N <= (u64)a.k) {
+    c->sel_all = 1;
+    c->cnt[C_CUT] = (u64)(int64_t)-1;
+    c->cnt[C_SHIFT] = 0;
+    return;
+  }
+  const u64 mn = ld(&c->kmin[p]), mx = ld(&c->kmax[p]);
+  if (a.mode == PCH_SELECT_DELTA) {
+    c->dmode = 1;
+    c->use_table = 1;
+    c->cutval = from_bits(mn) + c->delta;
+    c->cnt[C_CUT] = bits(c->cutval);
+    c->cnt[C_SHIFT] = (u64)(int64_t)-3;
+    return;
+  }
+  const u64 dif = mn ^ mx;
+  if (dif == 0) {
+    c->shift = 0;
+    c->want = mx;
+    c->cnt[C_CUT] = mx;
+    c->cnt[C_SHIFT] = 0;
+    return;
+  }
+  const int hb = 63 - __clzll((long long)dif);
+  int s = hb + 1 - 36;
+  if (s < 0) s = 0;
+  c->shift = (u64)s;
+  c->want = (mn >> s) >> 36;  // common prefix above the 36 bits searched
+  c->rank = (u64)a.k;
 }
 
 // ---------------------------------------------------------------------------
@@ -473,89 +654,34 @@ __global__ void k_set_sources(u64* g, const int32_t* src, int m) {
 }
 
 // Initialization (Algorithm 1, lines 1-2): every source gets a full fan into
-// pool 0 and deferred events for its one-ring into event buffer 0.
-__global__ void k_init_fans(RoundArgs a, const int32_t* src, int m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+// pool 0 and events for its one-ring into event buffer 0.
+__global__ void __launch_bounds__(kBlock) k_init_fans(RoundArgs a, const int32_t* src, int m) {
+  u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
-  expand_fan(a, src[i], 0.0, 0.0, true, 0, 0, &kept, &tiny, &ich, &defer, &notwin);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i - lane_id() < m; i += gridDim.x * kBlock) {
+    const bool has = i < m;
+    wave_fans(a, has, has ? src[i] : 0, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
+  }
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
+  if (lane_id() == 0) {
+    if (kmn != kAllOnes) atomicMin(&a.ctl->kmin[0], kmn);
+    if (kmx != 0) atomicMax(&a.ctl->kmax[0], kmx);
+  }
 }
 
-// Round set-up (single thread): log the previous round, stop when nothing is
-// left, otherwise reset the output buffers of this round and prepare the
-// cutoff search.
-__global__ void k_begin(RoundArgs a, int p) {
-  Ctl* c = a.ctl;
-  if (c->done) return;
-  if (c->active) {
-    const u64 r = c->round - 1;
-    c->cnt[C_NEND] = c->npool[p];
-    c->cnt[C_DEFER] = c->ndev[p];
-    if (a.log && (int64_t)r < a.max_log)
-      for (int f = 0; f < C_NUM; ++f) a.log[r * C_NUM + f] = (int64_t)c->cnt[f];
-    for (int f = 0; f < C_NUM; ++f) c->tot[f] += c->cnt[f];
-    c->active = 0;
-  }
-  if (c->overflow) {
-    c->done = 1;
-    return;
-  }
-  const u64 N = c->npool[p];
-  const u64 nd = c->ndev[p];
-  if (N == 0 && nd == 0) {
-    c->done = 1;
-    return;
-  }
-  c->active = 1;
-  c->round += 1;
-  if (N > c->peak) c->peak = N;
-  for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
-  c->cnt[C_N] = N;
-  c->npool[1 - p] = 0;
-  c->ndev[1 - p] = 0;
-  c->nsel = 0;
-  c->naev = 0;
-  c->kmin[1 - p] = kAllOnes;
-  c->kmax[1 - p] = 0;
-  c->use_table = 0;
-  c->sel_all = 0;
-  const u64 r = c->round - 1;
-  if (a.table && (int64_t)r < a.n_table) {
-    c->use_table = 1;
-    c->cutval = a.table[r];
-    c->cnt[C_CUT] = bits(c->cutval);
-    c->cnt[C_SHIFT] = (u64)(int64_t)-2;
-    c->rank = 0;
-    return;
-  }
-  if (N <= (u64)a.k) {
-    c->sel_all = 1;
-    c->cnt[C_CUT] = (u64)(int64_t)-1;
-    c->cnt[C_SHIFT] = 0;
-    c->rank = 0;
-    return;
-  }
-  const u64 mn = c->kmin[p], mx = c->kmax[p];
-  const u64 dif = mn ^ mx;
-  if (dif == 0) {
-    c->shift = 0;
-    c->want = mx;
-    c->rank = 0;  // no histogram pass needed
-    return;
-  }
-  const int hb = 63 - __clzll((long long)dif);
-  int s = hb + 1 - 36;
-  if (s < 0) s = 0;
-  c->shift = (u64)s;
-  c->want = (mn >> s) >> 36;  // common prefix above the 36 bits searched
-  c->rank = (u64)a.k;
-}
+__global__ void k_begin(RoundArgs a, int p) { round_begin(a, p); }
 
-// One 12-bit radix-select pass over the truncated keys t = key_bits >> shift.
+// One 12-bit radix-select pass over the truncated keys t = key_bits >> shift:
 // pass 0 bins bits 35..24, pass 1 bits 23..12, pass 2 bits 11..0, counting
-// only keys whose higher bits equal the prefix chosen so far.
+// only keys whose higher bits equal the prefix chosen so far. The last block
+// to finish finds the bin holding the remaining rank, extends the prefix and
+// clears the histogram.
 __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   __shared__ u32 h[kHistBins];
+  __shared__ u32 part[kBlock];
+  __shared__ u32 pick_bin, pick_before;
+  __shared__ int is_last;
   Ctl* c = a.ctl;
   if (!c->active || c->use_table || c->sel_all || c->rank == 0) return;
   for (int i = threadIdx.x; i < kHistBins; i += kBlock) h[i] = 0;
@@ -572,31 +698,27 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   __syncthreads();
   for (int i = threadIdx.x; i < kHistBins; i += kBlock)
     if (h[i]) atomicAdd(&a.hist[i], h[i]);
-}
-
-// Finds the bin holding the remaining rank, extends the prefix, clears the
-// histogram. One block.
-__global__ void __launch_bounds__(kBlock) k_hist_scan(RoundArgs a) {
-  __shared__ u32 part[kBlock];
-  __shared__ u32 pick_bin, pick_before;
-  Ctl* c = a.ctl;
-  if (!c->active || c->use_table || c->sel_all || c->rank == 0) return;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  constexpr int per = kHistBins / kBlock;
+  u32 loc[per];
+  u32 sum = 0;
+  for (int i = 0; i < per; ++i) {
+    loc[i] = __hip_atomic_load(&a.hist[threadIdx.x * per + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sum += loc[i];
+  }
   if (threadIdx.x == 0) {
     pick_bin = 0;
     pick_before = 0;
   }
-  constexpr int per = kHistBins / kBlock;  // 16 bins per thread
-  u32 loc[per];
-  u32 sum = 0;
-  for (int i = 0; i < per; ++i) {
-    loc[i] = a.hist[threadIdx.x * per + i];
-    sum += loc[i];
-  }
   part[threadIdx.x] = sum;
   __syncthreads();
-  // inclusive scan of part[] (Hillis-Steele in LDS)
   for (int o = 1; o < kBlock; o <<= 1) {
-    u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+    const u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
     __syncthreads();
     part[threadIdx.x] += y;
     __syncthreads();
@@ -618,8 +740,10 @@ __global__ void __launch_bounds__(kBlock) k_hist_scan(RoundArgs a) {
   __syncthreads();
   for (int i = threadIdx.x; i < kHistBins; i += kBlock) a.hist[i] = 0;
   if (threadIdx.x == 0) {
-    c->want = (c->want << 12) | pick_bin;
+    c->want = (want << 12) | pick_bin;
     c->rank = rank - pick_before;
+    c->ticket = 0;
+    if (pass == 2) c->cnt[C_CUT] = c->want, c->cnt[C_SHIFT] = c->shift;
   }
 }
 
@@ -703,6 +827,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->cnt[C_SEL] = c->nsel;
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
   u64 kmn = kAllOnes, kmx = 0;
   const u64 stride = (u64)gridDim.x * kBlock;
@@ -780,6 +905,8 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
             aD = d2;
             aX = X;
             doL = doR = true;
+          } else if (d2 <= Ds * kFm) {
+            doL = doR = true;  // a near-tie keeps both children
           } else if (X < Xs - tol) {
             doL = true;
           } else if (X > Xs + tol) {
@@ -976,8 +1103,10 @@ __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
 
 // Third pass: the winning crossing per corner; one fan per improved
 // pseudo-source vertex, windows into the next pool, deferred endpoint events
-// into the next round's event buffer.
+// into the next round's event buffer. The last block to finish sets up the
+// next round.
 __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
+  __shared__ int is_last;
   Ctl* c = a.ctl;
   if (!c->active) return;
   const u64 nd = min(c->ndev[p], (u64)a.ecap);
@@ -988,40 +1117,49 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
     if (bits(a.aev.D[i]) == a.s.AD[e]) atomicMin(&a.s.AX[e], ordkey(a.aev.X[i]));
   }
   const u32 stamp = (u32)c->round;
+  u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride) {
-    const int v = a.ev[p].v[i];
-    const double d = a.ev[p].d[i];
-    if (bits(d) != a.s.g[v] || !(a.m.flags[v] & pch::VF_PSEUDO)) continue;
-    const u64 tk = ordkey(a.ev[p].th[i]);
-    if (tk != a.s.fanth[v]) continue;
-    if (atomicMax(&a.s.claim[v], stamp) >= stamp) continue;
-    a.s.fanth[v] = kAllOnes;
-    fans++;
-    expand_fan(a, v, d, a.ev[p].th[i], a.full_fan != 0, 1 - p, 1 - p, &kept, &tiny, &ich, &defer, &notwin);
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < nd; i += stride) {
+    bool has = false;
+    int v = 0;
+    double d = 0.0, th = 0.0;
+    if (i < nd) {
+      v = a.ev[p].v[i];
+      d = a.ev[p].d[i];
+      th = a.ev[p].th[i];
+      if (bits(d) == a.s.g[v] && (a.m.flags[v] & pch::VF_PSEUDO) && ordkey(th) == a.s.fanth[v] &&
+          atomicMax(&a.s.claim[v], stamp) < stamp) {
+        a.s.fanth[v] = kAllOnes;
+        has = true;
+        fans++;
+      }
+    }
+    wave_fans(a, has, v, d, th, a.full_fan != 0, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
   kept = wave_sum(kept);
   tiny = wave_sum(tiny);
   ich = wave_sum(ich);
   fans = wave_sum(fans);
   notwin = wave_sum(notwin);
   if (lane_id() == 0) {
+    if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
+    if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
     if (kept) atomicAdd(&c->cnt[C_FANWIN], (u64)kept);
     if (tiny) atomicAdd(&c->cnt[C_TINY], (u64)tiny);
     if (ich) atomicAdd(&c->cnt[C_ICH], (u64)ich);
     if (fans) atomicAdd(&c->cnt[C_FANS], (u64)fans);
     if (notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)notwin);
   }
-}
-
-// Records the round's selection count and cutoff in its log counters.
-__global__ void k_note_sel(RoundArgs a) {
-  Ctl* c = a.ctl;
-  if (!c->active) return;
-  c->cnt[C_SEL] = c->nsel;
-  if (!c->sel_all && !c->use_table) {
-    c->cnt[C_CUT] = c->want;
-    c->cnt[C_SHIFT] = c->shift;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    __threadfence();
+    c->ticket = 0;
+    round_begin(a, 1 - p);
   }
 }
 
@@ -1215,6 +1353,7 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.ecap = M->ecap;
   a.acap = M->acap;
   a.k = o.k;
+  a.mode = o.select_mode;
   a.eps = o.eps_tiny;
   a.ch_on = (o.filters & 1) != 0;
   a.ich_on = (o.filters & 2) != 0;
@@ -1231,19 +1370,23 @@ int grid_for(int64_t work, int max_blocks) {
   return (int)b;
 }
 
-// Enqueue one round with input parity p.
-void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int gblocks) {
-  k_begin<<<1, 1, 0, st>>>(a, p);
-  for (int pass = 0; pass < 3; ++pass) {
-    k_hist<<<std::min(gblocks, 512), kBlock, 0, st>>>(a, p, pass);
-    k_hist_scan<<<1, kBlock, 0, st>>>(a);
-  }
-  k_partition<<<gblocks, kBlock, 0, st>>>(a, p);
-  k_note_sel<<<1, 1, 0, st>>>(a);
-  k_propagate<<<gblocks, kBlock, 0, st>>>(a, p);
-  k_events1<<<gblocks, kBlock, 0, st>>>(a, p);
-  k_events2<<<gblocks, kBlock, 0, st>>>(a, p);
-  k_events3<<<gblocks, kBlock, 0, st>>>(a, p);
+// Enqueue one round with input parity p (its set-up already ran: the initial
+// k_begin or the previous round's k_events3). ev0/ev1 (optional) bracket the
+// propagation launch.
+// Grids: the pool scan uses pool_blocks; propagation is sized for about twice
+// k windows; event passes and histograms use few blocks because their work is
+// small and the last-block ticket serializes one atomic per block.
+void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, int prop_blocks, bool kth,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  if (kth)
+    for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
+  k_partition<<<pool_blocks, kBlock, 0, st>>>(a, p);
+  if (ev0) (void)hipEventRecord(ev0, st);
+  k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p);
+  if (ev1) (void)hipEventRecord(ev1, st);
+  k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+  k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+  k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
 }
 
 }  // namespace
@@ -1350,8 +1493,10 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   pch_options o;
   pch_options_default(&o);
   if (opts) o = *opts;
-  if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_TABLE)
+  if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_TABLE)
     return set_err(PCH_EINVAL, "unknown select_mode");
+  if (!(o.delta0 >= 0.0)) return set_err(PCH_EINVAL, "delta0 must be >= 0");
+  if (o.collect_timing < 0) return set_err(PCH_EINVAL, "collect_timing must be >= 0");
   if (o.k < 1) return set_err(PCH_EINVAL, "k must be >= 1");
   if (o.select_mode == PCH_SELECT_TABLE && (o.n_cutoff < 0 || (o.n_cutoff > 0 && !o.cutoff_table)))
     return set_err(PCH_EINVAL, "cutoff table missing");
@@ -1384,6 +1529,12 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     }
     HIP_TRY(hipMemcpyAsync(M->dtable, o.cutoff_table, sizeof(double) * o.n_cutoff, hipMemcpyHostToDevice, st));
   }
+  double delta0 = o.delta0;
+  if (delta0 == 0.0) {
+    double sum = 0.0;
+    for (int64_t j = 0; j < H.nh; ++j) sum += H.he[j].L;
+    delta0 = 2.0 * (sum / (double)H.nh);
+  }
   int64_t cap = o.pool_capacity > 0 ? o.pool_capacity : std::max<int64_t>(1 << 18, 2 * H.nh);
   if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
   const int64_t log_rounds = 1 << 18;
@@ -1395,6 +1546,20 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   }
   int64_t restarts = 0;
   Ctl host_ctl, ctl_init;
+  // optional per-launch timing of the propagation kernel
+  std::vector<hipEvent_t> tev;
+  if (o.collect_timing) {
+    tev.resize(2 * (size_t)o.rounds_per_sync);
+    for (auto& e : tev) HIP_TRY(hipEventCreate(&e));
+  }
+  struct EvGuard {
+    std::vector<hipEvent_t>& v;
+    ~EvGuard() {
+      for (auto e : v) (void)hipEventDestroy(e);
+    }
+  } ev_guard{tev};
+  double prop_ms = 0.0;
+  int64_t prop_n = 0;
   for (;;) {
     pch_status s = ensure_work(M, cap);
     if (s != PCH_OK) return s;
@@ -1407,22 +1572,44 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     k_fill_u32<<<fill_blocks, kBlock, 0, st>>>(M->claim, H.nv, 0u);
     std::memset(&ctl_init, 0, sizeof(ctl_init));
     ctl_init.kmin[0] = ctl_init.kmin[1] = kAllOnes;
+    ctl_init.delta = delta0;
     HIP_TRY(hipMemcpyAsync(M->ctl, &ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, st));
     const int nsrc = (int)src.size();
     k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->dsrc, nsrc);
     k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, M->dsrc, nsrc);
+    k_begin<<<1, 1, 0, st>>>(a, 0);
     HIP_TRY(hipGetLastError());
-    const int gblocks = grid_for(std::max<int64_t>(cap, 1), 2048);
+    const int pool_blocks = grid_for(std::max<int64_t>(cap, 1), 1024);
+    const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
+    const bool kth = o.select_mode != PCH_SELECT_DELTA;
     int p = 0;
     bool overflow = false;
+    prop_ms = 0.0;
+    prop_n = 0;
+    u64 rounds_before = 0;
     for (;;) {
       for (int r = 0; r < o.rounds_per_sync; ++r) {
-        enqueue_round(a, p, st, gblocks);
+        const bool timed = o.collect_timing && ((rounds_before + (u64)r) % (u64)o.collect_timing == 0);
+        if (timed)
+          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, tev[2 * r], tev[2 * r + 1]);
+        else
+          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth);
         p ^= 1;
       }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(&host_ctl, M->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
+      if (o.collect_timing) {
+        const u64 ran = host_ctl.round - rounds_before;
+        for (u64 r = 0; r < ran && r < (u64)o.rounds_per_sync; ++r) {
+          if ((rounds_before + r) % (u64)o.collect_timing != 0) continue;
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, tev[2 * r], tev[2 * r + 1]));
+          prop_ms += ms;
+          prop_n++;
+        }
+      }
+      rounds_before = host_ctl.round;
       if (host_ctl.overflow) {
         overflow = true;
         break;
@@ -1467,6 +1654,9 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     stats->restarts = restarts;
     stats->ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    stats->ms_propagate = prop_ms;
+    stats->propagate_launches = prop_n;
+    stats->delta0 = delta0;
   }
   return PCH_OK;
 }

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpch.so")
 
 PCH_SELECT_KTH = 0
+PCH_SELECT_DELTA = 1
 PCH_SELECT_TABLE = 2
 
 ROUND_LOG_FIELDS = ["N", "cutbits", "shift", "sel", "stale", "kids", "tiny", "ich", "dev", "aev",
@@ -39,14 +40,16 @@ class Options(ctypes.Structure):
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64),
                 ("pool_limit", ctypes.c_int64), ("collect_stats", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
-                ("n_cutoff", ctypes.c_int64)]
+                ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("delta0", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ["rounds", "created", "processed", "stale", "tiny", "ich_dropped", "dist_events",
                  "angle_events", "fans", "fan_windows", "deferred", "peak_pool", "restarts"]] + \
-               [("ms_total", ctypes.c_double)]
+               [("ms_total", ctypes.c_double), ("ms_propagate", ctypes.c_double),
+                ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

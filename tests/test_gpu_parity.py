@@ -92,23 +92,38 @@ def test_small_config_vs_ich(pch, oracle, k):
 
 
 @pytest.mark.parametrize("case", [("sinusoid64", 0, 64), ("sinusoid64", 0, 1024), ("sphere4", 17, 512),
-                                  ("lshape", -1, 16), ("cone7", 5, 8), ("grid48", 100, 4096)])
+                                  ("lshape", -1, 16), ("cone7", 5, 8), ("grid48", 100, 4096),
+                                  ("sinusoid64", 0, 1024, 0.02), ("sphere4", 17, 512, 0.05),
+                                  ("grid48", 100, 2048, 0.01)])
 def test_round_log_matches_replica(pch, oracle, case):
-    name, s, k = case
+    name, s, k = case[:3]
+    delta0 = case[3] if len(case) > 3 else None
+    sel = dict(mode=1, delta0=delta0) if delta0 else {}
+    gsel = dict(select_mode=1, delta0=delta0) if delta0 else {}
     m = {"sinusoid64": lambda: G.config_mesh(1), "sphere4": lambda: G.bumpy_icosphere(4, seed=9),
          "lshape": lambda: G.lshape(6), "cone7": lambda: G.cone_fan(7, 6),
          "grid48": lambda: G.bump_grid(48, seed=4)}[name]()
     if s < 0:
         s = int(np.argmin(np.linalg.norm(m.xyz[:, :2] - [2.0, 0.0], axis=1)))
-    say(f"round log parity {name} source {s} k {k}")
-    dr, st_r, log_r = oracle.replica(m, [s], k)
-    d, st, log = gpu_field(pch, m, [s], k=k, collect_stats=1)
+    say(f"round log parity {name} source {s} k {k} delta0 {delta0}")
+    dr, st_r, log_r = oracle.replica(m, [s], k, **sel)
+    d, st, log = gpu_field(pch, m, [s], k=k, collect_stats=1, **gsel)
     assert log.shape == log_r.shape, f"rounds: gpu {log.shape[0]} replica {log_r.shape[0]}"
     bad = np.nonzero(np.any(log != log_r, axis=1))[0]
     assert bad.size == 0, f"first differing round {bad[0]}: gpu {log[bad[0]].tolist()} replica {log_r[bad[0]].tolist()}"
     assert np.array_equal(d.view(np.uint64), dr.view(np.uint64)), "distance bits differ from the replica"
     ref, _ = oracle.ich(m, [s])
     assert_close(d, ref, mean_edge(oracle, m), what=name)
+
+
+def test_grazing_boundary_regression(pch, oracle):
+    m = G.bump_grid(96, seed=23)
+    say("bump grid 96 seed 23 (grazing convex boundary)")
+    ref, _ = oracle.ich(m, [0])
+    assert np.isfinite(ref).all()
+    for mode in (0, 1):
+        d, _, _ = gpu_field(pch, m, [0], k=4096, select_mode=mode)
+        assert_close(d, ref, mean_edge(oracle, m), what=f"mode {mode}")
 
 
 def test_multi_source_min(pch, oracle):

@@ -125,3 +125,17 @@ def test_window_counts_close_to_ich(oracle, c1):
     _, st, _ = oracle.replica(c1, [0], 256)
     ratio = st["created"] / st_ich["created"]
     assert 0.95 < ratio < 1.3
+
+
+def test_grazing_convex_boundary_regression(oracle):
+    """A geodesic grazing a nearly straight boundary past a convex boundary
+    vertex is carried by a sliver window that wins against the path bending at
+    that vertex by about 1e-17 relative. Filters that decided such near-ties by
+    rounding left boundary vertices unreachable on this 96 x 96 bump grid."""
+    m = G.bump_grid(96, seed=23)
+    d, _ = oracle.ich(m, [0])
+    assert np.isfinite(d).all()
+    ref, _ = oracle.ich(m, [0], filters=1)  # CH rule only, no window filter
+    assert rel(d, ref) < 1e-12
+    dr, _, _ = oracle.replica(m, [0], 2048)
+    assert rel(dr, ref) < 1e-12
