@@ -142,6 +142,61 @@ pch_status pch_geodesic(pch_mesh mesh, const int32_t* sources, int32_t m, double
  * Writes min(max_rounds, rounds) records to out (host); *n_rounds = rounds. */
 pch_status pch_round_log(pch_mesh mesh, int64_t* out, int64_t max_rounds, int64_t* n_rounds);
 
+/* ------------------------------------------------------------------------
+ * Batched fields: many independent single-source fields on meshes of uneven
+ * size in one persistent launch. Each workgroup takes the next field from a
+ * device queue (largest meshes first) and runs all of its rounds alone with
+ * the adaptive-step selection (PCH_SELECT_DELTA); results equal pch_geodesic
+ * with the same k and delta0 bit for bit. Fields whose windows outgrow a
+ * workgroup's pool are rerun with pch_geodesic.
+ * ---------------------------------------------------------------------- */
+typedef struct pch_batch_s* pch_batch;
+
+typedef struct {
+  int64_t k;             /* windows per round and field (default 1024) */
+  int32_t teams_per_cu;  /* resident workgroups per compute unit (default 2) */
+  int32_t filters;       /* as pch_options.filters (default 3) */
+  double eps_tiny;       /* as pch_options.eps_tiny (default 0) */
+  int64_t pool_capacity; /* windows per workgroup; 0 = from the largest mesh */
+  int32_t use_graph;     /* 1 = replay a captured HIP graph of the launch (default) */
+  int32_t team_threads;  /* threads of the workgroup that runs one field: 256
+                            (default) or 1024 */
+} pch_batch_options;
+
+typedef struct {
+  int64_t fields, reruns, max_rounds, processed, created, teams, k;
+  double ms_total; /* host wall time of the call */
+} pch_batch_stats;
+
+void pch_batch_options_default(pch_batch_options* opts);
+
+/* meshes: n_meshes handles created on the current device (kept by reference:
+ * they must outlive the batch). Field f is the distance field from vertex
+ * field_source[f] of mesh field_mesh[f]. Errors: PCH_EINVAL (index out of
+ * range, n_fields < 1), PCH_ENOMEM, PCH_EDEVICE. */
+pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int32_t* field_mesh,
+                            const int32_t* field_source, int32_t n_fields, const pch_batch_options* opts,
+                            pch_batch* out);
+void pch_batch_destroy(pch_batch batch);
+
+/* offsets: host int64 [n_fields + 1]; field f occupies dist[offsets[f] ..
+ * offsets[f + 1]) in the output of pch_batch_run. */
+pch_status pch_batch_offsets(pch_batch batch, int64_t* offsets);
+
+/* dist: device double [offsets[n_fields]] (caller-owned). */
+pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_batch_stats* stats);
+
+/* Per-field record of the last run, host int64 [n_fields][8]: status (0 ok,
+ * 1 rerun after pool overflow, 2 rerun after the round limit), rounds,
+ * windows processed, windows created, fans, peak pool, stale windows, 0. */
+pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
+
+/* Autotuner: times k in {2048, 4096, 8192, 16384} with workgroup shapes
+ * (256 threads, 2 per CU), (256, 4) and (1024, 1) on the whole batch (into
+ * dist), keeps the fastest in the batch and returns it in chosen (may be
+ * NULL). */
+pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
+
 const char* pch_status_string(pch_status s);
 const char* pch_last_error(void);
 

@@ -129,6 +129,7 @@ struct DevMesh {
   const uint8_t* flags;
   const int32_t* coff;
   const int32_t* corner;
+  const pch::Corner* crec;
 };
 
 struct DevState {
@@ -174,6 +175,13 @@ __device__ __forceinline__ u64 ordkey(double x) {
 __device__ __forceinline__ double from_ordkey(u64 k) {
   return (k >> 63) ? from_bits(k & 0x7fffffffffffffffull) : from_bits(~k);
 }
+// Reads of geod_dist, angle_split and the fan keys, which are updated with
+// device-scope atomics (performed in L2): agent-scope loads bypass stale
+// vector-L1 lines, so phases of one workgroup see each other's updates
+// without invalidating the whole L1.
+__device__ __forceinline__ u64 lda(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int he_next(int j) { return j - j % 3 + (j % 3 + 1) % 3; }
 __device__ __forceinline__ int he_prev(int j) { return j - j % 3 + (j % 3 + 2) % 3; }
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -201,6 +209,37 @@ __device__ __forceinline__ u64 wave_reserve(u64* ctr, u32 n, u32* total_out = nu
   base = shfl64(base, kWave - 1);
   if (total_out) *total_out = total;
   return base + (incl - n);
+}
+
+// Three reservations at once: the last lane issues the three atomics back to
+// back so their round trips overlap.
+__device__ __forceinline__ void wave_reserve3(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64& s0, u64& s1,
+                                              u64& s2, u32& t0, u32& t1, u32& t2) {
+  const int lane = lane_id();
+  u32 i0 = n0, i1 = n1, i2 = n2;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const u32 y0 = __shfl_up(i0, o, kWave);
+    const u32 y1 = __shfl_up(i1, o, kWave);
+    const u32 y2 = __shfl_up(i2, o, kWave);
+    if (lane >= o) {
+      i0 += y0;
+      i1 += y1;
+      i2 += y2;
+    }
+  }
+  t0 = __shfl(i0, kWave - 1, kWave);
+  t1 = __shfl(i1, kWave - 1, kWave);
+  t2 = __shfl(i2, kWave - 1, kWave);
+  u64 b0 = 0, b1 = 0, b2 = 0;
+  if (lane == kWave - 1) {
+    if (t0) b0 = atomicAdd(c0, (u64)t0);
+    if (t1) b1 = atomicAdd(c1, (u64)t1);
+    if (t2) b2 = atomicAdd(c2, (u64)t2);
+  }
+  s0 = shfl64(b0, kWave - 1) + (i0 - n0);
+  s1 = shfl64(b1, kWave - 1) + (i1 - n1);
+  s2 = shfl64(b2, kWave - 1) + (i2 - n2);
 }
 
 __device__ __forceinline__ u32 wave_sum(u32 x) {
@@ -359,15 +398,15 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
   o.nev = 0;
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
-  const int j = m.corner[q];
-  const double al = m.alpha[j];
+  const pch::Corner cr = m.crec[q];
+  const double al = cr.alpha;
   double t0, t1;
   if (full) {
     t0 = 0.0;
     t1 = al;
   } else if (!(m.flags[v] & pch::VF_BOUNDARY)) {
     const double Th = m.theta[v];
-    double rel = m.phi[j] - th;
+    double rel = cr.phi - th;
     if (!isfinite(rel)) return;
     while (rel < 0.0) rel += Th;
     while (rel >= Th) rel -= Th;
@@ -377,7 +416,7 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
     t1 = hi < al ? hi : al;
     if (!(t0 <= t1)) return;
   } else {
-    const double rel = m.phi[j] - th;
+    const double rel = cr.phi - th;
     const double hiA = -kPi - rel;
     const double loB = kPi - rel;
     if (hiA >= 0.0) {
@@ -390,35 +429,33 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
       return;
     }
   }
-  const int n = he_next(j), pj = he_prev(j);
-  const pch::HalfEdge hj = m.he[j];
-  const pch::HalfEdge hn = m.he[n];
-  const int va = hn.v0;  // end of j
-  const int vb = hn.v1;  // start of prev(j)
+  const int va = cr.a;
+  const int vb = cr.b;
+  const double ga = from_bits(lda(&g[va])), gb = from_bits(lda(&g[vb]));
   if (t0 <= 0.0) {
-    const double da = d + hj.L;
-    if (da < from_bits(g[va]) * kEv) {
+    const double da = d + cr.l_va;
+    if (da < ga * kEv) {
       o.ev_v[o.nev] = va;
       o.ev_d[o.nev] = da;
-      o.ev_th[o.nev] = m.phi[n] + m.alpha[n];
+      o.ev_th[o.nev] = cr.th_a;
       o.nev++;
     }
   }
-  if (t1 >= al && m.twin[pj] < 0) {
-    const double db = d + hj.l02;
-    if (db < from_bits(g[vb]) * kEv) {
+  if (t1 >= al && cr.last) {
+    const double db = d + cr.l_vb;
+    if (db < gb * kEv) {
       o.ev_v[o.nev] = vb;
       o.ev_d[o.nev] = db;
-      o.ev_th[o.nev] = m.phi[pj];
+      o.ev_th[o.nev] = cr.th_b;
       o.nev++;
     }
   }
-  const int tw = m.twin[n];
+  const int tw = cr.tw;
   if (tw < 0) {
     notwin++;
     return;
   }
-  const double Ln = hn.L, x2n = hn.x2, y2n = hn.y2;
+  const double Ln = cr.L, x2n = cr.x2, y2n = cr.y2;
   const double ipx = Ln - x2n, ipy = -y2n;
   double c0, c1;
   if (t1 >= al) {
@@ -439,8 +476,7 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
   }
   if (c0 < 0.0) c0 = 0.0;
   if (c1 > Ln) c1 = Ln;
-  const int r = child_filter(c0, c1, ipx, ipy, d, Ln, from_bits(g[vb]), from_bits(g[va]), false, false, 0.0, 0.0,
-                             a.eps, a.ich_on);
+  const int r = child_filter(c0, c1, ipx, ipy, d, Ln, gb, ga, false, false, 0.0, 0.0, a.eps, a.ich_on);
   if (r == 1) {
     tiny++;
     return;
@@ -750,9 +786,8 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
 // Split the pool: stale windows (sigma > geod_dist of their pseudo-source) are
 // dropped, selected windows go to the selection buffer, the rest to the other
 // pool buffer. Appends are reserved per wavefront.
-__global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
+__device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  if (!c->active) return;
   const u64 N = min(c->npool[p], (u64)a.cap);
   const Pool P = a.pool[p];
   const Pool Q = a.pool[1 - p];
@@ -764,8 +799,7 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
   const double cv = c->cutval;
   u32 stale_n = 0;
   u64 kmn = kAllOnes, kmx = 0;
-  const u64 stride = (u64)gridDim.x * kBlock;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < N; i += stride) {
+  for (u64 i = t0; i - lane_id() < N; i += stride) {
     const bool valid = i < N;
     bool sel = false, keep = false;
     double b0 = 0, b1 = 0, px = 0, py = 0, sg = 0, key = 0;
@@ -774,7 +808,7 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
       sg = P.sg[i];
       src = P.src[i];
       key = P.key[i];
-      const bool stale = sg > from_bits(a.s.g[src]);
+      const bool stale = sg > from_bits(lda(&a.s.g[src]));
       if (stale) {
         stale_n++;
       } else {
@@ -787,8 +821,9 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
         e = P.e[i];
       }
     }
-    const u64 js = wave_reserve(&c->nsel, sel ? 1u : 0u);
-    const u64 jk = wave_reserve(&c->npool[1 - p], keep ? 1u : 0u);
+    u64 js, jk, jz;
+    u32 ts, tk, tz;
+    wave_reserve3(&c->nsel, sel ? 1u : 0u, &c->npool[1 - p], keep ? 1u : 0u, &c->nsel, 0u, js, jk, jz, ts, tk, tz);
     if (sel) {
       if (js < (u64)a.cap)
         store_window(S, js, b0, b1, px, py, sg, key, e, src);
@@ -816,22 +851,25 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
+  if (!a.ctl->active) return;
+  ph_partition(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+}
+
 // Algorithm 2 for every selected window, against the round-start geod_dist
 // and angle_split (delayed update, Remark 3).
-__global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
+__device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  if (!c->active) return;
   const u64 N = min(c->nsel, (u64)a.cap);
   const Pool S = a.sel;
   const Pool Q = a.pool[1 - p];
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
-  if (blockIdx.x == 0 && threadIdx.x == 0) c->cnt[C_SEL] = c->nsel;
+  if (t0 == 0) c->cnt[C_SEL] = c->nsel;
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
   u64 kmn = kAllOnes, kmx = 0;
-  const u64 stride = (u64)gridDim.x * kBlock;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < N; i += stride) {
+  for (u64 i = t0; i - lane_id() < N; i += stride) {
     // outputs of this lane
     int nk = 0;
     double kb0[2], kb1[2], kpx[2], kpy[2], kkey[2];
@@ -851,7 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
       const pch::HalfEdge h = m.he[e];
       const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
       const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
-      const double g0 = from_bits(g[v0]), g1 = from_bits(g[v1]), g2 = from_bits(g[v2]);
+      const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
       const double tol = kTau * L;
       const double den = y2 - py;
       const double t = (-py) / den;
@@ -898,8 +936,8 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
         if (!a.ch_on) {
           doL = doR = true;
         } else {
-          const double Ds = from_bits(a.s.AD[e]);
-          const double Xs = from_ordkey(a.s.AX[e]);
+          const double Ds = from_bits(lda(&a.s.AD[e]));
+          const double Xs = from_ordkey(lda(&a.s.AX[e]));
           if (d2 < Ds) {
             has_aev = true;
             aD = d2;
@@ -1012,9 +1050,9 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
     // append children, distance events and angle events (one reservation per
     // wavefront each)
     u32 tk, td, ta;
-    const u64 jk = wave_reserve(&c->npool[1 - p], (u32)nk, &tk);
-    const u64 jd = wave_reserve(&c->ndev[p], (u32)nd, &td);
-    const u64 ja = wave_reserve(&c->naev, has_aev ? 1u : 0u, &ta);
+    u64 jk, jd, ja;
+    wave_reserve3(&c->npool[1 - p], (u32)nk, &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, jk, jd, ja, tk, td,
+                  ta);
     for (int q = 0; q < nk; ++q) {
       const u64 j = jk + q;
       if (j < (u64)a.cap) {
@@ -1067,59 +1105,66 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
+  if (!a.ctl->active) return;
+  ph_propagate(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+}
+
 // Algorithm 4, first pass: geod_dist and the angle_split distance take the
 // minimum over this round's events (keys: vertex, oriented edge).
-__global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
+__device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  if (!c->active) return;
   const u64 nd = min(c->ndev[p], (u64)a.ecap);
   const u64 na = min(c->naev, (u64)a.acap);
-  const u64 stride = (u64)gridDim.x * kBlock;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride)
+  for (u64 i = t0; i < nd; i += stride)
     atomicMin(&a.s.g[a.ev[p].v[i]], bits(a.ev[p].d[i]));
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride)
+  for (u64 i = t0; i < na; i += stride)
     atomicMin(&a.s.AD[a.aev.e[i]], bits(a.aev.D[i]));
+}
+
+__global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
+  if (!a.ctl->active) return;
+  ph_events1(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
 // Second pass: corners whose distance changed forget their old crossing; each
 // improved pseudo-source vertex records the smallest incoming angle among the
 // events that reached its new distance.
-__global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
+__device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  if (!c->active) return;
   const u64 nd = min(c->ndev[p], (u64)a.ecap);
   const u64 na = min(c->naev, (u64)a.acap);
-  const u64 stride = (u64)gridDim.x * kBlock;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride) {
+  for (u64 i = t0; i < na; i += stride) {
     const int e = a.aev.e[i];
-    if (bits(a.aev.D[i]) == a.s.AD[e]) a.s.AX[e] = kAllOnes;
+    if (bits(a.aev.D[i]) == lda(&a.s.AD[e])) a.s.AX[e] = kAllOnes;
   }
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < nd; i += stride) {
+  for (u64 i = t0; i < nd; i += stride) {
     const int v = a.ev[p].v[i];
-    if (bits(a.ev[p].d[i]) == a.s.g[v] && (a.m.flags[v] & pch::VF_PSEUDO))
+    if (bits(a.ev[p].d[i]) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO))
       atomicMin(&a.s.fanth[v], ordkey(a.ev[p].th[i]));
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
+  if (!a.ctl->active) return;
+  ph_events2(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+}
+
 // Third pass: the winning crossing per corner; one fan per improved
 // pseudo-source vertex, windows into the next pool, deferred endpoint events
-// into the next round's event buffer. The last block to finish sets up the
-// next round.
-__global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
-  __shared__ int is_last;
+// into the next round's event buffer.
+__device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  if (!c->active) return;
   const u64 nd = min(c->ndev[p], (u64)a.ecap);
   const u64 na = min(c->naev, (u64)a.acap);
-  const u64 stride = (u64)gridDim.x * kBlock;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < na; i += stride) {
+  for (u64 i = t0; i < na; i += stride) {
     const int e = a.aev.e[i];
-    if (bits(a.aev.D[i]) == a.s.AD[e]) atomicMin(&a.s.AX[e], ordkey(a.aev.X[i]));
+    if (bits(a.aev.D[i]) == lda(&a.s.AD[e])) atomicMin(&a.s.AX[e], ordkey(a.aev.X[i]));
   }
   const u32 stamp = (u32)c->round;
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
-  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i - lane_id() < nd; i += stride) {
+  for (u64 i = t0; i - lane_id() < nd; i += stride) {
     bool has = false;
     int v = 0;
     double d = 0.0, th = 0.0;
@@ -1127,7 +1172,7 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
       v = a.ev[p].v[i];
       d = a.ev[p].d[i];
       th = a.ev[p].th[i];
-      if (bits(d) == a.s.g[v] && (a.m.flags[v] & pch::VF_PSEUDO) && ordkey(th) == a.s.fanth[v] &&
+      if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO) && ordkey(th) == lda(&a.s.fanth[v]) &&
           atomicMax(&a.s.claim[v], stamp) < stamp) {
         a.s.fanth[v] = kAllOnes;
         has = true;
@@ -1152,6 +1197,14 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
     if (fans) atomicAdd(&c->cnt[C_FANS], (u64)fans);
     if (notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)notwin);
   }
+}
+
+// The last block to finish sets up the next round.
+__global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
+  __shared__ int is_last;
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  ph_events3(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
@@ -1162,6 +1215,187 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
     round_begin(a, 1 - p);
   }
 }
+
+
+// ---------------------------------------------------------------------------
+// batched fields: one workgroup runs every round of one field at a time
+// ---------------------------------------------------------------------------
+
+struct BatchDev {
+  const DevMesh* meshes;      // [n_meshes]
+  const int64_t* mesh_nv;     // [n_meshes]
+  const int64_t* mesh_nh;     // [n_meshes]
+  const double* mesh_delta0;  // [n_meshes] first adaptive step
+  const int32_t* field_mesh;  // [n_fields]
+  const int32_t* field_src;   // [n_fields]
+  const int64_t* field_off;   // [n_fields] offset of the field in out
+  const int32_t* order;       // [n_fields] processing order (largest first)
+  int32_t n_fields;           // fields taken from the queue
+  double* out;                // concatenated distance fields
+  int64_t* fstat;             // [n_fields][kFieldStat]
+  u64* queue;                 // next position in order
+  // per-team buffers (team t uses slot t)
+  double *pb0, *pb1, *ppx, *ppy, *psg, *pkey;  // [n_teams][3][cap]: pool 0, pool 1, selection
+  int32_t *pe, *psrc;
+  int32_t* ev_v;  // [n_teams][2][ecap]
+  double *ev_d, *ev_th;
+  int32_t* ae_e;  // [n_teams][acap]
+  double *ae_D, *ae_X;
+  u64 *g, *fanth;  // [n_teams][max_nv]
+  u32* claim;      // [n_teams][max_nv]
+  u64 *AD, *AX;    // [n_teams][max_nh]
+  int64_t cap, ecap, acap, max_nv, max_nh;
+  int64_t k;
+  double eps;
+  int32_t ch_on, ich_on, full_fan;
+  int64_t max_rounds;
+};
+
+constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak pool, stale, reserved
+
+// Barrier between the phases of one workgroup's field. Values updated with
+// device-scope atomics are read with agent-scope loads (lda), so the barrier
+// only has to order this workgroup's plain stores before the next phase.
+__device__ __forceinline__ void team_sync() {
+  __threadfence();
+  __syncthreads();
+}
+
+__device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
+  const int64_t o = ((int64_t)t * 3 + b) * B.cap;
+  return Pool{B.pb0 + o, B.pb1 + o, B.ppx + o, B.ppy + o, B.psg + o, B.pkey + o, B.pe + o, B.psrc + o};
+}
+
+// Persistent workgroups: each takes the next field from the queue and runs
+// Algorithm 1 on it alone, the phases separated by workgroup barriers and
+// the round counters in LDS. Fields never wait for each other; a field
+// that outgrows the team's pool is flagged for a rerun by the host.
+// Out-of-line phases for the persistent kernel: each gets its own register
+// allocation instead of the union of all phases in one function.
+__device__ __noinline__ void nl_partition(const RoundArgs& a, int p, u64 t0, u64 s) { ph_partition(a, p, t0, s); }
+__device__ __noinline__ void nl_propagate(const RoundArgs& a, int p, u64 t0, u64 s) { ph_propagate(a, p, t0, s); }
+__device__ __noinline__ void nl_events1(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events1(a, p, t0, s); }
+__device__ __noinline__ void nl_events2(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events2(a, p, t0, s); }
+__device__ __noinline__ void nl_events3(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events3(a, p, t0, s); }
+__device__ __noinline__ void nl_begin(const RoundArgs& a, int p) { round_begin(a, p); }
+__device__ __noinline__ void nl_init_fan(const RoundArgs& a, int v, Ctl* ctl) {
+  u64 kmn = kAllOnes, kmx = 0;
+  u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
+  wave_fans(a, lane_id() == 0, v, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
+  if (lane_id() == 0) {
+    if (kmn != kAllOnes) atomicMin(&ctl->kmin[0], kmn);
+    if (kmx != 0) atomicMax(&ctl->kmax[0], kmx);
+  }
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
+  __shared__ Ctl ctl;
+  __shared__ RoundArgs sa;
+  __shared__ int cur;
+  const int t = blockIdx.x;
+  const u64 t0 = threadIdx.x, stride = BS;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const u64 q = atomicAdd(B.queue, 1ull);
+      cur = q < (u64)B.n_fields ? B.order[q] : -1;
+    }
+    __syncthreads();
+    const int f = cur;
+    if (f < 0) break;
+    const int mi = B.field_mesh[f];
+    const int64_t nv = B.mesh_nv[mi], nh = B.mesh_nh[mi];
+    if (threadIdx.x == 0) {
+      RoundArgs a;
+      a.m = B.meshes[mi];
+      a.s = DevState{B.g + t * B.max_nv, B.AD + t * B.max_nh, B.AX + t * B.max_nh, B.fanth + t * B.max_nv,
+                     B.claim + t * B.max_nv};
+      a.pool[0] = slot_pool(B, t, 0);
+      a.pool[1] = slot_pool(B, t, 1);
+      a.sel = slot_pool(B, t, 2);
+      for (int i = 0; i < 2; ++i) {
+        const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
+        a.ev[i] = DistEv{B.ev_v + o, B.ev_d + o, B.ev_th + o};
+      }
+      const int64_t oa = (int64_t)t * B.acap;
+      a.aev = AngEv{B.ae_e + oa, B.ae_D + oa, B.ae_X + oa};
+      a.ctl = &ctl;
+      a.hist = nullptr;
+      a.log = nullptr;
+      a.max_log = 0;
+      a.cap = B.cap;
+      a.ecap = B.ecap;
+      a.acap = B.acap;
+      a.k = B.k;
+      a.mode = PCH_SELECT_DELTA;
+      a.eps = B.eps;
+      a.ch_on = B.ch_on;
+      a.ich_on = B.ich_on;
+      a.full_fan = B.full_fan;
+      a.table = nullptr;
+      a.n_table = 0;
+      sa = a;
+      // zero the control block
+      u64* cw = (u64*)&ctl;
+      for (size_t w = 0; w < sizeof(Ctl) / sizeof(u64); ++w) cw[w] = 0;
+      ctl.kmin[0] = ctl.kmin[1] = kAllOnes;
+      ctl.delta = B.mesh_delta0[mi];
+    }
+    team_sync();
+    const RoundArgs& a = sa;
+    for (u64 i = t0; i < (u64)nv; i += stride) {
+      a.s.g[i] = i == (u64)B.field_src[f] ? 0ull : 0x7ff0000000000000ull;
+      a.s.fanth[i] = kAllOnes;
+      a.s.claim[i] = 0u;
+    }
+    for (u64 i = t0; i < (u64)nh; i += stride) {
+      a.s.AD[i] = 0x7ff0000000000000ull;
+      a.s.AX[i] = kAllOnes;
+    }
+    team_sync();
+    if (threadIdx.x < (u32)kWave) nl_init_fan(a, B.field_src[f], &ctl);
+    team_sync();
+    if (threadIdx.x == 0) nl_begin(a, 0);
+    team_sync();
+    int p = 0;
+    while (!ctl.done) {
+      nl_partition(a, p, t0, stride);
+      team_sync();
+      nl_propagate(a, p, t0, stride);
+      team_sync();
+      nl_events1(a, p, t0, stride);
+      team_sync();
+      nl_events2(a, p, t0, stride);
+      team_sync();
+      nl_events3(a, p, t0, stride);
+      team_sync();
+      if (threadIdx.x == 0) {
+        nl_begin(a, 1 - p);
+        if ((int64_t)ctl.round > B.max_rounds) ctl.done = 1;
+      }
+      team_sync();
+      p ^= 1;
+    }
+    const int64_t off = B.field_off[f];
+    for (u64 i = t0; i < (u64)nv; i += stride) B.out[off + i] = from_bits(lda(&a.s.g[i]));
+    if (threadIdx.x == 0) {
+      int64_t* st = B.fstat + (int64_t)f * kFieldStat;
+      st[0] = ctl.overflow ? 1 : ((int64_t)ctl.round > B.max_rounds ? 2 : 0);
+      st[1] = (int64_t)ctl.round;
+      st[2] = (int64_t)ctl.tot[C_SEL];
+      st[3] = (int64_t)(ctl.tot[C_KIDS] + ctl.tot[C_FANWIN]);
+      st[4] = (int64_t)ctl.tot[C_FANS];
+      st[5] = (int64_t)ctl.peak;
+      st[6] = (int64_t)ctl.tot[C_STALE];
+      st[7] = 0;
+    }
+    team_sync();
+  }
+}
+
+__global__ void k_reset_queue(u64* q) { *q = 0ull; }
 
 }  // namespace
 
@@ -1176,6 +1410,7 @@ struct pch_mesh_s {
   pch::HalfEdge* he = nullptr;
   double *phi = nullptr, *alpha = nullptr, *theta = nullptr;
   int32_t *twin = nullptr, *hv = nullptr, *coff = nullptr, *corner = nullptr;
+  pch::Corner* crec = nullptr;
   uint8_t* flags = nullptr;
   // state (sized with the mesh)
   u64 *g = nullptr, *AD = nullptr, *AX = nullptr, *fanth = nullptr;
@@ -1275,6 +1510,7 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   HIP_TRY(dalloc(&M->twin, H.nh));
   HIP_TRY(dalloc(&M->hv, H.nh));
   HIP_TRY(dalloc(&M->corner, H.nh));
+  HIP_TRY(dalloc(&M->crec, H.nh));
   HIP_TRY(dalloc(&M->theta, H.nv));
   HIP_TRY(dalloc(&M->flags, H.nv));
   HIP_TRY(dalloc(&M->coff, H.nv + 1));
@@ -1291,6 +1527,7 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(M->twin, H.twin.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->hv, H.hv.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->corner, H.corner.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->crec, H.crec.data(), sizeof(pch::Corner) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->theta, H.theta.data(), sizeof(double) * H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->flags, H.flags.data(), H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->coff, H.coff.data(), sizeof(int32_t) * (H.nv + 1), hipMemcpyHostToDevice, st));
@@ -1307,6 +1544,7 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->twin);
   (void)hipFree(M->hv);
   (void)hipFree(M->corner);
+  (void)hipFree(M->crec);
   (void)hipFree(M->theta);
   (void)hipFree(M->flags);
   (void)hipFree(M->coff);
@@ -1337,7 +1575,7 @@ pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
 
 RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   RoundArgs a;
-  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner};
+  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
   a.s = DevState{M->g, M->AD, M->AX, M->fanth, M->claim};
   a.pool[0] = M->pool[0];
   a.pool[1] = M->pool[1];
@@ -1658,6 +1896,352 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     stats->propagate_launches = prop_n;
     stats->delta0 = delta0;
   }
+  return PCH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched fields (host)
+// ---------------------------------------------------------------------------
+
+struct pch_batch_s {
+  std::vector<pch_mesh> meshes;
+  std::vector<int32_t> fmesh, fsrc;
+  std::vector<int64_t> off;  // n_fields + 1
+  std::vector<int32_t> order;
+  std::vector<double> delta0;
+  pch_batch_options o;
+  int device = 0;
+  int n_cu = 0;
+  int n_teams = 0;
+  int64_t max_nv = 0, max_nh = 0;
+  BatchDev B{};
+  // device tables
+  DevMesh* d_meshes = nullptr;
+  int64_t *d_nv = nullptr, *d_nh = nullptr, *d_off = nullptr, *d_fstat = nullptr;
+  double* d_delta0 = nullptr;
+  int32_t *d_fmesh = nullptr, *d_fsrc = nullptr, *d_order = nullptr;
+  u64* d_queue = nullptr;
+  bool slots = false;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* g_out = nullptr;
+  std::vector<int64_t> fstat;
+};
+
+namespace {
+
+void free_slots(pch_batch_s* b) {
+  if (!b->slots) return;
+  BatchDev& B = b->B;
+  for (void* p : {(void*)B.pb0, (void*)B.pb1, (void*)B.ppx, (void*)B.ppy, (void*)B.psg, (void*)B.pkey, (void*)B.pe,
+                  (void*)B.psrc, (void*)B.ev_v, (void*)B.ev_d, (void*)B.ev_th, (void*)B.ae_e, (void*)B.ae_D,
+                  (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.AD, (void*)B.AX})
+    (void)hipFree(p);
+  b->slots = false;
+}
+
+void drop_graph(pch_batch_s* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->g_out = nullptr;
+}
+
+// (Re)allocates the per-workgroup buffers for the current options.
+pch_status alloc_slots(pch_batch_s* b) {
+  free_slots(b);
+  drop_graph(b);
+  BatchDev& B = b->B;
+  const int nf = (int)b->fmesh.size();
+  b->n_teams = std::max(1, std::min(nf, b->o.teams_per_cu * b->n_cu));
+  int64_t cap = b->o.pool_capacity;
+  if (cap <= 0) cap = std::min<int64_t>(std::max<int64_t>(32768, b->max_nh / 12), 1 << 20);
+  B.cap = cap;
+  B.ecap = cap;
+  B.acap = std::max<int64_t>(cap / 2, 1024);
+  const int64_t T = b->n_teams;
+  const int64_t np = T * 3 * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
+  HIP_TRY(dalloc(&B.pb0, np));
+  HIP_TRY(dalloc(&B.pb1, np));
+  HIP_TRY(dalloc(&B.ppx, np));
+  HIP_TRY(dalloc(&B.ppy, np));
+  HIP_TRY(dalloc(&B.psg, np));
+  HIP_TRY(dalloc(&B.pkey, np));
+  HIP_TRY(dalloc(&B.pe, np));
+  HIP_TRY(dalloc(&B.psrc, np));
+  HIP_TRY(dalloc(&B.ev_v, ne));
+  HIP_TRY(dalloc(&B.ev_d, ne));
+  HIP_TRY(dalloc(&B.ev_th, ne));
+  HIP_TRY(dalloc(&B.ae_e, na));
+  HIP_TRY(dalloc(&B.ae_D, na));
+  HIP_TRY(dalloc(&B.ae_X, na));
+  HIP_TRY(dalloc(&B.g, T * b->max_nv));
+  HIP_TRY(dalloc(&B.fanth, T * b->max_nv));
+  HIP_TRY(dalloc(&B.claim, T * b->max_nv));
+  HIP_TRY(dalloc(&B.AD, T * b->max_nh));
+  HIP_TRY(dalloc(&B.AX, T * b->max_nh));
+  b->slots = true;
+  B.max_nv = b->max_nv;
+  B.max_nh = b->max_nh;
+  B.k = b->o.k;
+  B.eps = b->o.eps_tiny;
+  B.ch_on = (b->o.filters & 1) != 0;
+  B.ich_on = (b->o.filters & 2) != 0;
+  B.full_fan = (b->o.filters & 4) != 0;
+  return PCH_OK;
+}
+
+void enqueue_batch(pch_batch_s* b, hipStream_t st) {
+  k_reset_queue<<<1, 1, 0, st>>>(b->d_queue);
+  if (b->o.team_threads == 1024)
+    k_batch<1024><<<b->n_teams, 1024, 0, st>>>(b->B);
+  else
+    k_batch<kBlock><<<b->n_teams, kBlock, 0, st>>>(b->B);
+}
+
+// One run of the batch into out (graph replay when enabled), then reruns of
+// the fields that did not finish in a workgroup.
+pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  HIP_TRY(hipStreamSynchronize(user));
+  b->B.out = out;
+  const int nf = (int)b->fmesh.size();
+  if (b->o.use_graph) {
+    if (!b->gexec || b->g_out != out) {
+      drop_graph(b);
+      hipGraph_t graph;
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      enqueue_batch(b, b->stream);
+      HIP_TRY(hipStreamEndCapture(b->stream, &graph));
+      hipError_t e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return set_err(PCH_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      b->g_out = out;
+    }
+    HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+  } else {
+    enqueue_batch(b, b->stream);
+    HIP_TRY(hipGetLastError());
+  }
+  b->fstat.assign((size_t)nf * kFieldStat, 0);
+  HIP_TRY(hipMemcpyAsync(b->fstat.data(), b->d_fstat, sizeof(int64_t) * nf * kFieldStat, hipMemcpyDeviceToHost,
+                         b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int64_t reruns = 0;
+  for (int f = 0; f < nf; ++f) {
+    int64_t* fs = &b->fstat[(size_t)f * kFieldStat];
+    if (fs[0] == 0) continue;
+    pch_options o;
+    pch_options_default(&o);
+    o.select_mode = PCH_SELECT_DELTA;
+    o.k = b->o.k;
+    o.delta0 = b->delta0[b->fmesh[f]];
+    o.filters = b->o.filters;
+    o.eps_tiny = b->o.eps_tiny;
+    pch_stats s1;
+    pch_status rc = pch_geodesic(b->meshes[b->fmesh[f]], &b->fsrc[f], 1, out + b->off[f], b->stream, &o, &s1);
+    if (rc != PCH_OK) return rc;
+    fs[1] = s1.rounds;
+    fs[2] = s1.processed;
+    fs[3] = s1.created;
+    fs[4] = s1.fans;
+    fs[5] = s1.peak_pool;
+    fs[6] = s1.stale;
+    reruns++;
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->fields = nf;
+    stats->reruns = reruns;
+    stats->teams = b->n_teams;
+    stats->k = b->o.k;
+    for (int f = 0; f < nf; ++f) {
+      const int64_t* fs = &b->fstat[(size_t)f * kFieldStat];
+      stats->max_rounds = std::max(stats->max_rounds, fs[1]);
+      stats->processed += fs[2];
+      stats->created += fs[3];
+    }
+    stats->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return PCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pch_batch_options_default(pch_batch_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->k = 1024;
+  o->teams_per_cu = 2;
+  o->filters = 3;
+  o->eps_tiny = 0.0;
+  o->pool_capacity = 0;
+  o->use_graph = 1;
+  o->team_threads = 256;
+}
+
+void pch_batch_destroy(pch_batch b) {
+  if (!b) return;
+  drop_graph(b);
+  free_slots(b);
+  for (void* p : {(void*)b->d_meshes, (void*)b->d_nv, (void*)b->d_nh, (void*)b->d_off, (void*)b->d_fstat,
+                  (void*)b->d_delta0, (void*)b->d_fmesh, (void*)b->d_fsrc, (void*)b->d_order, (void*)b->d_queue})
+    (void)hipFree(p);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int32_t* field_mesh,
+                            const int32_t* field_source, int32_t n_fields, const pch_batch_options* opts,
+                            pch_batch* out) {
+  if (!meshes || !field_mesh || !field_source || !out) return set_err(PCH_EINVAL, "null pointer argument");
+  *out = nullptr;
+  if (n_meshes < 1 || n_fields < 1) return set_err(PCH_EINVAL, "need at least one mesh and one field");
+  pch_batch_options o;
+  pch_batch_options_default(&o);
+  if (opts) o = *opts;
+  if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 1024))
+    return set_err(PCH_EINVAL, "bad batch option");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  for (int i = 0; i < n_meshes; ++i) {
+    if (!meshes[i]) return set_err(PCH_EINVAL, "null mesh in batch");
+    if (meshes[i]->device != dev) return set_err(PCH_EINVAL, "mesh was created on another device");
+  }
+  for (int f = 0; f < n_fields; ++f) {
+    if (field_mesh[f] < 0 || field_mesh[f] >= n_meshes) return set_err(PCH_EINVAL, "field mesh index out of range");
+    if (field_source[f] < 0 || field_source[f] >= meshes[field_mesh[f]]->host.nv)
+      return set_err(PCH_EINVAL, "field source vertex out of range");
+  }
+  pch_batch_s* b = new (std::nothrow) pch_batch_s();
+  if (!b) return set_err(PCH_ENOMEM, "host allocation failed");
+  struct Guard {
+    pch_batch_s*& b;
+    ~Guard() {
+      if (b) pch_batch_destroy(b);
+    }
+  } guard{b};
+  b->meshes.assign(meshes, meshes + n_meshes);
+  b->fmesh.assign(field_mesh, field_mesh + n_fields);
+  b->fsrc.assign(field_source, field_source + n_fields);
+  b->o = o;
+  b->device = dev;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  b->n_cu = prop.multiProcessorCount;
+  HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  std::vector<DevMesh> dm(n_meshes);
+  std::vector<int64_t> nv(n_meshes), nh(n_meshes);
+  b->delta0.resize(n_meshes);
+  for (int i = 0; i < n_meshes; ++i) {
+    pch_mesh_s* M = meshes[i];
+    dm[i] = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+    nv[i] = M->host.nv;
+    nh[i] = M->host.nh;
+    double sum = 0.0;
+    for (int64_t j = 0; j < M->host.nh; ++j) sum += M->host.he[j].L;
+    b->delta0[i] = 2.0 * (sum / (double)M->host.nh);
+    b->max_nv = std::max(b->max_nv, nv[i]);
+    b->max_nh = std::max(b->max_nh, nh[i]);
+  }
+  b->off.resize(n_fields + 1);
+  b->off[0] = 0;
+  for (int f = 0; f < n_fields; ++f) b->off[f + 1] = b->off[f] + nv[field_mesh[f]];
+  // largest meshes first (longest processing time first)
+  b->order.resize(n_fields);
+  for (int f = 0; f < n_fields; ++f) b->order[f] = f;
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return meshes[field_mesh[x]]->host.nf > meshes[field_mesh[y]]->host.nf; });
+  HIP_TRY(dalloc(&b->d_meshes, n_meshes));
+  HIP_TRY(dalloc(&b->d_nv, n_meshes));
+  HIP_TRY(dalloc(&b->d_nh, n_meshes));
+  HIP_TRY(dalloc(&b->d_delta0, n_meshes));
+  HIP_TRY(dalloc(&b->d_fmesh, n_fields));
+  HIP_TRY(dalloc(&b->d_fsrc, n_fields));
+  HIP_TRY(dalloc(&b->d_off, n_fields));
+  HIP_TRY(dalloc(&b->d_order, n_fields));
+  HIP_TRY(dalloc(&b->d_fstat, (int64_t)n_fields * kFieldStat));
+  HIP_TRY(dalloc(&b->d_queue, 1));
+  HIP_TRY(hipMemcpy(b->d_meshes, dm.data(), sizeof(DevMesh) * n_meshes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_nv, nv.data(), sizeof(int64_t) * n_meshes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_nh, nh.data(), sizeof(int64_t) * n_meshes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_delta0, b->delta0.data(), sizeof(double) * n_meshes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_fmesh, field_mesh, sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_fsrc, field_source, sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * n_fields, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
+  BatchDev& B = b->B;
+  B.meshes = b->d_meshes;
+  B.mesh_nv = b->d_nv;
+  B.mesh_nh = b->d_nh;
+  B.mesh_delta0 = b->d_delta0;
+  B.field_mesh = b->d_fmesh;
+  B.field_src = b->d_fsrc;
+  B.field_off = b->d_off;
+  B.order = b->d_order;
+  B.n_fields = n_fields;
+  B.fstat = b->d_fstat;
+  B.queue = b->d_queue;
+  B.max_rounds = kMaxRounds;
+  pch_status s = alloc_slots(b);
+  if (s != PCH_OK) return s;
+  *out = b;
+  b = nullptr;  // owned by the caller now
+  return PCH_OK;
+}
+
+pch_status pch_batch_offsets(pch_batch b, int64_t* offsets) {
+  if (!b || !offsets) return set_err(PCH_EINVAL, "null pointer argument");
+  std::memcpy(offsets, b->off.data(), sizeof(int64_t) * b->off.size());
+  return PCH_OK;
+}
+
+pch_status pch_batch_run(pch_batch b, double* dist, void* hip_stream, pch_batch_stats* stats) {
+  if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != b->device) return set_err(PCH_EINVAL, "batch was created on another device");
+  return batch_run(b, dist, (hipStream_t)hip_stream, stats);
+}
+
+pch_status pch_batch_field_stats(pch_batch b, int64_t* out) {
+  if (!b || !out) return set_err(PCH_EINVAL, "null pointer argument");
+  if (b->fstat.empty()) return set_err(PCH_EINVAL, "batch has not run");
+  std::memcpy(out, b->fstat.data(), sizeof(int64_t) * b->fstat.size());
+  return PCH_OK;
+}
+
+pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen) {
+  if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
+  const int64_t ks[] = {2048, 4096, 8192, 16384};
+  const int shapes[][2] = {{256, 2}, {256, 4}, {1024, 1}};  // team threads, teams per CU
+  pch_batch_options best = b->o;
+  double best_ms = INFINITY;
+  for (const auto& sh : shapes) {
+    for (int64_t k : ks) {
+      b->o.k = k;
+      b->o.team_threads = sh[0];
+      b->o.teams_per_cu = sh[1];
+      pch_status s = alloc_slots(b);
+      if (s != PCH_OK) return s;
+      pch_batch_stats st;
+      s = batch_run(b, dist, (hipStream_t)hip_stream, &st);
+      if (s != PCH_OK) return s;
+      if (st.ms_total < best_ms) {
+        best_ms = st.ms_total;
+        best = b->o;
+      }
+    }
+  }
+  b->o = best;
+  pch_status s = alloc_slots(b);
+  if (s != PCH_OK) return s;
+  if (chosen) *chosen = best;
   return PCH_OK;
 }
 

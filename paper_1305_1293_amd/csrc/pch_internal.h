@@ -24,6 +24,24 @@ struct alignas(64) HalfEdge {
 };
 static_assert(sizeof(HalfEdge) == 64, "half-edge record must be 64 bytes");
 
+// Everything a fan needs about one corner of a vertex v (outgoing half-edge
+// j = v -> a, face (v, a, b)), stored in CCW order per vertex so that a fan
+// reads one record per corner.
+struct alignas(32) Corner {
+  double alpha;   // corner angle at v
+  double phi;     // angular position of j around v
+  double l_va;    // |v a| = length of j
+  double l_vb;    // |v b| = length of prev(j)
+  double L;       // |a b| = length of next(j), the edge opposite v
+  double x2, y2;  // v in the frame of next(j) (a at 0, b at (L, 0))
+  double th_a;    // angular position at a of the direction a -> v
+  double th_b;    // angular position at b of the direction b -> v
+  int32_t a, b;
+  int32_t tw;     // twin(next(j)): the half-edge a fan window lives on, or -1
+  int32_t last;   // 1 when v -> b is a boundary edge (j is v's last corner)
+};
+static_assert(sizeof(Corner) == 96, "corner record must be 96 bytes");
+
 enum : uint8_t { VF_BOUNDARY = 1, VF_PSEUDO = 2 };
 
 struct HostMesh {
@@ -37,6 +55,7 @@ struct HostMesh {
   std::vector<uint8_t> flags;    // [nv] VF_*
   std::vector<int32_t> coff;     // [nv + 1] CSR offsets of the CCW corner lists
   std::vector<int32_t> corner;   // [nh] outgoing half-edges in CCW order
+  std::vector<Corner> crec;      // [nh] corner records in the same order
   int64_t n_boundary_he = 0, n_pseudo = 0;
 };
 

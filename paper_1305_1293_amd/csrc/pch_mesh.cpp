@@ -203,6 +203,27 @@ int build_host_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* 
     M.flags[v] = (uint8_t)((boundary ? VF_BOUNDARY : 0) | (pseudo ? VF_PSEUDO : 0));
     M.n_pseudo += pseudo;
   }
+  // corner records (after every phi is known)
+  M.crec.resize(nh);
+  for (int64_t q = 0; q < nh; ++q) {
+    const int32_t j = M.corner[q];
+    if (j < 0) continue;
+    const int32_t n = he_next(j), p = he_prev(j);
+    Corner& c = M.crec[q];
+    c.alpha = M.alpha[j];
+    c.phi = M.phi[j];
+    c.l_va = M.he[j].L;
+    c.l_vb = M.he[j].l02;
+    c.L = M.he[n].L;
+    c.x2 = M.he[n].x2;
+    c.y2 = M.he[n].y2;
+    c.th_a = M.phi[n] + M.alpha[n];
+    c.th_b = M.phi[p];
+    c.a = M.hv[n];
+    c.b = M.hv[p];
+    c.tw = M.twin[n];
+    c.last = M.twin[p] < 0 ? 1 : 0;
+  }
   return PCH_OK;
 }
 

@@ -79,9 +79,9 @@ def lib():
         L.pch_options_default.restype = None
         L.pch_geodesic.argtypes = [P, P, i32, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
         L.pch_round_log.argtypes = [P, P, i64, P]
+        _lib = L
         for n in EXPORTS:
             getattr(L, n)
-        _lib = L
     return _lib
 
 
@@ -186,3 +186,112 @@ def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_s
     _check(lib().pch_geodesic(mesh.handle, src.ctypes.data, src.size, out.data_ptr(), _stream_handle(stream),
                               ctypes.byref(o), ctypes.byref(st)))
     return (out, st.as_dict()) if return_stats else out
+
+
+# ---------------------------------------------------------------------------
+# batched fields
+# ---------------------------------------------------------------------------
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("teams_per_cu", ctypes.c_int32), ("filters", ctypes.c_int32),
+                ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64), ("use_graph", ctypes.c_int32),
+                ("team_threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ["fields", "reruns", "max_rounds", "processed", "created", "teams", "k"]] \
+        + [("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "reserved"]
+EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
+            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune"]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        P, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.pch_batch_options_default.argtypes = [ctypes.POINTER(BatchOptions)]
+        L.pch_batch_options_default.restype = None
+        L.pch_batch_create.argtypes = [P, i32, P, P, i32, ctypes.POINTER(BatchOptions), ctypes.POINTER(P)]
+        L.pch_batch_destroy.argtypes = [P]
+        L.pch_batch_destroy.restype = None
+        L.pch_batch_offsets.argtypes = [P, P]
+        L.pch_batch_run.argtypes = [P, P, P, ctypes.POINTER(BatchStats)]
+        L.pch_batch_field_stats.argtypes = [P, P]
+        L.pch_batch_tune.argtypes = [P, P, P, ctypes.POINTER(BatchOptions)]
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many single-source fields on several meshes in one persistent launch."""
+
+    def __init__(self, meshes: Sequence[Mesh], field_mesh, field_source, **opts):
+        L = _batch_lib()
+        self.meshes = list(meshes)  # keep the handles alive
+        self.field_mesh = np.ascontiguousarray(field_mesh, dtype=np.int32)
+        self.field_source = np.ascontiguousarray(field_source, dtype=np.int32)
+        if self.field_mesh.shape != self.field_source.shape:
+            raise ValueError("field_mesh and field_source differ in length")
+        o = BatchOptions()
+        L.pch_batch_options_default(ctypes.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown batch option {k}")
+            setattr(o, k, v)
+        handles = (ctypes.c_void_p * len(self.meshes))(*[m.handle for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(L.pch_batch_create(handles, len(self.meshes), self.field_mesh.ctypes.data,
+                                  self.field_source.ctypes.data, self.field_mesh.size, ctypes.byref(o),
+                                  ctypes.byref(h)))
+        self.handle = h
+        self.n_fields = int(self.field_mesh.size)
+        off = np.zeros(self.n_fields + 1, np.int64)
+        _check(L.pch_batch_offsets(self.handle, off.ctypes.data))
+        self.offsets = off
+
+    def empty_output(self):
+        import torch
+        return torch.empty(int(self.offsets[-1]), dtype=torch.float64, device="cuda")
+
+    def run(self, out=None, stream=None):
+        """All fields into one device tensor (field f at offsets[f]:offsets[f+1])."""
+        if out is None:
+            out = self.empty_output()
+        st = BatchStats()
+        _check(_batch_lib().pch_batch_run(self.handle, out.data_ptr(), _stream_handle(stream), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def field(self, out, f):
+        return out[int(self.offsets[f]):int(self.offsets[f + 1])]
+
+    def field_stats(self) -> np.ndarray:
+        fs = np.zeros((self.n_fields, len(BATCH_FIELD_STATS)), np.int64)
+        _check(_batch_lib().pch_batch_field_stats(self.handle, fs.ctypes.data))
+        return fs
+
+    def tune(self, out=None, stream=None) -> dict:
+        if out is None:
+            out = self.empty_output()
+        o = BatchOptions()
+        _check(_batch_lib().pch_batch_tune(self.handle, out.data_ptr(), _stream_handle(stream), ctypes.byref(o)))
+        return o.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _batch_lib().pch_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,100 @@
+"""GPU tests of the batched persistent launch (many fields, uneven meshes).
+
+Every batched field must equal the single-field run with the same selection
+rule (adaptive step, same k and first step) bit for bit, and ICH to 1e-9;
+graph replays with eager work in between give the same bits again.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1305_1293_amd import meshgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pch():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1305_1293_amd import pch as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def setup(pch):
+    gens = [G.sinusoid_grid(24, 0), G.bumpy_icosphere(3, seed=5), G.bump_grid(32, seed=7), G.cone_fan(7, 5),
+            G.bump_grid(96, seed=23)]
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    rng = np.random.default_rng(1)
+    fm, fs = [], []
+    for i, m in enumerate(gens):
+        for s in rng.choice(m.nv, 4, replace=False):
+            fm.append(i)
+            fs.append(int(s))
+    return gens, meshes, np.array(fm), np.array(fs)
+
+
+def single(pch, mesh, s, k):
+    import torch
+    d = pch.geodesic(mesh, [s], k=k, select_mode=1)
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batch_equals_single_fields(pch, oracle, setup, use_graph):
+    import torch
+    gens, meshes, fm, fs = setup
+    k = 256
+    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, use_graph=use_graph)
+    say(f"batch of {b.n_fields} fields, graph {use_graph}")
+    out, st = b.run()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert st["fields"] == b.n_fields
+    fstat = b.field_stats()
+    assert np.all(fstat[:, 0] == 0), fstat[:, 0]
+    for f in range(b.n_fields):
+        ref = single(pch, meshes[fm[f]], int(fs[f]), k)
+        gf = got[b.offsets[f]:b.offsets[f + 1]]
+        assert np.array_equal(gf.view(np.uint64), ref.view(np.uint64)), f"field {f} differs from the single run"
+        d_ich, _ = oracle.ich(gens[fm[f]], [int(fs[f])])
+        hbar = float(oracle.lengths(gens[fm[f]]).mean())
+        assert np.max(np.abs(gf - d_ich) / np.maximum(d_ich, hbar)) <= 1e-9, f
+    # replays with eager work in between
+    for rep in range(3):
+        single(pch, meshes[0], 3, 64)
+        out2, _ = b.run(out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out2.cpu().numpy().view(np.uint64), got.view(np.uint64)), f"replay {rep}"
+    b.close()
+
+
+def test_batch_overflow_reruns(pch, setup):
+    import torch
+    gens, meshes, fm, fs = setup
+    b0 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1)
+    out0, _ = b0.run()
+    b1 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1, pool_capacity=128)
+    out1, st = b1.run()
+    torch.cuda.synchronize()
+    assert st["reruns"] > 0
+    assert np.array_equal(out0.cpu().numpy().view(np.uint64), out1.cpu().numpy().view(np.uint64))
+    b0.close()
+    b1.close()
+
+
+def test_batch_argument_errors(pch, setup):
+    gens, meshes, fm, fs = setup
+    with pytest.raises(pch.PchError):
+        pch.Batch(meshes, [0], [gens[0].nv])
+    with pytest.raises(pch.PchError):
+        pch.Batch(meshes, [len(meshes)], [0])
