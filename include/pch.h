@@ -84,8 +84,17 @@ enum {
   PCH_SELECT_DELTA = 1, /* keys up to the pool's smallest key plus a step that
                            starts at delta0 and is scaled after each round by
                            k / selected (clamped to [1/2, 2]); no histogram */
-  PCH_SELECT_TABLE = 2  /* per-round cutoff values from options.cutoff_table
+  PCH_SELECT_TABLE = 2,  /* per-round cutoff values from options.cutoff_table
                            (select key <= cutoff); after the table, KTH */
+  PCH_SELECT_LEARNED = 3 /* cutoff from predicted vertex distances
+                           (options.predicted): with C(r) the number of
+                           vertices predicted within r, m the pool's smallest
+                           key and w the windows processed per vertex within m
+                           so far (w0 before any), select keys up to
+                           C^-1(C(m) + f k / w), where the factor f starts at
+                           1 and is scaled after each such round by
+                           k / selected (clamped to [1/2, 2]); predictions
+                           only steer the rounds, the distances stay exact */
 };
 
 typedef struct {
@@ -107,6 +116,9 @@ typedef struct {
   int32_t reserved;
   double delta0;              /* first step of PCH_SELECT_DELTA; 0 = twice the
                                  mean edge length */
+  const float* predicted;     /* device, nv predicted distances (LEARNED) */
+  double w0;                  /* windows per vertex before the first round of
+                                 LEARNED (default 4) */
 } pch_options;
 
 /* Fill opts with the defaults above. */
@@ -196,6 +208,39 @@ pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
  * dist), keeps the fastest in the batch and returns it in chosen (may be
  * NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
+
+/* ------------------------------------------------------------------------
+ * Learned distance predictor for PCH_SELECT_LEARNED: an MLP 7 -> 64 -> 64 -> 1
+ * (ReLU) on features [(v - c) / R, (s - c) / R, |v - s| / R] of vertex v,
+ * source s, mesh centre c and radius R. Output |v - s| (1 + softplus(y)).
+ * FP32 master weights; weights and activations rounded to BF16 before each
+ * product, FP32 accumulation. Parameters (PCH_MLP_NPARAM floats, host
+ * copies): W1[7][64], b1[64], W2[64][64], b2[64], W3[64], b3.
+ * ---------------------------------------------------------------------- */
+#define PCH_MLP_NPARAM 4737
+typedef struct pch_mlp_s* pch_mlp;
+
+pch_status pch_mlp_create(uint64_t seed, pch_mlp* out);
+void pch_mlp_destroy(pch_mlp mlp);
+pch_status pch_mlp_get_params(pch_mlp mlp, float* host_params);
+pch_status pch_mlp_set_params(pch_mlp mlp, const float* host_params); /* resets AdamW state */
+
+/* xyz device double [nv][3]; center host double [3]; feats device float
+ * [nv][7]; base device float [nv] (the chord |v - s|). */
+pch_status pch_mlp_features(const double* xyz, int64_t nv, int32_t source, const double* center, double radius,
+                            float* feats, float* base, void* hip_stream);
+/* pred device float [n]. */
+pch_status pch_mlp_forward(pch_mlp mlp, const float* feats, const float* base, int64_t n, float* pred,
+                           void* hip_stream);
+/* Loss mean(((pred - target) / scale)^2) over n samples and its gradient
+ * (host float [PCH_MLP_NPARAM], may be NULL) without updating. */
+pch_status pch_mlp_gradients(pch_mlp mlp, const float* feats, const float* base, const float* target,
+                             const float* scale, int64_t n, float* grads_host, float* loss_host, void* hip_stream);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay on the
+ * weights) on that loss; loss_host (may be NULL) receives the loss before it. */
+pch_status pch_mlp_train_step(pch_mlp mlp, const float* feats, const float* base, const float* target,
+                              const float* scale, int64_t n, float lr, float weight_decay, float* loss_host,
+                              void* hip_stream);
 
 const char* pch_status_string(pch_status s);
 const char* pch_last_error(void);

@@ -42,6 +42,8 @@ pch_status set_err(pch_status s, const std::string& m) {
   return s;
 }
 
+constexpr int kCdfBins = 65536;
+
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
     hipError_t e_ = (expr);                                                             \
@@ -96,6 +98,8 @@ struct Ctl {
   double cutval;
   u64 dmode;        // current round uses the adaptive step
   double delta;     // adaptive step
+  u64 lmode;        // current round uses the learned cutoff
+  double lfac;      // feedback factor of the learned cutoff
   u64 ticket;       // last-block detection
   u64 cnt[C_NUM];   // current round
   u64 xcnt[X_NUM];
@@ -160,6 +164,9 @@ struct RoundArgs {
   int32_t ch_on, ich_on, full_fan;
   const double* table;  // device cutoff table or null
   int64_t n_table;
+  const u32* cdf;       // learned cutoff: cumulative counts of predicted distances
+  double pbin;          // width of a cdf bin
+  double w0;            // windows per vertex before the first learned round
 };
 
 // ---------------------------------------------------------------------------
@@ -597,11 +604,14 @@ __device__ void round_begin(const RoundArgs& a, int p) {
       c->tot[f] = ld(&c->tot[f]) + rec[f];
     }
     // adaptive step: steer the next cutoff toward k selected windows
-    if (ld(&c->dmode)) {
+    if (ld(&c->dmode) || ld(&c->lmode)) {
       const u64 ns = rec[C_SEL];
       const double ratio = (double)a.k / (double)(ns > 0 ? ns : 1ull);
       const double f = ratio < 0.5 ? 0.5 : (ratio > 2.0 ? 2.0 : ratio);
-      c->delta = c->delta * f;
+      if (ld(&c->dmode))
+        c->delta = c->delta * f;
+      else
+        c->lfac = c->lfac * f;
     }
     c->active = 0;
   }
@@ -630,6 +640,7 @@ __device__ void round_begin(const RoundArgs& a, int p) {
   c->use_table = 0;
   c->sel_all = 0;
   c->dmode = 0;
+  c->lmode = 0;
   c->rank = 0;
   const u64 r = round - 1;
   if (a.table && (int64_t)r < a.n_table) {
@@ -646,6 +657,36 @@ __device__ void round_begin(const RoundArgs& a, int p) {
     return;
   }
   const u64 mn = ld(&c->kmin[p]), mx = ld(&c->kmax[p]);
+  if (a.mode == PCH_SELECT_LEARNED) {
+    // C(m): vertices predicted within the pool's smallest key
+    const double m = from_bits(mn);
+    const double bm = m / a.pbin;
+    const u64 total = a.cdf[kCdfBins - 1];
+    const u64 cm = bm >= (double)kCdfBins ? total : a.cdf[(int)bm];
+    const u64 done_w = c->tot[C_SEL];
+    const double w = (done_w > 0 && cm > 0) ? (double)done_w / (double)cm : a.w0;
+    double add = c->lfac * (double)a.k / w;
+    if (add < 1.0) add = 1.0;
+    const u64 want = cm + (u64)add;
+    double rho;
+    if (want > total) {
+      rho = INFINITY;
+    } else {
+      int lo = 0, hi = kCdfBins - 1;  // smallest bin with cdf >= want
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((u64)a.cdf[mid] >= want) hi = mid; else lo = mid + 1;
+      }
+      rho = (double)(lo + 1) * a.pbin;
+    }
+    if (!(rho > m)) rho = m + a.pbin;
+    c->lmode = 1;
+    c->use_table = 1;
+    c->cutval = rho;
+    c->cnt[C_CUT] = bits(rho);
+    c->cnt[C_SHIFT] = (u64)(int64_t)-4;
+    return;
+  }
   if (a.mode == PCH_SELECT_DELTA) {
     c->dmode = 1;
     c->use_table = 1;
@@ -707,6 +748,50 @@ __global__ void __launch_bounds__(kBlock) k_init_fans(RoundArgs a, const int32_t
 }
 
 __global__ void k_begin(RoundArgs a, int p) { round_begin(a, p); }
+
+// Predicted-distance CDF for the learned cutoff: maximum, histogram, scan.
+__global__ void k_pred_max(const float* pred, int64_t n, u32* mx) {
+  u32 m = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = pred[i];
+    const u32 b = (x > 0.f && x < INFINITY) ? __float_as_uint(x) : 0u;  // non-negative floats order as u32
+    m = b > m ? b : m;
+  }
+  atomicMax(mx, m);
+}
+__global__ void k_pred_hist(const float* pred, int64_t n, const u32* mx, u32* hist) {
+  const double bw = (double)__uint_as_float(*mx) * 1.000001 / (double)kCdfBins;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = pred[i];
+    int b = (x > 0.f && bw > 0.0) ? (int)((double)x / bw) : 0;
+    if (!(x < INFINITY)) b = kCdfBins - 1;
+    b = b < 0 ? 0 : (b >= kCdfBins ? kCdfBins - 1 : b);
+    atomicAdd(&hist[b], 1u);
+  }
+}
+__global__ void __launch_bounds__(1024) k_pred_scan(u32* hist) {
+  __shared__ u32 part[1024];
+  constexpr int per = kCdfBins / 1024;
+  u32 loc[per];
+  u32 sum = 0;
+  for (int i = 0; i < per; ++i) {
+    loc[i] = hist[threadIdx.x * per + i];
+    sum += loc[i];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  u32 run = part[threadIdx.x] - sum;
+  for (int i = 0; i < per; ++i) {
+    run += loc[i];
+    hist[threadIdx.x * per + i] = run;
+  }
+}
 
 // One 12-bit radix-select pass over the truncated keys t = key_bits >> shift:
 // pass 0 bins bits 35..24, pass 1 bits 23..12, pass 2 bits 11..0, counting
@@ -1336,6 +1421,9 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.full_fan = B.full_fan;
       a.table = nullptr;
       a.n_table = 0;
+      a.cdf = nullptr;
+      a.pbin = 0.0;
+      a.w0 = 4.0;
       sa = a;
       // zero the control block
       u64* cw = (u64*)&ctl;
@@ -1399,6 +1487,11 @@ __global__ void k_reset_queue(u64* q) { *q = 0ull; }
 
 }  // namespace
 
+int pch::set_error(int s, const std::string& msg) {
+  t_err = msg;
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -1427,6 +1520,7 @@ struct pch_mesh_s {
   int64_t dsrc_cap = 0;
   double* dtable = nullptr;
   int64_t dtable_cap = 0;
+  u32* dcdf = nullptr;  // [kCdfBins + 1]: histogram / cdf, then the maximum
   int64_t* dlog = nullptr;
   int64_t dlog_cap = 0;
   std::vector<int64_t> last_log;
@@ -1557,6 +1651,7 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->hist);
   (void)hipFree(M->dsrc);
   (void)hipFree(M->dtable);
+  (void)hipFree(M->dcdf);
   (void)hipFree(M->dlog);
 }
 
@@ -1598,6 +1693,9 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.full_fan = (o.filters & 4) != 0;
   a.table = (o.select_mode == PCH_SELECT_TABLE) ? M->dtable : nullptr;
   a.n_table = (o.select_mode == PCH_SELECT_TABLE) ? o.n_cutoff : 0;
+  a.cdf = M->dcdf;
+  a.pbin = 0.0;
+  a.w0 = o.w0 > 0.0 ? o.w0 : 4.0;
   return a;
 }
 
@@ -1731,8 +1829,11 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   pch_options o;
   pch_options_default(&o);
   if (opts) o = *opts;
-  if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_TABLE)
+  if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_TABLE &&
+      o.select_mode != PCH_SELECT_LEARNED)
     return set_err(PCH_EINVAL, "unknown select_mode");
+  if (o.select_mode == PCH_SELECT_LEARNED && !o.predicted)
+    return set_err(PCH_EINVAL, "learned selection needs predicted distances");
   if (!(o.delta0 >= 0.0)) return set_err(PCH_EINVAL, "delta0 must be >= 0");
   if (o.collect_timing < 0) return set_err(PCH_EINVAL, "collect_timing must be >= 0");
   if (o.k < 1) return set_err(PCH_EINVAL, "k must be >= 1");
@@ -1773,6 +1874,21 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     for (int64_t j = 0; j < H.nh; ++j) sum += H.he[j].L;
     delta0 = 2.0 * (sum / (double)H.nh);
   }
+  double pbin = 0.0;
+  if (o.select_mode == PCH_SELECT_LEARNED) {
+    if (!M->dcdf) HIP_TRY(dalloc(&M->dcdf, kCdfBins + 1));
+    k_fill_u32<<<64, kBlock, 0, st>>>(M->dcdf, kCdfBins + 1, 0u);
+    k_pred_max<<<256, kBlock, 0, st>>>(o.predicted, H.nv, M->dcdf + kCdfBins);
+    k_pred_hist<<<1024, kBlock, 0, st>>>(o.predicted, H.nv, M->dcdf + kCdfBins, M->dcdf);
+    k_pred_scan<<<1, 1024, 0, st>>>(M->dcdf);
+    u32 mxb = 0;
+    HIP_TRY(hipMemcpyAsync(&mxb, M->dcdf + kCdfBins, sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float mx;
+    std::memcpy(&mx, &mxb, sizeof(mx));
+    pbin = (double)mx * 1.000001 / (double)kCdfBins;
+    if (!(pbin > 0.0)) return set_err(PCH_EINVAL, "predicted distances must be positive");
+  }
   int64_t cap = o.pool_capacity > 0 ? o.pool_capacity : std::max<int64_t>(1 << 18, 2 * H.nh);
   if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
   const int64_t log_rounds = 1 << 18;
@@ -1802,6 +1918,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     pch_status s = ensure_work(M, cap);
     if (s != PCH_OK) return s;
     RoundArgs a = make_args(M, o);
+    a.pbin = pbin;
     const int fill_blocks = 1024;
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->g, H.nv, bits_host(INFINITY));
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->AD, H.nh, bits_host(INFINITY));
@@ -1811,6 +1928,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     std::memset(&ctl_init, 0, sizeof(ctl_init));
     ctl_init.kmin[0] = ctl_init.kmin[1] = kAllOnes;
     ctl_init.delta = delta0;
+    ctl_init.lfac = 1.0;
     HIP_TRY(hipMemcpyAsync(M->ctl, &ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, st));
     const int nsrc = (int)src.size();
     k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->dsrc, nsrc);

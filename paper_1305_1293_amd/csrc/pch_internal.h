@@ -64,6 +64,9 @@ struct HostMesh {
 int build_host_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, HostMesh& out,
                     std::string& msg);
 
+// Records the thread's last error text (read by pch_last_error) and returns s.
+int set_error(int s, const std::string& msg);
+
 // Half-edge lengths from coordinates.
 int lengths_from_xyz(const double* xyz, int64_t nv, const int32_t* faces, int64_t nf, std::vector<double>& len,
                      std::string& msg);

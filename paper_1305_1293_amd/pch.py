@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpch.so")
 PCH_SELECT_KTH = 0
 PCH_SELECT_DELTA = 1
 PCH_SELECT_TABLE = 2
+PCH_SELECT_LEARNED = 3
 
 ROUND_LOG_FIELDS = ["N", "cutbits", "shift", "sel", "stale", "kids", "tiny", "ich", "dev", "aev",
                     "fans", "fanwin", "defer", "nend"]
@@ -41,7 +42,7 @@ class Options(ctypes.Structure):
                 ("pool_limit", ctypes.c_int64), ("collect_stats", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
                 ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("delta0", ctypes.c_double)]
+                ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -160,6 +161,11 @@ def options(**kw) -> Options:
     o = Options()
     lib().pch_options_default(ctypes.byref(o))
     table = kw.pop("cutoff_table", None)
+    predicted = kw.pop("predicted", None)
+    if predicted is not None:
+        o.select_mode = PCH_SELECT_LEARNED
+        o.predicted = predicted.data_ptr() if hasattr(predicted, "data_ptr") else int(predicted)
+        o._pred = predicted  # keep alive
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
@@ -288,6 +294,96 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             _batch_lib().pch_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# learned distance predictor
+# ---------------------------------------------------------------------------
+
+MLP_NPARAM = 4737
+EXPORTS += ["pch_mlp_create", "pch_mlp_destroy", "pch_mlp_get_params", "pch_mlp_set_params", "pch_mlp_features",
+            "pch_mlp_forward", "pch_mlp_gradients", "pch_mlp_train_step"]
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_ready", False):
+        P, i64, i32, f, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
+        L.pch_mlp_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(P)]
+        L.pch_mlp_destroy.argtypes = [P]
+        L.pch_mlp_destroy.restype = None
+        L.pch_mlp_get_params.argtypes = [P, P]
+        L.pch_mlp_set_params.argtypes = [P, P]
+        L.pch_mlp_features.argtypes = [P, i64, i32, P, d, P, P, P]
+        L.pch_mlp_forward.argtypes = [P, P, P, i64, P, P]
+        L.pch_mlp_gradients.argtypes = [P, P, P, P, P, i64, P, P, P]
+        L.pch_mlp_train_step.argtypes = [P, P, P, P, P, i64, f, f, P, P]
+        L._mlp_ready = True
+    return L
+
+
+class MLP:
+    """Device-resident distance predictor (7 -> 64 -> 64 -> 1)."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(_mlp_lib().pch_mlp_create(seed, ctypes.byref(h)))
+        self.handle = h
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(MLP_NPARAM, np.float32)
+        _check(_mlp_lib().pch_mlp_get_params(self.handle, p.ctypes.data))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == MLP_NPARAM
+        _check(_mlp_lib().pch_mlp_set_params(self.handle, p.ctypes.data))
+
+    @staticmethod
+    def features(xyz_dev, source: int, center, radius: float, stream=None):
+        import torch
+        nv = int(xyz_dev.shape[0])
+        feats = torch.empty((nv, 7), dtype=torch.float32, device=xyz_dev.device)
+        base = torch.empty(nv, dtype=torch.float32, device=xyz_dev.device)
+        c = np.ascontiguousarray(center, dtype=np.float64)
+        _check(_mlp_lib().pch_mlp_features(xyz_dev.data_ptr(), nv, int(source), c.ctypes.data, float(radius),
+                                           feats.data_ptr(), base.data_ptr(), _stream_handle(stream)))
+        return feats, base
+
+    def forward(self, feats, base, stream=None):
+        import torch
+        n = int(feats.shape[0])
+        out = torch.empty(n, dtype=torch.float32, device=feats.device)
+        _check(_mlp_lib().pch_mlp_forward(self.handle, feats.data_ptr(), base.data_ptr(), n, out.data_ptr(),
+                                          _stream_handle(stream)))
+        return out
+
+    def gradients(self, feats, base, target, scale, stream=None):
+        g = np.empty(MLP_NPARAM, np.float32)
+        loss = ctypes.c_float()
+        _check(_mlp_lib().pch_mlp_gradients(self.handle, feats.data_ptr(), base.data_ptr(), target.data_ptr(),
+                                            scale.data_ptr(), int(feats.shape[0]), g.ctypes.data, ctypes.byref(loss),
+                                            _stream_handle(stream)))
+        return float(loss.value), g
+
+    def train_step(self, feats, base, target, scale, lr=1e-3, weight_decay=1e-4, want_loss=False, stream=None):
+        loss = ctypes.c_float()
+        _check(_mlp_lib().pch_mlp_train_step(self.handle, feats.data_ptr(), base.data_ptr(), target.data_ptr(),
+                                             scale.data_ptr(), int(feats.shape[0]), float(lr), float(weight_decay),
+                                             ctypes.byref(loss) if want_loss else None, _stream_handle(stream)))
+        return float(loss.value) if want_loss else None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _mlp_lib().pch_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

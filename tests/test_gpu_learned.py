@@ -1,0 +1,146 @@
+"""GPU tests of the learned selection cutoff.
+
+* the MLP kernels against the FP64 reference with emulated BF16 rounding
+  (predictions; gradients norm-wise within 1e-2 per tensor);
+* training on PCH-generated fields lowers the loss;
+* fields computed with the learned cutoff are exact (ICH, 1e-9) and their
+  per-round records replay bit for bit in the round-based replica fed with the
+  logged cutoffs;
+* what the trained network gains over plain k-th-key selection.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+from paper_1305_1293_amd import meshgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pch():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1305_1293_amd import pch as P
+    P.lib()
+    return P
+
+
+def _tensor_slices():
+    return {"W1": slice(R.OW1, R.OB1), "b1": slice(R.OB1, R.OW2), "W2": slice(R.OW2, R.OB2),
+            "b2": slice(R.OB2, R.OW3), "W3": slice(R.OW3, R.OB3), "b3": slice(R.OB3, R.NP)}
+
+
+def test_mlp_matches_reference(pch):
+    import torch
+    rng = np.random.default_rng(3)
+    n = 777
+    p = (rng.normal(size=R.NP) * 0.25).astype(np.float32)
+    X = rng.normal(size=(n, 7)).astype(np.float32)
+    base = rng.uniform(0.05, 1.0, n).astype(np.float32)
+    target = (base * rng.uniform(1.0, 1.6, n)).astype(np.float32)
+    scale = np.maximum(target, 0.05).astype(np.float32)
+    mlp = pch.MLP(0)
+    mlp.set_params(p)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    pred = mlp.forward(dev(X), dev(base)).cpu().numpy()
+    ref, _ = R.forward(p.astype(np.float64), X.astype(np.float64), base.astype(np.float64), bf16=True)
+    assert np.max(np.abs(pred - ref) / ref) < 2e-3
+    loss, g = mlp.gradients(dev(X), dev(base), dev(target), dev(scale))
+    lref, gref = R.loss_and_grad(p.astype(np.float64), X.astype(np.float64), base.astype(np.float64),
+                                 target.astype(np.float64), scale.astype(np.float64), bf16=True)
+    assert abs(loss - lref) <= 5e-3 * lref
+    for name, sl in _tensor_slices().items():
+        err = np.linalg.norm(g[sl] - gref[sl]) / max(np.linalg.norm(gref[sl]), 1e-12)
+        assert err < 1e-2, (name, err)
+    mlp.close()
+
+
+@pytest.fixture(scope="module")
+def trained(pch):
+    from paper_1305_1293_amd import learned as Lr
+    gens = []
+    for i, lvl in enumerate([4, 4, 5]):
+        m = G.bumpy_icosphere(lvl, seed=200 + i)
+        m.meta["sources"] = np.random.default_rng(i).choice(m.nv, 4, replace=False)
+        gens.append(m)
+    data, fields = Lr.build_training_set(gens, k=2048)
+    mlp = pch.MLP(7)
+    say(f"training samples {int(data.feats.shape[0])}")
+    losses = Lr.train(mlp, data, epochs=6, batch=4096, lr=2e-3, log_every=10)
+    say(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    return mlp, losses
+
+
+def test_training_lowers_loss(trained):
+    mlp, losses = trained
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_cutoff_exact_and_replayable(pch, oracle, trained):
+    import torch
+    from paper_1305_1293_amd import learned as Lr
+    mlp, _ = trained
+    for m, s, k in [(G.bumpy_icosphere(4, seed=31), 7, 512), (G.bump_grid(64, seed=12), 0, 1024),
+                    (G.sinusoid_grid(48, 3), 100, 256)]:
+        say(f"learned cutoff {m.name} source {s} k {k}")
+        dm = pch.Mesh.from_generated(m)
+        xyz = torch.from_numpy(m.xyz).cuda()
+        d, st = Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k, collect_stats=1)
+        torch.cuda.synchronize()
+        got = d.cpu().numpy()
+        log = dm.round_log()
+        ref, _ = oracle.ich(m, [s])
+        hbar = float(oracle.lengths(m).mean())
+        assert np.max(np.abs(got - ref) / np.maximum(ref, hbar)) <= 1e-9
+        learned_rounds = log[:, 2] == -4
+        assert learned_rounds.any()
+        cut = log[:, 1].astype(np.uint64).view(np.float64).copy()
+        cut[~learned_rounds] = np.inf  # rounds that took the whole pool
+        dr, _, log_r = oracle.replica(m, [s], k, cutoffs=cut)
+        assert np.array_equal(got.view(np.uint64), dr.view(np.uint64))
+        assert np.array_equal(log[:, 0], log_r[:, 0]) and np.array_equal(log[:, 3:], log_r[:, 3:])
+        dm.close()
+
+
+def test_learned_gain_over_plain(pch, trained):
+    """Learned cutoff against the plain method (k-th-key selection) with the
+    same k on held-out meshes: both exact; the learned rounds skip the three
+    histogram passes per round."""
+    import torch
+    from paper_1305_1293_amd import learned as Lr
+    mlp, _ = trained
+    rows = []
+    for m, s in [(G.bumpy_icosphere(5, seed=77), 11), (G.bump_grid(128, seed=13), 0)]:
+        dm = pch.Mesh.from_generated(m)
+        xyz = torch.from_numpy(m.xyz).cuda()
+        k = 4096
+        for rep in range(2):  # second repetition is the timed one
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            dp, sp = pch.geodesic(dm, [s], k=k, select_mode=pch.PCH_SELECT_KTH, return_stats=True)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t
+            t = time.perf_counter()
+            dl, sl = Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k)
+            torch.cuda.synchronize()
+            tl = time.perf_counter() - t
+            t = time.perf_counter()
+            dd, sd = pch.geodesic(dm, [s], k=k, select_mode=pch.PCH_SELECT_DELTA, return_stats=True)
+            torch.cuda.synchronize()
+            td = time.perf_counter() - t
+        assert torch.equal(dp, dl) or float((dp - dl).abs().max()) <= 1e-9 * float(dp.max())
+        rows.append((m.name, tp, tl, sp["processed"], sl["processed"], sp["rounds"], sl["rounds"]))
+        say(f"{m.name}: plain {1000*tp:.1f} ms {sp['processed']} windows {sp['rounds']} rounds | "
+            f"learned {1000*tl:.1f} ms {sl['processed']} windows {sl['rounds']} rounds | "
+            f"adaptive step {1000*td:.1f} ms {sd['processed']} windows {sd['rounds']} rounds")
+        dm.close()
+    assert sum(r[2] for r in rows) < sum(r[1] for r in rows)
