@@ -69,10 +69,14 @@ def main():
     ap.add_argument("--k", type=int, default=8192, help="windows selected per round")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
+    ap.add_argument("--hops", type=int, default=1, help="propagation hops per round")
     ap.add_argument("--time-every", type=int, default=8,
                     help="time the propagation kernel of every n-th round with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes 5 times (the reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's fields are "
@@ -86,12 +90,21 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_bytes > 0:
+        n = args.copy_bytes // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n, "copies": 5}), flush=True)
+        return
     m = G.config_mesh(2)
     rng = np.random.default_rng(2024)
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
     out = torch.empty(m.nv, dtype=torch.float64, device="cuda")
-    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0)
+    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0, hops=args.hops)
 
     for i in range(args.warmup):
         pch.geodesic(mesh, [int(srcs[i])], out=out, **opts)
@@ -115,16 +128,20 @@ def main():
     kids = tot["created"] - tot["fan_windows"]
     prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
                   + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
-    launches = max(tot["propagate_launches"], 1)
-    avg_launch_s = tot["ms_propagate"] / 1000.0 / launches
-    bytes_per_launch = prop_bytes / launches
+    # every round launches the propagation kernel once per hop; the HIP events
+    # bracket the launches of every n-th round
+    timed = max(tot["propagate_launches"], 1)
+    avg_launch_s = tot["ms_propagate"] / 1000.0 / timed
+    all_launches = max(tot["rounds"] * args.hops, 1)
+    bytes_per_launch = prop_bytes / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     traffic = traffic_from_profile("icosphere7")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_propagate", "avg_launch_us": round(avg_launch_s * 1e6, 3),
-                "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": tot["propagate_launches"],
-                "propagate_share_of_wall": round(tot["ms_propagate"] / 1000.0 / wall, 4)}
+                "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
+                "timed_launches": tot["propagate_launches"],
+                "propagate_share_of_wall": round(avg_launch_s * all_launches / wall, 4)}
 
     cpu = None
     max_err = None
@@ -159,7 +176,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, one seeded random "
                                "source per field", "faces": m.nf, "vertices": m.nv, "k": args.k,
-                   "select": ["kth", "adaptive-step"][args.select]},
+                   "select": ["kth", "adaptive-step"][args.select], "hops": args.hops},
         "windows_per_s": round(tot["processed"] / wall, 1),
         "fields_per_s": round(args.steps / wall, 3),
         "windows_per_field": round(tot["processed"] / args.steps, 1),

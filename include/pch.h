@@ -113,7 +113,15 @@ typedef struct {
   int32_t collect_timing;     /* n > 0: time the propagation launch of every
                                  n-th round with HIP events on hip_stream
                                  (pch_stats.ms_propagate) */
-  int32_t reserved;
+  int32_t hops;               /* propagation hops per round, 1..16 (default 1:
+                                 every selected window crosses one face, as in
+                                 Algorithm 1). With h > 1, children that pass
+                                 the round's own selection test propagate
+                                 again in the same round, up to h times,
+                                 against the round-start geod_dist and
+                                 angle_split; distances are unchanged (the
+                                 order of propagation does not matter and
+                                 stale values only prune less), rounds drop */
   double delta0;              /* first step of PCH_SELECT_DELTA; 0 = twice the
                                  mean edge length */
   const float* predicted;     /* device, nv predicted distances (LEARNED) */
@@ -173,6 +181,8 @@ typedef struct {
   int32_t use_graph;     /* 1 = replay a captured HIP graph of the launch (default) */
   int32_t team_threads;  /* threads of the workgroup that runs one field: 256
                             (default) or 1024 */
+  int32_t hops;          /* as pch_options.hops (default 1) */
+  int32_t pad;
 } pch_batch_options;
 
 typedef struct {

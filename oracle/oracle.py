@@ -49,7 +49,7 @@ def lib():
         L.orc_lengths.argtypes = [P, i64, P, i64, P]
         L.orc_mesh_info.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P]
         L.orc_ich.argtypes = [P, i64, i64, P, P, i32, d, i32, P, P]
-        L.orc_replica.argtypes = [P, i64, i64, P, P, i32, i64, d, i32, i32, d, P, i64, P, P, P, i64, P, P]
+        L.orc_replica.argtypes = [P, i64, i64, P, P, i32, i64, i32, d, i32, i32, d, P, i64, P, P, P, i64, P, P]
         L.orc_dijkstra.argtypes = [P, i64, i64, P, P, i32, P]
         L.orc_fn_atan2.argtypes = [d, d]
         L.orc_fn_atan2.restype = d
@@ -117,13 +117,16 @@ def ich(mesh, sources, eps_tiny: float = 0.0, filters: int = 3):
 
 def replica(mesh, sources, k: int, eps_tiny: float = 0.0, filters: int = 3, cutoffs=None,
             max_log: int = 1 << 16, vertex_updates: Optional[np.ndarray] = None, mode: int = 0,
-            delta0: float = 0.0):
+            delta0: float = 0.0, hops: int = 1):
     """Round-based PCH with delayed updates; returns (dist, stats, round_log).
 
     mode 0 selects the k smallest keys each round; mode 1 selects keys up to
     the pool's smallest key plus an adaptive step that starts at ``delta0``.
     ``cutoffs`` (optional float64 array) replaces the rule of round r by
     ``cutoffs[r]`` (select key <= cutoff) for as many rounds as it holds.
+    ``hops`` > 1 lets children that pass the round's selection test propagate
+    again within the round (up to ``hops`` propagations), against the same
+    round-start snapshot; the log's selected count covers every hop.
     """
     s = _sources(sources)
     he = lengths(mesh)
@@ -132,7 +135,7 @@ def replica(mesh, sources, k: int, eps_tiny: float = 0.0, filters: int = 3, cuto
     rlog = np.zeros((max_log, len(RL_FIELDS)), np.int64)
     nr = np.zeros(1, np.int64)
     ct = None if cutoffs is None else np.ascontiguousarray(cutoffs, np.float64)
-    _check(lib().orc_replica(_ptr(mesh.faces), mesh.nf, mesh.nv, _ptr(he), _ptr(s), s.size, int(k), eps_tiny,
+    _check(lib().orc_replica(_ptr(mesh.faces), mesh.nf, mesh.nv, _ptr(he), _ptr(s), s.size, int(k), int(hops), eps_tiny,
                              filters, int(mode), float(delta0), _ptr(ct), 0 if ct is None else ct.size, _ptr(dist),
                              _ptr(stats), _ptr(rlog),
                              max_log, _ptr(nr), _ptr(vertex_updates)))

@@ -766,16 +766,16 @@ enum {
 // after a round that did not take the whole pool, delta is multiplied by
 // k / selected clamped to [1/2, 2]. A cutoff table overrides either rule for
 // its rounds.
-int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double eps_tiny, int32_t filters,
-                int32_t mode, double delta0, const double* cut_table, int64_t n_cut, double* dist, int64_t* stats,
-                int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
+int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, int32_t hops, double eps_tiny,
+                int32_t filters, int32_t mode, double delta0, const double* cut_table, int64_t n_cut, double* dist,
+                int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
   const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
   const int64_t nh = 3 * M.nf;
   std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
   std::vector<RWin> pool, nextp;
   std::vector<Ev> pending, dev, dfr;
   std::vector<AEv> aev;
-  std::vector<Cand> kids, fw;
+  std::vector<Cand> kids, fw, hop_in;
   std::vector<double> fan_th(M.nv, INFINITY);
   std::vector<int32_t> touched;
   Cnt Ctot;
@@ -820,6 +820,11 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
     aev.clear();
     kids.clear();
     int64_t nsel = 0, nstale = 0;
+    // this round's selection test on a key
+    auto selected = [&](double key) {
+      if (ext || dmode) return key <= cval;
+      return cut.all || ((bits_of(key) >> cut.shift) <= cut.T);
+    };
     // snapshot semantics: every selected window reads the same g, AD, AX
     for (int64_t i = 0; i < N; ++i) {
       const RWin& w = pool[i];
@@ -827,19 +832,29 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, double
         nstale++;
         continue;
       }
-      bool sel;
-      if (ext || dmode) {
-        sel = w.key <= cval;
-      } else {
-        sel = cut.all || ((bits_of(w.key) >> cut.shift) <= cut.T);
-      }
-      if (!sel) {
+      if (!selected(w.key)) {
         nextp.push_back(w);
         continue;
       }
       nsel++;
       propagate(M, w.b0, w.b1, w.px, w.py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, eps_tiny,
                 dev, aev, kids, C);
+    }
+    // Further hops of the same round: children that pass the round's
+    // selection test propagate at once, against the same snapshot, up to
+    // `hops` propagations per round. Distances do not depend on the order in
+    // which windows propagate; stale snapshot values only prune less.
+    for (int32_t h = 1; h < hops; ++h) {
+      hop_in.clear();
+      std::vector<Cand> stay;
+      for (const Cand& c : kids) (selected(c.key) ? hop_in : stay).push_back(c);
+      kids.swap(stay);
+      if (hop_in.empty()) break;
+      for (const Cand& c : hop_in) {
+        nsel++;
+        propagate(M, c.b0, c.b1, c.px, c.py, c.sg, c.e, c.src, g.data(), AD.data(), AX.data(), ch_on, ich_on,
+                  eps_tiny, dev, aev, kids, C);
+      }
     }
     add(nextp, kids);
     const int64_t ndev_prop = (int64_t)dev.size();
@@ -993,7 +1008,8 @@ int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, 
 }
 
 int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
-                int64_t k, double eps_tiny, int32_t filters, int32_t mode, double delta0, const double* cut_table,
+                int64_t k, int32_t hops, double eps_tiny, int32_t filters, int32_t mode, double delta0,
+                const double* cut_table,
                 int64_t n_cut, double* dist, int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds,
                 int64_t* vupd) {
   OMesh M;
@@ -1002,13 +1018,14 @@ int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_l
   rc = check_sources(src, m, nv);
   if (rc) return rc;
   if (k < 1) return fail(EINVAL_, "k must be >= 1");
+  if (hops < 1) return fail(EINVAL_, "hops must be >= 1");
   if (mode != 0 && mode != 1) return fail(EINVAL_, "unknown selection mode");
   if (mode == 1 && !(delta0 > 0.0)) return fail(EINVAL_, "delta0 must be > 0");
   std::vector<int32_t> s(src, src + m);
   std::sort(s.begin(), s.end());
   s.erase(std::unique(s.begin(), s.end()), s.end());
-  return run_replica(M, s.data(), (int32_t)s.size(), k, eps_tiny, filters, mode, delta0, cut_table, n_cut, dist,
-                     stats, rlog, max_log, n_rounds, vupd);
+  return run_replica(M, s.data(), (int32_t)s.size(), k, hops, eps_tiny, filters, mode, delta0, cut_table, n_cut,
+                     dist, stats, rlog, max_log, n_rounds, vupd);
 }
 
 // Dijkstra along mesh edges (length of the best edge path).

@@ -43,6 +43,7 @@ pch_status set_err(pch_status s, const std::string& m) {
 }
 
 constexpr int kCdfBins = 65536;
+constexpr int kMaxHops = 16;  // propagation hops per round at most
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -101,6 +102,7 @@ struct Ctl {
   u64 lmode;        // current round uses the learned cutoff
   double lfac;      // feedback factor of the learned cutoff
   u64 ticket;       // last-block detection
+  u64 nhop[kMaxHops + 1];  // nhop[h]: windows queued by hop h for hop h + 1
   u64 cnt[C_NUM];   // current round
   u64 xcnt[X_NUM];
   u64 tot[C_NUM];   // totals over all rounds
@@ -149,6 +151,7 @@ struct RoundArgs {
   DevState s;
   Pool pool[2];
   Pool sel;
+  Pool hq[2];      // hop queues: hop h reads hq[h & 1] (h >= 2), writes hq[(h + 1) & 1]
   DistEv ev[2];
   AngEv aev;
   Ctl* ctl;
@@ -167,6 +170,7 @@ struct RoundArgs {
   const u32* cdf;       // learned cutoff: cumulative counts of predicted distances
   double pbin;          // width of a cdf bin
   double w0;            // windows per vertex before the first learned round
+  int32_t hops;         // propagation hops per round (1 = each selected window once)
 };
 
 // ---------------------------------------------------------------------------
@@ -587,54 +591,69 @@ __device__ __forceinline__ u64 ld(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Round set-up for input parity p (one thread): log and total the previous
-// round, stop when nothing is left, reset this round's output buffers and set
-// up the selection rule.
-__device__ void round_begin(const RoundArgs& a, int p) {
+// Lane 0's part of the round set-up for input parity p: log and total the
+// previous round, stop when nothing is left, reset this round's output buffers
+// and set up the selection rule. Every counter it reads is loaded first, in one
+// batch of independent loads, so the set-up costs a few memory round trips.
+// Returns 1 when the round takes the learned cutoff: *want is then the number
+// of vertices whose predicted distance the cutoff must reach and *m the pool's
+// smallest key.
+__device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, double* m_out) {
   Ctl* c = a.ctl;
-  if (ld(&c->done)) return;
-  if (ld(&c->active)) {
-    const u64 r = ld(&c->round) - 1;
-    u64 rec[C_NUM];
-    for (int f = 0; f < C_NUM; ++f) rec[f] = ld(&c->cnt[f]);
-    rec[C_NEND] = ld(&c->npool[p]);
-    rec[C_DEFER] = ld(&c->ndev[p]);
+  const u64 done = ld(&c->done), active = ld(&c->active), overflow = ld(&c->overflow);
+  const u64 round = ld(&c->round), peak = ld(&c->peak);
+  const u64 dmode = ld(&c->dmode), lmode = ld(&c->lmode);
+  const u64 N = ld(&c->npool[p]), nd = ld(&c->ndev[p]);
+  const u64 mn = ld(&c->kmin[p]), mx = ld(&c->kmax[p]);
+  u64 rec[C_NUM], tot[C_NUM];
+#pragma unroll
+  for (int f = 0; f < C_NUM; ++f) rec[f] = ld(&c->cnt[f]);
+#pragma unroll
+  for (int f = 0; f < C_NUM; ++f) tot[f] = ld(&c->tot[f]);
+  double delta = c->delta, lfac = c->lfac;
+  if (done) return 0;
+  if (active) {
+    const u64 r = round - 1;
+    rec[C_NEND] = N;
+    rec[C_DEFER] = nd;
+    const bool logit = a.log && (int64_t)r < a.max_log;
+#pragma unroll
     for (int f = 0; f < C_NUM; ++f) {
-      if (a.log && (int64_t)r < a.max_log) a.log[r * C_NUM + f] = (int64_t)rec[f];
-      c->tot[f] = ld(&c->tot[f]) + rec[f];
+      if (logit) a.log[r * C_NUM + f] = (int64_t)rec[f];
+      tot[f] += rec[f];
+      c->tot[f] = tot[f];
     }
-    // adaptive step: steer the next cutoff toward k selected windows
-    if (ld(&c->dmode) || ld(&c->lmode)) {
+    // adaptive step / learned feedback: steer the next cutoff toward k
+    // selected windows
+    if (dmode || lmode) {
       const u64 ns = rec[C_SEL];
       const double ratio = (double)a.k / (double)(ns > 0 ? ns : 1ull);
       const double f = ratio < 0.5 ? 0.5 : (ratio > 2.0 ? 2.0 : ratio);
-      if (ld(&c->dmode))
-        c->delta = c->delta * f;
-      else
-        c->lfac = c->lfac * f;
+      if (dmode) {
+        delta = delta * f;
+        c->delta = delta;
+      } else {
+        lfac = lfac * f;
+        c->lfac = lfac;
+      }
     }
     c->active = 0;
   }
-  if (ld(&c->overflow)) {
+  if (overflow || (N == 0 && nd == 0)) {
     c->done = 1;
-    return;
-  }
-  const u64 N = ld(&c->npool[p]);
-  const u64 nd = ld(&c->ndev[p]);
-  if (N == 0 && nd == 0) {
-    c->done = 1;
-    return;
+    return 0;
   }
   c->active = 1;
-  const u64 round = ld(&c->round) + 1;
-  c->round = round;
-  if (N > ld(&c->peak)) c->peak = N;
+  c->round = round + 1;
+  if (N > peak) c->peak = N;
+#pragma unroll
   for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
   c->cnt[C_N] = N;
   c->npool[1 - p] = 0;
   c->ndev[1 - p] = 0;
   c->nsel = 0;
   c->naev = 0;
+  for (int h = 1; h < a.hops; ++h) c->nhop[h] = 0;
   c->kmin[1 - p] = kAllOnes;
   c->kmax[1 - p] = 0;
   c->use_table = 0;
@@ -642,58 +661,42 @@ __device__ void round_begin(const RoundArgs& a, int p) {
   c->dmode = 0;
   c->lmode = 0;
   c->rank = 0;
-  const u64 r = round - 1;
+  const u64 r = round;  // index of the round being set up
   if (a.table && (int64_t)r < a.n_table) {
     c->use_table = 1;
     c->cutval = a.table[r];
     c->cnt[C_CUT] = bits(c->cutval);
     c->cnt[C_SHIFT] = (u64)(int64_t)-2;
-    return;
+    return 0;
   }
   if (N <= (u64)a.k) {
     c->sel_all = 1;
     c->cnt[C_CUT] = (u64)(int64_t)-1;
     c->cnt[C_SHIFT] = 0;
-    return;
+    return 0;
   }
-  const u64 mn = ld(&c->kmin[p]), mx = ld(&c->kmax[p]);
   if (a.mode == PCH_SELECT_LEARNED) {
-    // C(m): vertices predicted within the pool's smallest key
+    // C(m): vertices predicted within the pool's smallest key; w: windows
+    // processed per such vertex so far (w0 before any)
     const double m = from_bits(mn);
     const double bm = m / a.pbin;
     const u64 total = a.cdf[kCdfBins - 1];
     const u64 cm = bm >= (double)kCdfBins ? total : a.cdf[(int)bm];
-    const u64 done_w = c->tot[C_SEL];
+    const u64 done_w = tot[C_SEL];
     const double w = (done_w > 0 && cm > 0) ? (double)done_w / (double)cm : a.w0;
-    double add = c->lfac * (double)a.k / w;
+    double add = lfac * (double)a.k / w;
     if (add < 1.0) add = 1.0;
-    const u64 want = cm + (u64)add;
-    double rho;
-    if (want > total) {
-      rho = INFINITY;
-    } else {
-      int lo = 0, hi = kCdfBins - 1;  // smallest bin with cdf >= want
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((u64)a.cdf[mid] >= want) hi = mid; else lo = mid + 1;
-      }
-      rho = (double)(lo + 1) * a.pbin;
-    }
-    if (!(rho > m)) rho = m + a.pbin;
-    c->lmode = 1;
-    c->use_table = 1;
-    c->cutval = rho;
-    c->cnt[C_CUT] = bits(rho);
-    c->cnt[C_SHIFT] = (u64)(int64_t)-4;
-    return;
+    *want_out = cm + (u64)add;
+    *m_out = m;
+    return 1;
   }
   if (a.mode == PCH_SELECT_DELTA) {
     c->dmode = 1;
     c->use_table = 1;
-    c->cutval = from_bits(mn) + c->delta;
+    c->cutval = from_bits(mn) + delta;
     c->cnt[C_CUT] = bits(c->cutval);
     c->cnt[C_SHIFT] = (u64)(int64_t)-3;
-    return;
+    return 0;
   }
   const u64 dif = mn ^ mx;
   if (dif == 0) {
@@ -701,7 +704,7 @@ __device__ void round_begin(const RoundArgs& a, int p) {
     c->want = mx;
     c->cnt[C_CUT] = mx;
     c->cnt[C_SHIFT] = 0;
-    return;
+    return 0;
   }
   const int hb = 63 - __clzll((long long)dif);
   int s = hb + 1 - 36;
@@ -709,6 +712,41 @@ __device__ void round_begin(const RoundArgs& a, int p) {
   c->shift = (u64)s;
   c->want = (mn >> s) >> 36;  // common prefix above the 36 bits searched
   c->rank = (u64)a.k;
+  return 0;
+}
+
+// Round set-up, run by one whole wavefront (every lane must call it). For the
+// learned cutoff the wavefront finds the smallest CDF bin b with
+// cdf[b] >= want in three 64-way steps (65536 = 64 * 64 * 16 bins) and the
+// cutoff is the bin's upper edge, above the pool's smallest key.
+__device__ void round_begin(const RoundArgs& a, int p) {
+  const int lane = lane_id();
+  u64 want = 0;
+  double m = 0.0;
+  int learned = 0;
+  if (lane == 0) learned = round_begin_lane0(a, p, &want, &m);
+  learned = __shfl(learned, 0, kWave);
+  if (!learned) return;
+  want = shfl64(want, 0);
+  m = shfl_d(m, 0);
+  const u64 total = a.cdf[kCdfBins - 1];
+  double rho = INFINITY;
+  if (want <= total) {
+    int lo = (__ffsll((unsigned long long)__ballot((u64)a.cdf[(lane + 1) * 1024 - 1] >= want)) - 1) * 1024;
+    lo += (__ffsll((unsigned long long)__ballot((u64)a.cdf[lo + (lane + 1) * 16 - 1] >= want)) - 1) * 16;
+    const bool hit = lane < 16 && (u64)a.cdf[lo + (lane < 16 ? lane : 15)] >= want;
+    lo += __ffsll((unsigned long long)__ballot(hit)) - 1;
+    rho = (double)(lo + 1) * a.pbin;
+  }
+  if (lane == 0) {
+    Ctl* c = a.ctl;
+    if (!(rho > m)) rho = m + a.pbin;
+    c->lmode = 1;
+    c->use_table = 1;
+    c->cutval = rho;
+    c->cnt[C_CUT] = bits(rho);
+    c->cnt[C_SHIFT] = (u64)(int64_t)-4;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -942,16 +980,35 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
 }
 
 // Algorithm 2 for every selected window, against the round-start geod_dist
-// and angle_split (delayed update, Remark 3).
-__device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, u64 t0, u64 stride) {
+// and angle_split (delayed update, Remark 3). Hop 1 takes the windows the
+// partition selected. With hops > 1 a child that passes the round's own
+// selection test is queued for the next hop of the same round instead of
+// entering the pool, and hop h >= 2 propagates hop h - 1's queue, still
+// against the round-start values: the order in which windows propagate does
+// not change the distances, and stale values only prune less.
+__device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 N = min(c->nsel, (u64)a.cap);
-  const Pool S = a.sel;
+  const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
+  const u64 N = min(n_in, (u64)a.cap);
+  const Pool S = hop <= 1 ? a.sel : a.hq[hop & 1];
   const Pool Q = a.pool[1 - p];
+  const bool to_hop = hop < a.hops;
+  const Pool HQ = a.hq[(hop + 1) & 1];
+  u64* nq_ctr = &c->nhop[hop < kMaxHops ? hop : kMaxHops];
+  const int sh = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
-  if (t0 == 0) c->cnt[C_SEL] = c->nsel;
+  if (t0 == 0) {
+    if (hop <= 1)
+      c->cnt[C_SEL] = n_in;
+    else
+      c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
+  }
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
@@ -1132,14 +1189,32 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, u64 t0, 
         }
       }
     }
+    // children that pass the round's selection test go to the next hop
+    bool toq[2] = {false, false};
+    int nq = 0;
+    if (to_hop) {
+      for (int q = 0; q < nk; ++q) {
+        toq[q] = tab ? (kkey[q] <= cv) : (all || ((bits(kkey[q]) >> sh) <= T));
+        nq += toq[q] ? 1 : 0;
+      }
+    }
     // append children, distance events and angle events (one reservation per
     // wavefront each)
-    u32 tk, td, ta;
-    u64 jk, jd, ja;
-    wave_reserve3(&c->npool[1 - p], (u32)nk, &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, jk, jd, ja, tk, td,
-                  ta);
+    u32 tk, td, ta, tq = 0;
+    u64 jk, jd, ja, jq = 0;
+    wave_reserve3(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, jk, jd, ja,
+                  tk, td, ta);
+    if (to_hop) jq = wave_reserve(nq_ctr, (u32)nq, &tq);
     for (int q = 0; q < nk; ++q) {
-      const u64 j = jk + q;
+      if (toq[q]) {
+        const u64 j = jq++;
+        if (j < (u64)a.cap)
+          store_window(HQ, j, kb0[q], kb1[q], kpx[q], kpy[q], sg, kkey[q], ke[q], src);
+        else
+          flag_overflow(c);
+        continue;
+      }
+      const u64 j = jk++;
       if (j < (u64)a.cap) {
         store_window(Q, j, kb0[q], kb1[q], kpx[q], kpy[q], sg, kkey[q], ke[q], src);
         const u64 kb = bits(kkey[q]);
@@ -1169,7 +1244,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, u64 t0, 
       }
     }
     if (lane_id() == 0) {
-      if (tk) atomicAdd(&c->cnt[C_KIDS], (u64)tk);
+      if (tk + tq) atomicAdd(&c->cnt[C_KIDS], (u64)(tk + tq));
       if (td) atomicAdd(&c->cnt[C_DEV], (u64)td);
       if (ta) atomicAdd(&c->cnt[C_AEV], (u64)ta);
     }
@@ -1190,9 +1265,9 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, u64 t0, 
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p) {
+__global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int hop) {
   if (!a.ctl->active) return;
-  ph_propagate(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+  ph_propagate(a, p, hop, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
 // Algorithm 4, first pass: geod_dist and the angle_split distance take the
@@ -1249,7 +1324,12 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   const u32 stamp = (u32)c->round;
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
-  for (u64 i = t0; i - lane_id() < nd; i += stride) {
+  // Events are dealt round-robin over the launch's wavefronts (event
+  // w + nw * lane of each stride-wide chunk to lane `lane` of wavefront w), so
+  // the few fans of a round spread over many compute units.
+  const u64 nw = stride / kWave, w = t0 / kWave;
+  for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
+    const u64 i = j0 + w + nw * (u64)lane_id();
     bool has = false;
     int v = 0;
     double d = 0.0, th = 0.0;
@@ -1294,9 +1374,9 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
   __syncthreads();
   if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
   __syncthreads();
-  if (is_last && threadIdx.x == 0) {
+  if (is_last && threadIdx.x < kWave) {
     __threadfence();
-    c->ticket = 0;
+    if (threadIdx.x == 0) c->ticket = 0;
     round_begin(a, 1 - p);
   }
 }
@@ -1333,6 +1413,8 @@ struct BatchDev {
   int64_t k;
   double eps;
   int32_t ch_on, ich_on, full_fan;
+  int32_t hops;   // propagation hops per round
+  int32_t nslot;  // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
   int64_t max_rounds;
 };
 
@@ -1347,7 +1429,7 @@ __device__ __forceinline__ void team_sync() {
 }
 
 __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
-  const int64_t o = ((int64_t)t * 3 + b) * B.cap;
+  const int64_t o = ((int64_t)t * B.nslot + b) * B.cap;
   return Pool{B.pb0 + o, B.pb1 + o, B.ppx + o, B.ppy + o, B.psg + o, B.pkey + o, B.pe + o, B.psrc + o};
 }
 
@@ -1358,7 +1440,9 @@ __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
 // Out-of-line phases for the persistent kernel: each gets its own register
 // allocation instead of the union of all phases in one function.
 __device__ __noinline__ void nl_partition(const RoundArgs& a, int p, u64 t0, u64 s) { ph_partition(a, p, t0, s); }
-__device__ __noinline__ void nl_propagate(const RoundArgs& a, int p, u64 t0, u64 s) { ph_propagate(a, p, t0, s); }
+__device__ __noinline__ void nl_propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 s) {
+  ph_propagate(a, p, hop, t0, s);
+}
 __device__ __noinline__ void nl_events1(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events1(a, p, t0, s); }
 __device__ __noinline__ void nl_events2(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events2(a, p, t0, s); }
 __device__ __noinline__ void nl_events3(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events3(a, p, t0, s); }
@@ -1400,6 +1484,9 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.pool[0] = slot_pool(B, t, 0);
       a.pool[1] = slot_pool(B, t, 1);
       a.sel = slot_pool(B, t, 2);
+      a.hq[0] = B.hops > 1 ? slot_pool(B, t, 3) : Pool{};
+      a.hq[1] = B.hops > 1 ? slot_pool(B, t, 4) : Pool{};
+      a.hops = B.hops;
       for (int i = 0; i < 2; ++i) {
         const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
         a.ev[i] = DistEv{B.ev_v + o, B.ev_d + o, B.ev_th + o};
@@ -1445,23 +1532,28 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     team_sync();
     if (threadIdx.x < (u32)kWave) nl_init_fan(a, B.field_src[f], &ctl);
     team_sync();
-    if (threadIdx.x == 0) nl_begin(a, 0);
+    if (threadIdx.x < (u32)kWave) nl_begin(a, 0);
     team_sync();
     int p = 0;
     while (!ctl.done) {
       nl_partition(a, p, t0, stride);
       team_sync();
-      nl_propagate(a, p, t0, stride);
+      nl_propagate(a, p, 1, t0, stride);
       team_sync();
+      for (int h = 2; h <= B.hops; ++h) {
+        if (ctl.nhop[h - 1] == 0) break;
+        nl_propagate(a, p, h, t0, stride);
+        team_sync();
+      }
       nl_events1(a, p, t0, stride);
       team_sync();
       nl_events2(a, p, t0, stride);
       team_sync();
       nl_events3(a, p, t0, stride);
       team_sync();
-      if (threadIdx.x == 0) {
+      if (threadIdx.x < (u32)kWave) {
         nl_begin(a, 1 - p);
-        if ((int64_t)ctl.round > B.max_rounds) ctl.done = 1;
+        if (threadIdx.x == 0 && (int64_t)ctl.round > B.max_rounds) ctl.done = 1;
       }
       team_sync();
       p ^= 1;
@@ -1512,6 +1604,8 @@ struct pch_mesh_s {
   int64_t cap = 0, ecap = 0, acap = 0;
   Pool pool[2] = {};
   Pool sel = {};
+  Pool hq[2] = {};
+  int64_t hq_cap = 0;
   DistEv ev[2] = {};
   AngEv aev = {};
   Ctl* ctl = nullptr;
@@ -1569,6 +1663,9 @@ void free_work(pch_mesh_s* M) {
     M->ev[i] = DistEv{};
   }
   free_pool(M->sel);
+  free_pool(M->hq[0]);
+  free_pool(M->hq[1]);
+  M->hq_cap = 0;
   (void)hipFree(M->aev.e);
   (void)hipFree(M->aev.D);
   (void)hipFree(M->aev.X);
@@ -1576,8 +1673,15 @@ void free_work(pch_mesh_s* M) {
   M->cap = M->ecap = M->acap = 0;
 }
 
-pch_status ensure_work(pch_mesh_s* M, int64_t cap) {
-  if (cap <= M->cap) return PCH_OK;
+pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
+  if (cap <= M->cap && (!hop_queues || M->hq_cap >= M->cap)) return PCH_OK;
+  if (cap <= M->cap) {
+    // the hop queues are allocated on first use
+    HIP_TRY(alloc_pool(M->hq[0], M->cap));
+    HIP_TRY(alloc_pool(M->hq[1], M->cap));
+    M->hq_cap = M->cap;
+    return PCH_OK;
+  }
   free_work(M);
   const int64_t ecap = 4 * cap, acap = cap;
   for (int i = 0; i < 2; ++i) {
@@ -1587,6 +1691,11 @@ pch_status ensure_work(pch_mesh_s* M, int64_t cap) {
     HIP_TRY(dalloc(&M->ev[i].th, ecap));
   }
   HIP_TRY(alloc_pool(M->sel, cap));
+  if (hop_queues) {
+    HIP_TRY(alloc_pool(M->hq[0], cap));
+    HIP_TRY(alloc_pool(M->hq[1], cap));
+    M->hq_cap = cap;
+  }
   HIP_TRY(dalloc(&M->aev.e, acap));
   HIP_TRY(dalloc(&M->aev.D, acap));
   HIP_TRY(dalloc(&M->aev.X, acap));
@@ -1675,6 +1784,9 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.pool[0] = M->pool[0];
   a.pool[1] = M->pool[1];
   a.sel = M->sel;
+  a.hq[0] = M->hq[0];
+  a.hq[1] = M->hq[1];
+  a.hops = o.hops;
   a.ev[0] = M->ev[0];
   a.ev[1] = M->ev[1];
   a.aev = M->aev;
@@ -1718,7 +1830,7 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
     for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
   k_partition<<<pool_blocks, kBlock, 0, st>>>(a, p);
   if (ev0) (void)hipEventRecord(ev0, st);
-  k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p);
+  for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
   if (ev1) (void)hipEventRecord(ev1, st);
   k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
@@ -1761,6 +1873,7 @@ void pch_options_default(pch_options* o) {
   o->rounds_per_sync = 16;
   o->cutoff_table = nullptr;
   o->n_cutoff = 0;
+  o->hops = 1;
 }
 
 pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len,
@@ -1841,6 +1954,8 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     return set_err(PCH_EINVAL, "cutoff table missing");
   if (!(o.eps_tiny >= 0.0)) return set_err(PCH_EINVAL, "eps_tiny must be >= 0");
   if (o.rounds_per_sync < 1) o.rounds_per_sync = 16;
+  if (o.hops == 0) o.hops = 1;
+  if (o.hops < 1 || o.hops > kMaxHops) return set_err(PCH_EINVAL, "hops must be in [1, 16]");
   const pch::HostMesh& H = M->host;
   std::vector<int32_t> src(sources, sources + m);
   for (int32_t s : src)
@@ -1915,7 +2030,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   double prop_ms = 0.0;
   int64_t prop_n = 0;
   for (;;) {
-    pch_status s = ensure_work(M, cap);
+    pch_status s = ensure_work(M, cap, o.hops > 1);
     if (s != PCH_OK) return s;
     RoundArgs a = make_args(M, o);
     a.pbin = pbin;
@@ -1933,7 +2048,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     const int nsrc = (int)src.size();
     k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->dsrc, nsrc);
     k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, M->dsrc, nsrc);
-    k_begin<<<1, 1, 0, st>>>(a, 0);
+    k_begin<<<1, kWave, 0, st>>>(a, 0);
     HIP_TRY(hipGetLastError());
     const int pool_blocks = grid_for(std::max<int64_t>(cap, 1), 1024);
     const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
@@ -1962,7 +2077,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
           float ms = 0.f;
           HIP_TRY(hipEventElapsedTime(&ms, tev[2 * r], tev[2 * r + 1]));
           prop_ms += ms;
-          prop_n++;
+          prop_n += o.hops;
         }
       }
       rounds_before = host_ctl.round;
@@ -2079,7 +2194,9 @@ pch_status alloc_slots(pch_batch_s* b) {
   B.ecap = cap;
   B.acap = std::max<int64_t>(cap / 2, 1024);
   const int64_t T = b->n_teams;
-  const int64_t np = T * 3 * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
+  B.hops = b->o.hops;
+  B.nslot = B.hops > 1 ? 5 : 3;
+  const int64_t np = T * B.nslot * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
   HIP_TRY(dalloc(&B.pb0, np));
   HIP_TRY(dalloc(&B.pb1, np));
   HIP_TRY(dalloc(&B.ppx, np));
@@ -2157,6 +2274,7 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
     o.delta0 = b->delta0[b->fmesh[f]];
     o.filters = b->o.filters;
     o.eps_tiny = b->o.eps_tiny;
+    o.hops = b->o.hops;
     pch_stats s1;
     pch_status rc = pch_geodesic(b->meshes[b->fmesh[f]], &b->fsrc[f], 1, out + b->off[f], b->stream, &o, &s1);
     if (rc != PCH_OK) return rc;
@@ -2201,6 +2319,7 @@ void pch_batch_options_default(pch_batch_options* o) {
   o->pool_capacity = 0;
   o->use_graph = 1;
   o->team_threads = 256;
+  o->hops = 1;
 }
 
 void pch_batch_destroy(pch_batch b) {
@@ -2223,7 +2342,9 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   pch_batch_options o;
   pch_batch_options_default(&o);
   if (opts) o = *opts;
-  if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 1024))
+  if (o.hops == 0) o.hops = 1;
+  if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 1024) ||
+      o.hops < 1 || o.hops > kMaxHops)
     return set_err(PCH_EINVAL, "bad batch option");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));

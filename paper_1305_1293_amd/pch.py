@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64),
                 ("pool_limit", ctypes.c_int64), ("collect_stats", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
-                ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("hops", ctypes.c_int32),
                 ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double)]
 
 
@@ -201,7 +201,7 @@ def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_s
 class BatchOptions(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("teams_per_cu", ctypes.c_int32), ("filters", ctypes.c_int32),
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64), ("use_graph", ctypes.c_int32),
-                ("team_threads", ctypes.c_int32)]
+                ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -42,20 +42,20 @@ def setup(pch):
     return gens, meshes, np.array(fm), np.array(fs)
 
 
-def single(pch, mesh, s, k):
+def single(pch, mesh, s, k, hops=1):
     import torch
-    d = pch.geodesic(mesh, [s], k=k, select_mode=1)
+    d = pch.geodesic(mesh, [s], k=k, select_mode=1, hops=hops)
     torch.cuda.synchronize()
     return d.cpu().numpy()
 
 
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_batch_equals_single_fields(pch, oracle, setup, use_graph):
+@pytest.mark.parametrize("use_graph,hops", [(1, 1), (0, 1), (1, 4)])
+def test_batch_equals_single_fields(pch, oracle, setup, use_graph, hops):
     import torch
     gens, meshes, fm, fs = setup
     k = 256
-    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, use_graph=use_graph)
-    say(f"batch of {b.n_fields} fields, graph {use_graph}")
+    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, use_graph=use_graph, hops=hops)
+    say(f"batch of {b.n_fields} fields, graph {use_graph}, hops {hops}")
     out, st = b.run()
     torch.cuda.synchronize()
     got = out.cpu().numpy()
@@ -63,7 +63,7 @@ def test_batch_equals_single_fields(pch, oracle, setup, use_graph):
     fstat = b.field_stats()
     assert np.all(fstat[:, 0] == 0), fstat[:, 0]
     for f in range(b.n_fields):
-        ref = single(pch, meshes[fm[f]], int(fs[f]), k)
+        ref = single(pch, meshes[fm[f]], int(fs[f]), k, hops)
         gf = got[b.offsets[f]:b.offsets[f + 1]]
         assert np.array_equal(gf.view(np.uint64), ref.view(np.uint64)), f"field {f} differs from the single run"
         d_ich, _ = oracle.ich(gens[fm[f]], [int(fs[f])])
@@ -78,12 +78,13 @@ def test_batch_equals_single_fields(pch, oracle, setup, use_graph):
     b.close()
 
 
-def test_batch_overflow_reruns(pch, setup):
+@pytest.mark.parametrize("hops", [1, 3])
+def test_batch_overflow_reruns(pch, setup, hops):
     import torch
     gens, meshes, fm, fs = setup
-    b0 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1)
+    b0 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1, hops=hops)
     out0, _ = b0.run()
-    b1 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1, pool_capacity=128)
+    b1 = pch.Batch(meshes, fm, fs, k=256, teams_per_cu=1, pool_capacity=128, hops=hops)
     out1, st = b1.run()
     torch.cuda.synchronize()
     assert st["reruns"] > 0

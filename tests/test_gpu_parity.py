@@ -94,18 +94,23 @@ def test_small_config_vs_ich(pch, oracle, k):
 @pytest.mark.parametrize("case", [("sinusoid64", 0, 64), ("sinusoid64", 0, 1024), ("sphere4", 17, 512),
                                   ("lshape", -1, 16), ("cone7", 5, 8), ("grid48", 100, 4096),
                                   ("sinusoid64", 0, 1024, 0.02), ("sphere4", 17, 512, 0.05),
-                                  ("grid48", 100, 2048, 0.01)])
+                                  ("grid48", 100, 2048, 0.01),
+                                  ("sinusoid64", 0, 256, None, 3), ("sphere4", 17, 1 << 20, None, 4),
+                                  ("lshape", -1, 16, None, 16), ("cone7", 5, 64, None, 2),
+                                  ("grid48", 100, 2048, 0.01, 4), ("sinusoid64", 0, 1024, 0.02, 8)])
 def test_round_log_matches_replica(pch, oracle, case):
     name, s, k = case[:3]
     delta0 = case[3] if len(case) > 3 else None
+    hops = case[4] if len(case) > 4 else 1
     sel = dict(mode=1, delta0=delta0) if delta0 else {}
     gsel = dict(select_mode=1, delta0=delta0) if delta0 else {}
+    sel["hops"] = gsel["hops"] = hops
     m = {"sinusoid64": lambda: G.config_mesh(1), "sphere4": lambda: G.bumpy_icosphere(4, seed=9),
          "lshape": lambda: G.lshape(6), "cone7": lambda: G.cone_fan(7, 6),
          "grid48": lambda: G.bump_grid(48, seed=4)}[name]()
     if s < 0:
         s = int(np.argmin(np.linalg.norm(m.xyz[:, :2] - [2.0, 0.0], axis=1)))
-    say(f"round log parity {name} source {s} k {k} delta0 {delta0}")
+    say(f"round log parity {name} source {s} k {k} delta0 {delta0} hops {hops}")
     dr, st_r, log_r = oracle.replica(m, [s], k, **sel)
     d, st, log = gpu_field(pch, m, [s], k=k, collect_stats=1, **gsel)
     assert log.shape == log_r.shape, f"rounds: gpu {log.shape[0]} replica {log_r.shape[0]}"

@@ -106,6 +106,24 @@ def test_order_independence_random_cutoffs(oracle, c1):
     assert sel.min() == 0 and sel.max() > 500  # the cutoffs really vary the rounds
 
 
+def test_order_independence_hops(oracle, c1, sphere):
+    """Rounds with several propagation hops (children that pass the round's
+    selection test propagate again against the round-start snapshot) reach the
+    same distances, in fewer rounds, under every selection rule."""
+    hbar = float(oracle.lengths(c1).mean())
+    lsh = G.lshape(12)
+    for m, s in [(c1, 0), (sphere, 3), (lsh, 0)]:
+        d0, _ = oracle.ich(m, [s])
+        for hops in (2, 3, 16):
+            for kw in (dict(k=1 << 30), dict(k=64), dict(k=256, mode=1, delta0=2 * hbar)):
+                d, st, log = oracle.replica(m, [s], hops=hops, **kw)
+                assert rel(d, d0) < 1e-12, (m.name, hops, kw)
+                assert st["processed"] == int(log[:, 3].sum())
+        _, st1, _ = oracle.replica(m, [s], 1 << 30)
+        _, st4, _ = oracle.replica(m, [s], 1 << 30, hops=4)
+        assert st4["rounds"] < st1["rounds"]
+
+
 def test_filters_and_full_fan_do_not_change_distances(oracle, c1):
     m = G.sinusoid_grid(24, 1)
     d0, st0 = oracle.ich(m, [7])
