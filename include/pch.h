@@ -127,6 +127,12 @@ typedef struct {
   const float* predicted;     /* device, nv predicted distances (LEARNED) */
   double w0;                  /* windows per vertex before the first round of
                                  LEARNED (default 4) */
+  int32_t organize;           /* 1 = before they propagate, group each round's
+                                 selected windows by edge (a one-pass bucket
+                                 sort on the half-edge index, 4096 buckets;
+                                 data organization, Algorithm 3); the order
+                                 changes no result (default 0) */
+  int32_t pad;
 } pch_options;
 
 /* Fill opts with the defaults above. */
@@ -213,10 +219,10 @@ pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_ba
  * windows processed, windows created, fans, peak pool, stale windows, 0. */
 pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
 
-/* Autotuner: times k in {2048, 4096, 8192, 16384} with workgroup shapes
- * (256 threads, 2 per CU), (256, 4) and (1024, 1) on the whole batch (into
- * dist), keeps the fastest in the batch and returns it in chosen (may be
- * NULL). */
+/* Autotuner: times k in {4096, 8192, 16384} with workgroup shapes
+ * (256 threads, 1 per CU), (256, 2) and (1024, 1) and 1 or 4 hops per round
+ * on the whole batch (into dist), keeps the fastest in the batch and returns
+ * it in chosen (may be NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
 
 /* ------------------------------------------------------------------------

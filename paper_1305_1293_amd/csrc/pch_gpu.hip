@@ -44,6 +44,7 @@ pch_status set_err(pch_status s, const std::string& m) {
 
 constexpr int kCdfBins = 65536;
 constexpr int kMaxHops = 16;  // propagation hops per round at most
+constexpr int kOrgBuckets = 4096;  // edge buckets of the organization by edge
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -136,6 +137,7 @@ struct DevMesh {
   const int32_t* coff;
   const int32_t* corner;
   const pch::Corner* crec;
+  const pch::HalfEdgeAng* hang;
 };
 
 struct DevState {
@@ -171,6 +173,12 @@ struct RoundArgs {
   double pbin;          // width of a cdf bin
   double w0;            // windows per vertex before the first learned round
   int32_t hops;         // propagation hops per round (1 = each selected window once)
+  // organization by edge: the selected windows are grouped by the bucket
+  // e >> org_shift of their half-edge before they propagate (org_shift < 0: off)
+  int32_t org_shift;
+  Pool sorted;
+  u32* org_hist;  // [kOrgBuckets] selected windows per bucket
+  u32* org_ofs;   // [kOrgBuckets] next free slot per bucket
 };
 
 // ---------------------------------------------------------------------------
@@ -251,6 +259,42 @@ __device__ __forceinline__ void wave_reserve3(u64* c0, u32 n0, u64* c1, u32 n1, 
   s0 = shfl64(b0, kWave - 1) + (i0 - n0);
   s1 = shfl64(b1, kWave - 1) + (i1 - n1);
   s2 = shfl64(b2, kWave - 1) + (i2 - n2);
+}
+
+// Four reservations at once (the fourth may be unused: n3 = 0 on every lane).
+__device__ __forceinline__ void wave_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64* c3, u32 n3,
+                                              u64& s0, u64& s1, u64& s2, u64& s3, u32& t0, u32& t1, u32& t2,
+                                              u32& t3) {
+  const int lane = lane_id();
+  u32 i0 = n0, i1 = n1, i2 = n2, i3 = n3;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const u32 y0 = __shfl_up(i0, o, kWave);
+    const u32 y1 = __shfl_up(i1, o, kWave);
+    const u32 y2 = __shfl_up(i2, o, kWave);
+    const u32 y3 = __shfl_up(i3, o, kWave);
+    if (lane >= o) {
+      i0 += y0;
+      i1 += y1;
+      i2 += y2;
+      i3 += y3;
+    }
+  }
+  t0 = __shfl(i0, kWave - 1, kWave);
+  t1 = __shfl(i1, kWave - 1, kWave);
+  t2 = __shfl(i2, kWave - 1, kWave);
+  t3 = __shfl(i3, kWave - 1, kWave);
+  u64 b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  if (lane == kWave - 1) {
+    if (t0) b0 = atomicAdd(c0, (u64)t0);
+    if (t1) b1 = atomicAdd(c1, (u64)t1);
+    if (t2) b2 = atomicAdd(c2, (u64)t2);
+    if (t3) b3 = atomicAdd(c3, (u64)t3);
+  }
+  s0 = shfl64(b0, kWave - 1) + (i0 - n0);
+  s1 = shfl64(b1, kWave - 1) + (i1 - n1);
+  s2 = shfl64(b2, kWave - 1) + (i2 - n2);
+  s3 = shfl64(b3, kWave - 1) + (i3 - n3);
 }
 
 __device__ __forceinline__ u32 wave_sum(u32 x) {
@@ -398,15 +442,15 @@ struct FanOut {
   bool win;
   double b0, b1, px, py, key;
   int32_t e;
-  int nev;
-  int32_t ev_v[2];
-  double ev_d[2], ev_th[2];
+  bool ea, eb;  // distance events at the corner's vertices a and b
+  int32_t va, vb;
+  double da, db, tha, thb;
 };
 
 __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool full, int q, FanOut& o,
                            u32& tiny, u32& ich, u32& notwin) {
   o.win = false;
-  o.nev = 0;
+  o.ea = o.eb = false;
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
   const pch::Corner cr = m.crec[q];
@@ -446,19 +490,19 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
   if (t0 <= 0.0) {
     const double da = d + cr.l_va;
     if (da < ga * kEv) {
-      o.ev_v[o.nev] = va;
-      o.ev_d[o.nev] = da;
-      o.ev_th[o.nev] = cr.th_a;
-      o.nev++;
+      o.ea = true;
+      o.va = va;
+      o.da = da;
+      o.tha = cr.th_a;
     }
   }
   if (t1 >= al && cr.last) {
     const double db = d + cr.l_vb;
     if (db < gb * kEv) {
-      o.ev_v[o.nev] = vb;
-      o.ev_d[o.nev] = db;
-      o.ev_th[o.nev] = cr.th_b;
-      o.nev++;
+      o.eb = true;
+      o.vb = vb;
+      o.db = db;
+      o.thb = cr.th_b;
     }
   }
   const int tw = cr.tw;
@@ -524,12 +568,13 @@ __device__ __forceinline__ double shfl_d(double x, int src) {
 // lane finds the owner of its pair by binary search over the lanes. Windows
 // and events are reserved once per wavefront and step; windows go to pool qi,
 // events to event buffer qi. Every lane of the wavefront must call it.
-__device__ void wave_fans(const RoundArgs& a, bool has, int v, double d, double th, bool full, int qi, u64& kmn,
-                          u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer, u32& notwin) {
+// The lane's corners are q0 .. q0 + deg - 1 of the CCW corner list (deg = 0
+// when it has no fan).
+__device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, double d, double th, bool full,
+                          int qi, u64& kmn, u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer, u32& notwin) {
   Ctl* c = a.ctl;
   const int lane = lane_id();
-  const int q0 = has ? a.m.coff[v] : 0;
-  const int deg = has ? a.m.coff[v + 1] - q0 : 0;
+  if (!has) deg = 0;
   int incl = deg;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
@@ -558,10 +603,12 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, double d, double 
     const double oth = shfl_d(th, owner);
     FanOut o;
     o.win = false;
-    o.nev = 0;
+    o.ea = o.eb = false;
     if (t < total) fan_corner(a, ov, od, oth, full, oq, o, tiny, ich, notwin);
-    const u64 jw = wave_reserve(&c->npool[qi], o.win ? 1u : 0u);
-    const u64 je = wave_reserve(&c->ndev[qi], (u32)o.nev);
+    const u32 nev = (o.ea ? 1u : 0u) + (o.eb ? 1u : 0u);
+    u64 jw, je, jz;
+    u32 tw, te, tz;
+    wave_reserve3(&c->npool[qi], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, jw, je, jz, tw, te, tz);
     if (o.win) {
       if (jw < (u64)a.cap) {
         store_window(P, jw, o.b0, o.b1, o.px, o.py, od, o.key, o.e, ov);
@@ -573,16 +620,26 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, double d, double 
       }
       kept++;
     }
-    for (int q = 0; q < o.nev; ++q) {
-      if (je + q < (u64)a.ecap) {
-        E.v[je + q] = o.ev_v[q];
-        E.d[je + q] = o.ev_d[q];
-        E.th[je + q] = o.ev_th[q];
+    if (o.ea) {
+      if (je < (u64)a.ecap) {
+        E.v[je] = o.va;
+        E.d[je] = o.da;
+        E.th[je] = o.tha;
+      } else {
+        flag_overflow(c);
+      }
+      je++;
+    }
+    if (o.eb) {
+      if (je < (u64)a.ecap) {
+        E.v[je] = o.vb;
+        E.d[je] = o.db;
+        E.th[je] = o.thb;
       } else {
         flag_overflow(c);
       }
     }
-    defer += (u32)o.nev;
+    defer += nev;
   }
 }
 
@@ -775,7 +832,10 @@ __global__ void __launch_bounds__(kBlock) k_init_fans(RoundArgs a, const int32_t
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i - lane_id() < m; i += gridDim.x * kBlock) {
     const bool has = i < m;
-    wave_fans(a, has, has ? src[i] : 0, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
+    const int v = has ? src[i] : 0;
+    const int q0 = has ? a.m.coff[v] : 0;
+    const int deg = has ? a.m.coff[v + 1] - q0 : 0;
+    wave_fans(a, has, v, q0, deg, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
   kmn = wave_min64(kmn);
   kmx = wave_max64(kmx);
@@ -948,10 +1008,12 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
     u32 ts, tk, tz;
     wave_reserve3(&c->nsel, sel ? 1u : 0u, &c->npool[1 - p], keep ? 1u : 0u, &c->nsel, 0u, js, jk, jz, ts, tk, tz);
     if (sel) {
-      if (js < (u64)a.cap)
+      if (js < (u64)a.cap) {
         store_window(S, js, b0, b1, px, py, sg, key, e, src);
-      else
+        if (a.org_shift >= 0) atomicAdd(&a.org_hist[e >> a.org_shift], 1u);
+      } else {
         flag_overflow(c);
+      }
     }
     if (keep) {
       if (jk < (u64)a.cap) {
@@ -990,7 +1052,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   Ctl* c = a.ctl;
   const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
   const u64 N = min(n_in, (u64)a.cap);
-  const Pool S = hop <= 1 ? a.sel : a.hq[hop & 1];
+  const Pool S = hop > 1 ? a.hq[hop & 1] : (a.org_shift >= 0 ? a.sorted : a.sel);
   const Pool Q = a.pool[1 - p];
   const bool to_hop = hop < a.hops;
   const Pool HQ = a.hq[(hop + 1) & 1];
@@ -1012,13 +1074,15 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
-    // outputs of this lane
-    int nk = 0;
-    double kb0[2], kb1[2], kpx[2], kpy[2], kkey[2];
-    int32_t ke[2];
-    int nd = 0;
-    int32_t dv[3];
-    double dd[3], dth[3];
+    // outputs of this lane, in fixed slots (no per-lane arrays, which would
+    // live in scratch memory): the left and right child, and the distance
+    // events at v0, v1 and v2
+    bool cl = false, cr = false;
+    double lb0 = 0, lb1 = 0, lpx = 0, lpy = 0, lkey = 0, rb0 = 0, rb1 = 0, rpx = 0, rpy = 0, rkey = 0;
+    int32_t le = 0, re = 0;
+    bool e0 = false, e1 = false, e2 = false;
+    int32_t ev0 = 0, ev1 = 0, ev2 = 0;
+    double ed0 = 0, ed1 = 0, ed2 = 0, et0 = 0, et1 = 0, et2 = 0;
     bool has_aev = false;
     double aD = 0, aX = 0;
     double sg = 0;
@@ -1028,7 +1092,11 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       sg = S.sg[i];
       e = S.e[i];
       src = S.src[i];
+      // everything that depends on e only, in one batch of loads
       const pch::HalfEdge h = m.he[e];
+      const pch::HalfEdgeAng ha = m.hang[e];
+      const u64 ad_bits = lda(&a.s.AD[e]);
+      const u64 ax_bits = lda(&a.s.AX[e]);
       const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
       const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
       const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
@@ -1038,24 +1106,23 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       const double X = px + (x2 - px) * t;
       if (!isfinite(X)) n_nonfin++;
       const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
-      const int en = he_next(e), ep = he_prev(e);
       if (b0 <= tol) {
         const double d = sg + sqrt(px * px + py * py);
         if (d < g0 * kEv) {
-          dv[nd] = v0;
-          dd[nd] = d;
-          dth[nd] = (m.flags[v0] & pch::VF_PSEUDO) ? m.phi[e] - dev_atan2(-py, px) : 0.0;
-          nd++;
+          e0 = true;
+          ev0 = v0;
+          ed0 = d;
+          et0 = (h.pflags & 1) ? ha.th0 - dev_atan2(-py, px) : 0.0;
         }
       }
       if (b1 >= L - tol) {
         const double dx = px - L;
         const double d = sg + sqrt(dx * dx + py * py);
         if (d < g1 * kEv) {
-          dv[nd] = v1;
-          dd[nd] = d;
-          dth[nd] = (m.flags[v1] & pch::VF_PSEUDO) ? (m.phi[en] + m.alpha[en]) + dev_atan2(-py, L - px) : 0.0;
-          nd++;
+          e1 = true;
+          ev1 = v1;
+          ed1 = d;
+          et1 = (h.pflags & 2) ? ha.th1 + dev_atan2(-py, L - px) : 0.0;
         }
       }
       bool doL = false, doR = false;
@@ -1064,22 +1131,22 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
         const double d2 = sg + sqrt(dx * dx + dy * dy);
         if (d2 < g2 * kEv) {
           double th = 0.0;
-          if (m.flags[v2] & pch::VF_PSEUDO) {
+          if (h.pflags & 4) {
             const double ux = -x2, uy = -y2, wx = px - x2, wy = py - y2;
             const double cr = ux * wy - uy * wx;
             const double dt = ux * wx + uy * wy;
-            th = m.phi[ep] + dev_atan2(cr, dt);
+            th = ha.th2 + dev_atan2(cr, dt);
           }
-          dv[nd] = v2;
-          dd[nd] = d2;
-          dth[nd] = th;
-          nd++;
+          e2 = true;
+          ev2 = v2;
+          ed2 = d2;
+          et2 = th;
         }
         if (!a.ch_on) {
           doL = doR = true;
         } else {
-          const double Ds = from_bits(lda(&a.s.AD[e]));
-          const double Xs = from_ordkey(lda(&a.s.AX[e]));
+          const double Ds = from_bits(ad_bits);
+          const double Xs = from_ordkey(ax_bits);
           if (d2 < Ds) {
             has_aev = true;
             aD = d2;
@@ -1132,13 +1199,13 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           } else if (r == 2) {
             n_ich++;
           } else {
-            kb0[nk] = c0;
-            kb1[nk] = c1;
-            kpx[nk] = cpx;
-            kpy[nk] = cpy;
-            kkey[nk] = window_key(c0, c1, cpx, cpy, sg);
-            ke[nk] = h.tl;
-            nk++;
+            cl = true;
+            lb0 = c0;
+            lb1 = c1;
+            lpx = cpx;
+            lpy = cpy;
+            lkey = window_key(c0, c1, cpx, cpy, sg);
+            le = h.tl;
           }
         }
       }
@@ -1178,62 +1245,63 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           } else if (r == 2) {
             n_ich++;
           } else {
-            kb0[nk] = c0;
-            kb1[nk] = c1;
-            kpx[nk] = cpx;
-            kpy[nk] = cpy;
-            kkey[nk] = window_key(c0, c1, cpx, cpy, sg);
-            ke[nk] = h.tr;
-            nk++;
+            cr = true;
+            rb0 = c0;
+            rb1 = c1;
+            rpx = cpx;
+            rpy = cpy;
+            rkey = window_key(c0, c1, cpx, cpy, sg);
+            re = h.tr;
           }
         }
       }
     }
     // children that pass the round's selection test go to the next hop
-    bool toq[2] = {false, false};
-    int nq = 0;
-    if (to_hop) {
-      for (int q = 0; q < nk; ++q) {
-        toq[q] = tab ? (kkey[q] <= cv) : (all || ((bits(kkey[q]) >> sh) <= T));
-        nq += toq[q] ? 1 : 0;
-      }
-    }
+    const bool ql = cl && to_hop && (tab ? (lkey <= cv) : (all || ((bits(lkey) >> sh) <= T)));
+    const bool qr = cr && to_hop && (tab ? (rkey <= cv) : (all || ((bits(rkey) >> sh) <= T)));
+    const int nk = (cl ? 1 : 0) + (cr ? 1 : 0);
+    const int nq = (ql ? 1 : 0) + (qr ? 1 : 0);
+    const int nd = (e0 ? 1 : 0) + (e1 ? 1 : 0) + (e2 ? 1 : 0);
     // append children, distance events and angle events (one reservation per
     // wavefront each)
-    u32 tk, td, ta, tq = 0;
-    u64 jk, jd, ja, jq = 0;
-    wave_reserve3(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, jk, jd, ja,
-                  tk, td, ta);
-    if (to_hop) jq = wave_reserve(nq_ctr, (u32)nq, &tq);
-    for (int q = 0; q < nk; ++q) {
-      if (toq[q]) {
+    u32 tk, td, ta, tq;
+    u64 jk, jd, ja, jq;
+    wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+                  (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
+    auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
+      if (toq) {
         const u64 j = jq++;
         if (j < (u64)a.cap)
-          store_window(HQ, j, kb0[q], kb1[q], kpx[q], kpy[q], sg, kkey[q], ke[q], src);
+          store_window(HQ, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
         else
           flag_overflow(c);
-        continue;
+        return;
       }
       const u64 j = jk++;
       if (j < (u64)a.cap) {
-        store_window(Q, j, kb0[q], kb1[q], kpx[q], kpy[q], sg, kkey[q], ke[q], src);
-        const u64 kb = bits(kkey[q]);
+        store_window(Q, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
+        const u64 kb = bits(ckey);
         kmn = kb < kmn ? kb : kmn;
         kmx = kb > kmx ? kb : kmx;
       } else {
         flag_overflow(c);
       }
-    }
-    for (int q = 0; q < nd; ++q) {
-      const u64 j = jd + q;
+    };
+    if (cl) put_child(ql, lb0, lb1, lpx, lpy, lkey, le);
+    if (cr) put_child(qr, rb0, rb1, rpx, rpy, rkey, re);
+    auto put_event = [&](int32_t v, double dv, double th) {
+      const u64 j = jd++;
       if (j < (u64)a.ecap) {
-        E.v[j] = dv[q];
-        E.d[j] = dd[q];
-        E.th[j] = dth[q];
+        E.v[j] = v;
+        E.d[j] = dv;
+        E.th[j] = th;
       } else {
         flag_overflow(c);
       }
-    }
+    };
+    if (e0) put_event(ev0, ed0, et0);
+    if (e1) put_event(ev1, ed1, et1);
+    if (e2) put_event(ev2, ed2, et2);
     if (has_aev) {
       if (ja < (u64)a.acap) {
         a.aev.e[ja] = e;
@@ -1262,6 +1330,52 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     if (n_ich) atomicAdd(&c->cnt[C_ICH], (u64)n_ich);
     if (n_notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)n_notwin);
     if (n_nonfin) atomicAdd(&c->nonfinite, (u64)n_nonfin);
+  }
+}
+
+// Organization by edge (Algorithm 3's reorganization, here as a one-pass
+// bucket sort): exclusive scan of the per-bucket counts of the selected
+// windows into slot offsets, clearing the counts for the next round.
+__global__ void __launch_bounds__(1024) k_org_scan(RoundArgs a) {
+  __shared__ u32 part[1024];
+  if (!a.ctl->active) return;
+  constexpr int per = kOrgBuckets / 1024;
+  u32 loc[per];
+  u32 sum = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    loc[i] = a.org_hist[threadIdx.x * per + i];
+    a.org_hist[threadIdx.x * per + i] = 0u;
+    sum += loc[i];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  u32 run = part[threadIdx.x] - sum;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    a.org_ofs[threadIdx.x * per + i] = run;
+    run += loc[i];
+  }
+}
+
+// Scatter of the selected windows into their bucket's slots: windows on
+// nearby half-edges (nearby faces) end up next to each other, so neighbouring
+// lanes of the propagation read neighbouring half-edge records and vertices.
+__global__ void __launch_bounds__(kBlock) k_org_scatter(RoundArgs a) {
+  Ctl* c = a.ctl;
+  if (!c->active) return;
+  const u64 N = min(c->nsel, (u64)a.cap);
+  const Pool S = a.sel, D = a.sorted;
+  for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+    const int32_t e = S.e[i];
+    const u64 j = atomicAdd(&a.org_ofs[e >> a.org_shift], 1u);
+    store_window(D, j, S.b0[i], S.b1[i], S.px[i], S.py[i], S.sg[i], S.key[i], e, S.src[i]);
   }
 }
 
@@ -1331,20 +1445,25 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
     const u64 i = j0 + w + nw * (u64)lane_id();
     bool has = false;
-    int v = 0;
+    int v = 0, q0 = 0, q1 = 0;
     double d = 0.0, th = 0.0;
     if (i < nd) {
       v = a.ev[p].v[i];
       d = a.ev[p].d[i];
       th = a.ev[p].th[i];
-      if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO) && ordkey(th) == lda(&a.s.fanth[v]) &&
-          atomicMax(&a.s.claim[v], stamp) < stamp) {
+      // everything that depends on v only, in one batch of loads
+      const u64 gv = lda(&a.s.g[v]);
+      const u64 fv = lda(&a.s.fanth[v]);
+      const uint8_t fl = a.m.flags[v];
+      q0 = a.m.coff[v];
+      q1 = a.m.coff[v + 1];
+      if (bits(d) == gv && (fl & pch::VF_PSEUDO) && ordkey(th) == fv && atomicMax(&a.s.claim[v], stamp) < stamp) {
         a.s.fanth[v] = kAllOnes;
         has = true;
         fans++;
       }
     }
-    wave_fans(a, has, v, d, th, a.full_fan != 0, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
+    wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
   kmn = wave_min64(kmn);
   kmx = wave_max64(kmx);
@@ -1447,10 +1566,12 @@ __device__ __noinline__ void nl_events1(const RoundArgs& a, int p, u64 t0, u64 s
 __device__ __noinline__ void nl_events2(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events2(a, p, t0, s); }
 __device__ __noinline__ void nl_events3(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events3(a, p, t0, s); }
 __device__ __noinline__ void nl_begin(const RoundArgs& a, int p) { round_begin(a, p); }
-__device__ __noinline__ void nl_init_fan(const RoundArgs& a, int v, Ctl* ctl) {
+__device__ __forceinline__ void init_fan(const RoundArgs& a, int v, Ctl* ctl) {
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
-  wave_fans(a, lane_id() == 0, v, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
+  const int q0 = a.m.coff[v];
+  wave_fans(a, lane_id() == 0, v, q0, a.m.coff[v + 1] - q0, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer,
+            notwin);
   kmn = wave_min64(kmn);
   kmx = wave_max64(kmx);
   if (lane_id() == 0) {
@@ -1458,9 +1579,39 @@ __device__ __noinline__ void nl_init_fan(const RoundArgs& a, int v, Ctl* ctl) {
     if (kmx != 0) atomicMax(&ctl->kmax[0], kmx);
   }
 }
+__device__ __noinline__ void nl_init_fan(const RoundArgs& a, int v, Ctl* ctl) { init_fan(a, v, ctl); }
+
+// Phases of the persistent kernel: 1024-thread teams (at most 128 VGPRs per
+// lane) call them out of line, each with its own register allocation;
+// 256-thread teams inline them into one allocation without spills.
+template <bool kOOL>
+struct TeamPhases {
+  static __device__ __forceinline__ void init_fan_(const RoundArgs& a, int v, Ctl* ctl) {
+    if constexpr (kOOL) nl_init_fan(a, v, ctl); else init_fan(a, v, ctl);
+  }
+  static __device__ __forceinline__ void begin(const RoundArgs& a, int p) {
+    if constexpr (kOOL) nl_begin(a, p); else round_begin(a, p);
+  }
+  static __device__ __forceinline__ void partition(const RoundArgs& a, int p, u64 t0, u64 s) {
+    if constexpr (kOOL) nl_partition(a, p, t0, s); else ph_partition(a, p, t0, s);
+  }
+  static __device__ __forceinline__ void propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 s) {
+    if constexpr (kOOL) nl_propagate(a, p, hop, t0, s); else ph_propagate(a, p, hop, t0, s);
+  }
+  static __device__ __forceinline__ void events1(const RoundArgs& a, int p, u64 t0, u64 s) {
+    if constexpr (kOOL) nl_events1(a, p, t0, s); else ph_events1(a, p, t0, s);
+  }
+  static __device__ __forceinline__ void events2(const RoundArgs& a, int p, u64 t0, u64 s) {
+    if constexpr (kOOL) nl_events2(a, p, t0, s); else ph_events2(a, p, t0, s);
+  }
+  static __device__ __forceinline__ void events3(const RoundArgs& a, int p, u64 t0, u64 s) {
+    if constexpr (kOOL) nl_events3(a, p, t0, s); else ph_events3(a, p, t0, s);
+  }
+};
 
 template <int BS>
 __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
+  using Ph = TeamPhases<(BS > 256)>;
   __shared__ Ctl ctl;
   __shared__ RoundArgs sa;
   __shared__ int cur;
@@ -1487,6 +1638,10 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.hq[0] = B.hops > 1 ? slot_pool(B, t, 3) : Pool{};
       a.hq[1] = B.hops > 1 ? slot_pool(B, t, 4) : Pool{};
       a.hops = B.hops;
+      a.org_shift = -1;  // fields of one workgroup are not organized by edge
+      a.sorted = Pool{};
+      a.org_hist = nullptr;
+      a.org_ofs = nullptr;
       for (int i = 0; i < 2; ++i) {
         const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
         a.ev[i] = DistEv{B.ev_v + o, B.ev_d + o, B.ev_th + o};
@@ -1530,29 +1685,29 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.s.AX[i] = kAllOnes;
     }
     team_sync();
-    if (threadIdx.x < (u32)kWave) nl_init_fan(a, B.field_src[f], &ctl);
+    if (threadIdx.x < (u32)kWave) Ph::init_fan_(a, B.field_src[f], &ctl);
     team_sync();
-    if (threadIdx.x < (u32)kWave) nl_begin(a, 0);
+    if (threadIdx.x < (u32)kWave) Ph::begin(a, 0);
     team_sync();
     int p = 0;
     while (!ctl.done) {
-      nl_partition(a, p, t0, stride);
+      Ph::partition(a, p, t0, stride);
       team_sync();
-      nl_propagate(a, p, 1, t0, stride);
+      Ph::propagate(a, p, 1, t0, stride);
       team_sync();
       for (int h = 2; h <= B.hops; ++h) {
         if (ctl.nhop[h - 1] == 0) break;
-        nl_propagate(a, p, h, t0, stride);
+        Ph::propagate(a, p, h, t0, stride);
         team_sync();
       }
-      nl_events1(a, p, t0, stride);
+      Ph::events1(a, p, t0, stride);
       team_sync();
-      nl_events2(a, p, t0, stride);
+      Ph::events2(a, p, t0, stride);
       team_sync();
-      nl_events3(a, p, t0, stride);
+      Ph::events3(a, p, t0, stride);
       team_sync();
       if (threadIdx.x < (u32)kWave) {
-        nl_begin(a, 1 - p);
+        Ph::begin(a, 1 - p);
         if (threadIdx.x == 0 && (int64_t)ctl.round > B.max_rounds) ctl.done = 1;
       }
       team_sync();
@@ -1596,6 +1751,7 @@ struct pch_mesh_s {
   double *phi = nullptr, *alpha = nullptr, *theta = nullptr;
   int32_t *twin = nullptr, *hv = nullptr, *coff = nullptr, *corner = nullptr;
   pch::Corner* crec = nullptr;
+  pch::HalfEdgeAng* hang = nullptr;
   uint8_t* flags = nullptr;
   // state (sized with the mesh)
   u64 *g = nullptr, *AD = nullptr, *AX = nullptr, *fanth = nullptr;
@@ -1606,6 +1762,9 @@ struct pch_mesh_s {
   Pool sel = {};
   Pool hq[2] = {};
   int64_t hq_cap = 0;
+  Pool sorted = {};
+  int64_t sorted_cap = 0;
+  u32 *org_hist = nullptr, *org_ofs = nullptr;
   DistEv ev[2] = {};
   AngEv aev = {};
   Ctl* ctl = nullptr;
@@ -1666,6 +1825,8 @@ void free_work(pch_mesh_s* M) {
   free_pool(M->hq[0]);
   free_pool(M->hq[1]);
   M->hq_cap = 0;
+  free_pool(M->sorted);
+  M->sorted_cap = 0;
   (void)hipFree(M->aev.e);
   (void)hipFree(M->aev.D);
   (void)hipFree(M->aev.X);
@@ -1714,6 +1875,7 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   HIP_TRY(dalloc(&M->hv, H.nh));
   HIP_TRY(dalloc(&M->corner, H.nh));
   HIP_TRY(dalloc(&M->crec, H.nh));
+  HIP_TRY(dalloc(&M->hang, H.nh));
   HIP_TRY(dalloc(&M->theta, H.nv));
   HIP_TRY(dalloc(&M->flags, H.nv));
   HIP_TRY(dalloc(&M->coff, H.nv + 1));
@@ -1731,6 +1893,7 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(M->hv, H.hv.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->corner, H.corner.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->crec, H.crec.data(), sizeof(pch::Corner) * H.nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(M->hang, H.hang.data(), sizeof(pch::HalfEdgeAng) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->theta, H.theta.data(), sizeof(double) * H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->flags, H.flags.data(), H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->coff, H.coff.data(), sizeof(int32_t) * (H.nv + 1), hipMemcpyHostToDevice, st));
@@ -1748,6 +1911,7 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->hv);
   (void)hipFree(M->corner);
   (void)hipFree(M->crec);
+  (void)hipFree(M->hang);
   (void)hipFree(M->theta);
   (void)hipFree(M->flags);
   (void)hipFree(M->coff);
@@ -1762,6 +1926,8 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->dtable);
   (void)hipFree(M->dcdf);
   (void)hipFree(M->dlog);
+  (void)hipFree(M->org_hist);
+  (void)hipFree(M->org_ofs);
 }
 
 pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
@@ -1779,7 +1945,7 @@ pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
 
 RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   RoundArgs a;
-  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec, M->hang};
   a.s = DevState{M->g, M->AD, M->AX, M->fanth, M->claim};
   a.pool[0] = M->pool[0];
   a.pool[1] = M->pool[1];
@@ -1787,6 +1953,15 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.hq[0] = M->hq[0];
   a.hq[1] = M->hq[1];
   a.hops = o.hops;
+  a.org_shift = -1;
+  if (o.organize) {
+    int bitlen = 0;
+    while (((M->host.nh - 1) >> bitlen) > 0) ++bitlen;
+    a.org_shift = bitlen > 12 ? bitlen - 12 : 0;  // (nh - 1) >> org_shift < kOrgBuckets
+  }
+  a.sorted = M->sorted;
+  a.org_hist = M->org_hist;
+  a.org_ofs = M->org_ofs;
   a.ev[0] = M->ev[0];
   a.ev[1] = M->ev[1];
   a.aev = M->aev;
@@ -1829,6 +2004,10 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
   if (kth)
     for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
   k_partition<<<pool_blocks, kBlock, 0, st>>>(a, p);
+  if (a.org_shift >= 0) {
+    k_org_scan<<<1, 1024, 0, st>>>(a);
+    k_org_scatter<<<prop_blocks, kBlock, 0, st>>>(a);
+  }
   if (ev0) (void)hipEventRecord(ev0, st);
   for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
   if (ev1) (void)hipEventRecord(ev1, st);
@@ -2032,6 +2211,16 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   for (;;) {
     pch_status s = ensure_work(M, cap, o.hops > 1);
     if (s != PCH_OK) return s;
+    if (o.organize && M->sorted_cap < M->cap) {
+      free_pool(M->sorted);
+      HIP_TRY(alloc_pool(M->sorted, M->cap));
+      M->sorted_cap = M->cap;
+      if (!M->org_hist) {
+        HIP_TRY(dalloc(&M->org_hist, kOrgBuckets));
+        HIP_TRY(dalloc(&M->org_ofs, kOrgBuckets));
+        HIP_TRY(hipMemsetAsync(M->org_hist, 0, sizeof(u32) * kOrgBuckets, st));
+      }
+    }
     RoundArgs a = make_args(M, o);
     a.pbin = pbin;
     const int fill_blocks = 1024;
@@ -2379,7 +2568,8 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   b->delta0.resize(n_meshes);
   for (int i = 0; i < n_meshes; ++i) {
     pch_mesh_s* M = meshes[i];
-    dm[i] = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+    dm[i] = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec,
+                    M->hang};
     nv[i] = M->host.nv;
     nh[i] = M->host.nh;
     double sum = 0.0;
@@ -2457,23 +2647,27 @@ pch_status pch_batch_field_stats(pch_batch b, int64_t* out) {
 
 pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen) {
   if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
-  const int64_t ks[] = {2048, 4096, 8192, 16384};
-  const int shapes[][2] = {{256, 2}, {256, 4}, {1024, 1}};  // team threads, teams per CU
+  const int64_t ks[] = {4096, 8192, 16384};
+  const int shapes[][2] = {{256, 1}, {256, 2}, {1024, 1}};  // team threads, teams per CU
+  const int hop_set[] = {1, 4};
   pch_batch_options best = b->o;
   double best_ms = INFINITY;
   for (const auto& sh : shapes) {
     for (int64_t k : ks) {
-      b->o.k = k;
-      b->o.team_threads = sh[0];
-      b->o.teams_per_cu = sh[1];
-      pch_status s = alloc_slots(b);
-      if (s != PCH_OK) return s;
-      pch_batch_stats st;
-      s = batch_run(b, dist, (hipStream_t)hip_stream, &st);
-      if (s != PCH_OK) return s;
-      if (st.ms_total < best_ms) {
-        best_ms = st.ms_total;
-        best = b->o;
+      for (int hops : hop_set) {
+        b->o.k = k;
+        b->o.team_threads = sh[0];
+        b->o.teams_per_cu = sh[1];
+        b->o.hops = hops;
+        pch_status s = alloc_slots(b);
+        if (s != PCH_OK) return s;
+        pch_batch_stats st;
+        s = batch_run(b, dist, (hipStream_t)hip_stream, &st);
+        if (s != PCH_OK) return s;
+        if (st.ms_total < best_ms) {
+          best_ms = st.ms_total;
+          best = b->o;
+        }
       }
     }
   }

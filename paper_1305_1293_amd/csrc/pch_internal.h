@@ -20,9 +20,19 @@ struct alignas(64) HalfEdge {
   int32_t v0, v1, v2;
   int32_t tl;  // twin(prev(e)): half-edge v0 -> v2 in the face across
   int32_t tr;  // twin(next(e)): half-edge v2 -> v1 in the face across
-  int32_t pad;
+  int32_t pflags;  // bits 0, 1, 2: v0, v1, v2 is a pseudo-source vertex
 };
 static_assert(sizeof(HalfEdge) == 64, "half-edge record must be 64 bytes");
+
+// Angular positions a window on half-edge e needs for the incoming angle of
+// its distance events (only read when the vertex is a pseudo-source): around
+// v0 the position of e, around v1 the position of v1 -> v0 (that of next(e)
+// plus its corner angle), around v2 the position of prev(e).
+struct alignas(32) HalfEdgeAng {
+  double th0, th1, th2;
+  double pad;
+};
+static_assert(sizeof(HalfEdgeAng) == 32, "half-edge angle record must be 32 bytes");
 
 // Everything a fan needs about one corner of a vertex v (outgoing half-edge
 // j = v -> a, face (v, a, b)), stored in CCW order per vertex so that a fan
@@ -56,6 +66,7 @@ struct HostMesh {
   std::vector<int32_t> coff;     // [nv + 1] CSR offsets of the CCW corner lists
   std::vector<int32_t> corner;   // [nh] outgoing half-edges in CCW order
   std::vector<Corner> crec;      // [nh] corner records in the same order
+  std::vector<HalfEdgeAng> hang; // [nh]
   int64_t n_boundary_he = 0, n_pseudo = 0;
 };
 

@@ -140,7 +140,7 @@ int build_host_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* 
     h.v2 = M.hv[p];
     h.tl = -1;
     h.tr = -1;
-    h.pad = 0;
+    h.pflags = 0;
     M.alpha[j] = std::atan2(h.y2, h.x2);
   }
   for (int64_t j = 0; j < nh; ++j) {
@@ -202,6 +202,16 @@ int build_host_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* 
     const bool pseudo = boundary || sum > two_pi + kSaddleExcess;
     M.flags[v] = (uint8_t)((boundary ? VF_BOUNDARY : 0) | (pseudo ? VF_PSEUDO : 0));
     M.n_pseudo += pseudo;
+  }
+  // pseudo-source bits and angular positions per half-edge (after every phi
+  // and vertex class is known)
+  M.hang.resize(nh);
+  for (int64_t j = 0; j < nh; ++j) {
+    const int32_t n = he_next((int32_t)j), p = he_prev((int32_t)j);
+    HalfEdge& h = M.he[j];
+    h.pflags = ((M.flags[h.v0] & VF_PSEUDO) ? 1 : 0) | ((M.flags[h.v1] & VF_PSEUDO) ? 2 : 0) |
+               ((M.flags[h.v2] & VF_PSEUDO) ? 4 : 0);
+    M.hang[j] = HalfEdgeAng{M.phi[j], M.phi[n] + M.alpha[n], M.phi[p], 0.0};
   }
   // corner records (after every phi is known)
   M.crec.resize(nh);

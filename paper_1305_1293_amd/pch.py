@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("pool_limit", ctypes.c_int64), ("collect_stats", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
                 ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("hops", ctypes.c_int32),
-                ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double)]
+                ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double),
+                ("organize", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

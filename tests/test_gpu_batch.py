@@ -99,3 +99,24 @@ def test_batch_argument_errors(pch, setup):
         pch.Batch(meshes, [0], [gens[0].nv])
     with pytest.raises(pch.PchError):
         pch.Batch(meshes, [len(meshes)], [0])
+
+
+def test_tune_keeps_fields_exact(pch, setup):
+    """The autotuner times its grid of (k, workgroup shape, hops) settings on the
+    batch and keeps the fastest; the batch then still equals the single-field
+    runs with the chosen k and hops, bit for bit."""
+    import torch
+    gens, meshes, fm, fs = setup
+    b = pch.Batch(meshes[:3], fm[fm < 3], fs[fm < 3], k=256, teams_per_cu=1)
+    out, _ = b.run()
+    chosen = b.tune(out)
+    say(f"tuned: {chosen}")
+    assert chosen["k"] in (4096, 8192, 16384) and chosen["hops"] in (1, 4)
+    assert (chosen["team_threads"], chosen["teams_per_cu"]) in ((256, 1), (256, 2), (1024, 1))
+    out, st = b.run(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for f in range(b.n_fields):
+        ref = single(pch, meshes[int(b.field_mesh[f])], int(b.field_source[f]), chosen["k"], chosen["hops"])
+        assert np.array_equal(got[b.offsets[f]:b.offsets[f + 1]].view(np.uint64), ref.view(np.uint64)), f
+    b.close()

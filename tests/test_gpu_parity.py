@@ -121,6 +121,24 @@ def test_round_log_matches_replica(pch, oracle, case):
     assert_close(d, ref, mean_edge(oracle, m), what=name)
 
 
+@pytest.mark.parametrize("hops", [1, 4])
+def test_organize_by_edge_changes_nothing(pch, oracle, hops):
+    """Grouping the selected windows by edge only reorders them: the per-round
+    records and the distance bits equal the unorganized run and the replica."""
+    for m, s, kw in [(G.config_mesh(1), 0, dict(k=1024)), (G.bumpy_icosphere(4, seed=9), 17, dict(k=512)),
+                     (G.bump_grid(48, seed=4), 100, dict(k=2048, select_mode=1, delta0=0.01))]:
+        say(f"organize by edge {m.name} source {s} {kw} hops {hops}")
+        d0, _, log0 = gpu_field(pch, m, [s], collect_stats=1, hops=hops, **kw)
+        d1, _, log1 = gpu_field(pch, m, [s], collect_stats=1, hops=hops, organize=1, **kw)
+        assert np.array_equal(log0, log1)
+        assert np.array_equal(d0.view(np.uint64), d1.view(np.uint64))
+        rkw = dict(k=kw["k"], hops=hops)
+        if "select_mode" in kw:
+            rkw.update(mode=1, delta0=kw["delta0"])
+        dr, _, log_r = oracle.replica(m, [s], **rkw)
+        assert np.array_equal(log1, log_r)
+
+
 def test_grazing_boundary_regression(pch, oracle):
     m = G.bump_grid(96, seed=23)
     say("bump grid 96 seed 23 (grazing convex boundary)")
