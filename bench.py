@@ -15,7 +15,15 @@ Prints one JSON line. Besides the headline (ms per field) it carries:
                  library's stream during the timed steps, against 8 TB/s;
   cpu_baseline - the CPU oracle (sequential ICH, one core) on a bounded
                  sample of the same workload, whose fields also check the
-                 first GPU fields.
+                 first GPU fields;
+  batched      - 512 fields (16 meshes of 20k-330k faces, 32 sources each)
+                 in one persistent launch against plain PCH (k-th-key
+                 selection, one face per round, k tuned per mesh) run field
+                 after field on a sample of the same fields.
+
+--workload learned prints a separate line for the learned selection cutoff:
+the network is trained on 200 fields of bumpy icospheres and sets the
+cutoffs on 1024 x 1024 bump grids, against plain PCH on the same fields.
 """
 from __future__ import annotations
 
@@ -47,7 +55,7 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload_tag: str):
+def traffic_from_profile(workload_tag: str, config_tag: str):
     """HBM bytes per propagation launch from the committed counter summary, or
     None when the summary is missing or the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", f"k_propagate_{workload_tag}_traffic.md")
@@ -56,9 +64,98 @@ def traffic_from_profile(workload_tag: str):
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != kernel_source_hash():
+    cfg = re.search(r"bench_config:\s*(.+)", text)
+    if not m or not b or not cfg or m.group(1) != kernel_source_hash() or cfg.group(1).strip() != config_tag:
         return None
     return float(b.group(1))
+
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, r
+
+
+def measure_batched(pch, G, torch):
+    """512 fields in one persistent launch against plain PCH field by field."""
+    gens = G.batch_meshes(3)
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
+    fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
+    opts = dict(k=16384, team_threads=256, teams_per_cu=1, hops=4)
+    b = pch.Batch(meshes, fm, fs, **opts)
+    out, _ = b.run()  # first run captures the graph
+    dt, (out, st) = _timed(torch, lambda: b.run(out))
+    batch_ms = 1000.0 * dt
+    windows = int(b.field_stats()[:, 2].sum())
+    got = out.cpu().numpy()
+    ks = (4096, 8192, 16384, 32768)
+    plain_ms, worst = 0.0, 0.0
+    for i, (g, dm) in enumerate(zip(gens, meshes)):
+        srcs = [int(x) for x in g.meta["sources"]]
+        times = {k: _timed(torch, lambda: pch.geodesic(dm, [srcs[0]], k=k, select_mode=0))[0] for k in ks}
+        kbest = min(times, key=times.get)
+        tt = 0.0
+        for j in (1, 2):
+            t, d = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=kbest, select_mode=0))
+            tt += t
+            f = i * 32 + j
+            ref = got[b.offsets[f]:b.offsets[f + 1]]
+            worst = max(worst, float(np.max(np.abs(d.cpu().numpy() - ref) / np.maximum(ref, 1e-3))))
+        plain_ms += 1000.0 * 32 * tt / 2
+    b.close()
+    for dm in meshes:
+        dm.close()
+    return {"fields": int(fm.size), "meshes": len(gens), "faces": [int(m.nf) for m in gens], "ms": round(batch_ms, 2),
+            "ms_per_field": round(batch_ms / fm.size, 4), "windows_per_s": round(windows / dt, 1), "options": opts,
+            "plain_ms_est": round(plain_ms, 1),
+            "plain": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on its first "
+                     "source; 2 more sources per mesh timed and scaled to 32",
+            "speedup_vs_plain": round(plain_ms / batch_ms, 3), "max_rel_diff_vs_plain": worst}
+
+
+def measure_learned(args, pch, G, torch):
+    """Learned selection cutoff against plain PCH on the 1024 x 1024 bump grids."""
+    from paper_1305_1293_amd import learned as Lr
+    train, test = G.learned_cutoff_sets(4)
+    t0 = time.perf_counter()
+    data, _ = Lr.build_training_set(train, k=8192)
+    mlp = pch.MLP(7)
+    losses = Lr.train(mlp, data, epochs=6, batch=16384, lr=2e-3, log_every=50)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    k = args.k_learned
+    rows = []
+    for g in test:
+        dm = pch.Mesh.from_generated(g)
+        xyz = torch.from_numpy(g.xyz).cuda()
+        for s in [int(x) for x in g.meta["sources"][:args.learned_sources]]:
+            tp, (dp, sp) = _timed(torch, lambda: pch.geodesic(dm, [s], k=k, select_mode=0, return_stats=True))
+            tl, (dl, sl) = _timed(torch, lambda: Lr.learned_geodesic(mlp, g, dm, xyz, s, k=k))
+            td, (dd, sd) = _timed(torch, lambda: pch.geodesic(dm, [s], k=k, select_mode=1, return_stats=True))
+            ref = dp.cpu().numpy()
+            err = float(np.max(np.abs(dl.cpu().numpy() - ref) / np.maximum(ref, 1e-3)))
+            rows.append((tp, tl, td, sp["rounds"], sl["rounds"], sd["rounds"], sp["processed"], sl["processed"], err))
+        dm.close()
+    a = np.array(rows)
+    plain_ms, learned_ms, step_ms = 1000 * a[:, 0].mean(), 1000 * a[:, 1].mean(), 1000 * a[:, 2].mean()
+    return {"metric": "learned-cutoff vs plain speedup (ms per exact single-source field)",
+            "value": round(plain_ms / learned_ms, 4), "unit": "x", "higher_is_better": True,
+            "n_gpus": 1, "dtype": "f64 fields, bf16/f32 network", "data": "synthetic",
+            "config": {"workload": "train: 200 fields of bumpy icospheres (levels 5 and 6, 20 meshes x 10 sources); "
+                                   "test: 1024 x 1024 bump grids (seeds 2, 20, 21), 2,093,058 faces",
+                       "fields": len(rows), "k": k, "hops": 1},
+            "ms_per_field": {"plain_kth": round(plain_ms, 2), "learned": round(learned_ms, 2),
+                             "adaptive_step": round(step_ms, 2)},
+            "rounds_per_field": {"plain_kth": float(a[:, 3].mean()), "learned": float(a[:, 4].mean()),
+                                 "adaptive_step": float(a[:, 5].mean())},
+            "windows_per_field": {"plain_kth": float(a[:, 6].mean()), "learned": float(a[:, 7].mean())},
+            "max_rel_diff_learned_vs_plain": float(a[:, 8].max()),
+            "training": {"samples": int(data.feats.shape[0]), "seconds": round(train_s, 2),
+                         "loss_first": losses[0], "loss_last": losses[-1]}}
 
 
 def main():
@@ -66,10 +163,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=8192, help="windows selected per round")
+    ap.add_argument("--workload", choices=["field", "learned"], default="field")
+    ap.add_argument("--k", type=int, default=16384, help="windows selected per round")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
-    ap.add_argument("--hops", type=int, default=1, help="propagation hops per round")
+    ap.add_argument("--hops", type=int, default=4, help="propagation hops per round")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-versus-plain measurement")
+    ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
+    ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
     ap.add_argument("--time-every", type=int, default=8,
                     help="time the propagation kernel of every n-th round with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
@@ -98,6 +199,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 8 * n, "copies": 5}), flush=True)
+        return
+    if args.workload == "learned":
+        print(json.dumps(measure_learned(args, pch, G, torch)), flush=True)
         return
     m = G.config_mesh(2)
     rng = np.random.default_rng(2024)
@@ -135,7 +239,7 @@ def main():
     all_launches = max(tot["rounds"] * args.hops, 1)
     bytes_per_launch = prop_bytes / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = traffic_from_profile("icosphere7")
+    traffic = traffic_from_profile("icosphere7", f"select={args.select} k={args.k} hops={args.hops}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_propagate", "avg_launch_us": round(avg_launch_s * 1e6, 3),
@@ -161,6 +265,8 @@ def main():
                "sample": f"{n} fields (the first timed sources) on the same mesh, sequential ICH on one core"}
         max_err = max(errs)
 
+    batched = None if args.no_batched else measure_batched(pch, G, torch)
+
     line = {
         "metric": "ms per exact single-source field",
         "value": round(ms_per_field, 4),
@@ -184,6 +290,7 @@ def main():
         "max_rel_err_vs_oracle": max_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     mesh.close()
