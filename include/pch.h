@@ -219,7 +219,7 @@ pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_ba
  * windows processed, windows created, fans, peak pool, stale windows, 0. */
 pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
 
-/* Autotuner: times k in {4096, 8192, 16384} with workgroup shapes
+/* Autotuner: times k in {8192, 16384, 32768, 65536} with workgroup shapes
  * (256 threads, 1 per CU), (256, 2) and (1024, 1) and 1 or 4 hops per round
  * on the whole batch (into dist), keeps the fastest in the batch and returns
  * it in chosen (may be NULL). */

@@ -643,6 +643,37 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
   }
 }
 
+// Workgroup totals of per-wave partial results, so that a phase issues one
+// atomic per workgroup and counter instead of one per wavefront (same-address
+// atomics serialize). Every thread of the workgroup must call it; the totals
+// are valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_totals(u64& kmn, u64& kmx, u32 (&v)[NV]) {
+  __shared__ u64 s_mn[16], s_mx[16];
+  __shared__ u32 s_v[NV][16];
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  kmn = wave_min64(kmn);
+  kmx = wave_max64(kmx);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  if (lane_id() == 0) {
+    s_mn[w] = kmn;
+    s_mx[w] = kmx;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s_v[j][w] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < nw; ++q) {
+      kmn = s_mn[q] < kmn ? s_mn[q] : kmn;
+      kmx = s_mx[q] > kmx ? s_mx[q] : kmx;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) v[j] += s_v[j][q];
+    }
+  }
+  __syncthreads();
+}
+
 // relaxed agent-scope load of a counter that other workgroups update atomically
 __device__ __forceinline__ u64 ld(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -971,10 +1002,24 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
 // pool buffer. Appends are reserved per wavefront.
 __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 N = min(c->npool[p], (u64)a.cap);
   const Pool P = a.pool[p];
   const Pool Q = a.pool[1 - p];
   const Pool S = a.sel;
+  // the lane's first window is loaded together with the round's counters
+  double f_b0 = 0, f_b1 = 0, f_px = 0, f_py = 0, f_sg = 0, f_key = 0;
+  int32_t f_e = 0, f_src = 0;
+  if (t0 < (u64)a.cap) {
+    f_b0 = P.b0[t0];
+    f_b1 = P.b1[t0];
+    f_px = P.px[t0];
+    f_py = P.py[t0];
+    f_sg = P.sg[t0];
+    f_key = P.key[t0];
+    f_e = P.e[t0];
+    f_src = P.src[t0];
+  }
+  const bool active = c->active != 0;
+  const u64 N = active ? min(c->npool[p], (u64)a.cap) : 0;
   const int s = (int)c->shift;
   const u64 T = c->want;
   const bool all = c->sel_all;
@@ -988,20 +1033,31 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
     double b0 = 0, b1 = 0, px = 0, py = 0, sg = 0, key = 0;
     int32_t e = 0, src = 0;
     if (valid) {
-      sg = P.sg[i];
-      src = P.src[i];
-      key = P.key[i];
+      if (i == t0) {
+        b0 = f_b0;
+        b1 = f_b1;
+        px = f_px;
+        py = f_py;
+        sg = f_sg;
+        key = f_key;
+        e = f_e;
+        src = f_src;
+      } else {
+        b0 = P.b0[i];
+        b1 = P.b1[i];
+        px = P.px[i];
+        py = P.py[i];
+        sg = P.sg[i];
+        key = P.key[i];
+        e = P.e[i];
+        src = P.src[i];
+      }
       const bool stale = sg > from_bits(lda(&a.s.g[src]));
       if (stale) {
         stale_n++;
       } else {
         sel = tab ? (key <= cv) : (all || ((bits(key) >> s) <= T));
         keep = !sel;
-        b0 = P.b0[i];
-        b1 = P.b1[i];
-        px = P.px[i];
-        py = P.py[i];
-        e = P.e[i];
       }
     }
     u64 js, jk, jz;
@@ -1026,18 +1082,16 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
       }
     }
   }
-  kmn = wave_min64(kmn);
-  kmx = wave_max64(kmx);
-  stale_n = wave_sum(stale_n);
-  if (lane_id() == 0) {
+  u32 tot[1] = {stale_n};
+  block_totals(kmn, kmx, tot);
+  if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (stale_n) atomicAdd(&c->cnt[C_STALE], (u64)stale_n);
+    if (tot[0]) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
-  if (!a.ctl->active) return;
   ph_partition(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
@@ -1050,9 +1104,23 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
 // not change the distances, and stale values only prune less.
 __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
-  const u64 N = min(n_in, (u64)a.cap);
   const Pool S = hop > 1 ? a.hq[hop & 1] : (a.org_shift >= 0 ? a.sorted : a.sel);
+  // The lane's first window is loaded together with the round's counters (an
+  // index below cap is always in bounds), so the two round trips overlap.
+  double f_b0 = 0, f_b1 = 0, f_px = 0, f_py = 0, f_sg = 0;
+  int32_t f_e = 0, f_src = 0;
+  if (t0 < (u64)a.cap) {
+    f_b0 = S.b0[t0];
+    f_b1 = S.b1[t0];
+    f_px = S.px[t0];
+    f_py = S.py[t0];
+    f_sg = S.sg[t0];
+    f_e = S.e[t0];
+    f_src = S.src[t0];
+  }
+  const bool active = c->active != 0;
+  const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
+  const u64 N = active ? min(n_in, (u64)a.cap) : 0;
   const Pool Q = a.pool[1 - p];
   const bool to_hop = hop < a.hops;
   const Pool HQ = a.hq[(hop + 1) & 1];
@@ -1065,13 +1133,13 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
-  if (t0 == 0) {
+  if (t0 == 0 && active) {
     if (hop <= 1)
       c->cnt[C_SEL] = n_in;
     else
       c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
   }
-  u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0;
+  u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
     // outputs of this lane, in fixed slots (no per-lane arrays, which would
@@ -1088,10 +1156,24 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     double sg = 0;
     int32_t src = 0, e = 0;
     if (i < N) {
-      const double b0 = S.b0[i], b1 = S.b1[i], px = S.px[i], py = S.py[i];
-      sg = S.sg[i];
-      e = S.e[i];
-      src = S.src[i];
+      double b0, b1, px, py;
+      if (i == t0) {
+        b0 = f_b0;
+        b1 = f_b1;
+        px = f_px;
+        py = f_py;
+        sg = f_sg;
+        e = f_e;
+        src = f_src;
+      } else {
+        b0 = S.b0[i];
+        b1 = S.b1[i];
+        px = S.px[i];
+        py = S.py[i];
+        sg = S.sg[i];
+        e = S.e[i];
+        src = S.src[i];
+      }
       // everything that depends on e only, in one batch of loads
       const pch::HalfEdge h = m.he[e];
       const pch::HalfEdgeAng ha = m.hang[e];
@@ -1311,25 +1393,25 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
         flag_overflow(c);
       }
     }
+    // wavefront totals (the same on every lane), counted once by lane 0
     if (lane_id() == 0) {
-      if (tk + tq) atomicAdd(&c->cnt[C_KIDS], (u64)(tk + tq));
-      if (td) atomicAdd(&c->cnt[C_DEV], (u64)td);
-      if (ta) atomicAdd(&c->cnt[C_AEV], (u64)ta);
+      n_kids += tk + tq;
+      n_dev += td;
+      n_aev += ta;
     }
   }
-  kmn = wave_min64(kmn);
-  kmx = wave_max64(kmx);
-  n_tiny = wave_sum(n_tiny);
-  n_ich = wave_sum(n_ich);
-  n_notwin = wave_sum(n_notwin);
-  n_nonfin = wave_sum(n_nonfin);
-  if (lane_id() == 0) {
+  u32 tot[7] = {n_tiny, n_ich, n_notwin, n_nonfin, n_kids, n_dev, n_aev};
+  block_totals(kmn, kmx, tot);
+  if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (n_tiny) atomicAdd(&c->cnt[C_TINY], (u64)n_tiny);
-    if (n_ich) atomicAdd(&c->cnt[C_ICH], (u64)n_ich);
-    if (n_notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)n_notwin);
-    if (n_nonfin) atomicAdd(&c->nonfinite, (u64)n_nonfin);
+    if (tot[0]) atomicAdd(&c->cnt[C_TINY], (u64)tot[0]);
+    if (tot[1]) atomicAdd(&c->cnt[C_ICH], (u64)tot[1]);
+    if (tot[2]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[2]);
+    if (tot[3]) atomicAdd(&c->nonfinite, (u64)tot[3]);
+    if (tot[4]) atomicAdd(&c->cnt[C_KIDS], (u64)tot[4]);
+    if (tot[5]) atomicAdd(&c->cnt[C_DEV], (u64)tot[5]);
+    if (tot[6]) atomicAdd(&c->cnt[C_AEV], (u64)tot[6]);
   }
 }
 
@@ -1380,24 +1462,52 @@ __global__ void __launch_bounds__(kBlock) k_org_scatter(RoundArgs a) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int hop) {
-  if (!a.ctl->active) return;
   ph_propagate(a, p, hop, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
 // Algorithm 4, first pass: geod_dist and the angle_split distance take the
 // minimum over this round's events (keys: vertex, oriented edge).
+// The lane's first distance event and first angle event, loaded together
+// with the round's counters (indices below the capacities are in bounds).
+struct FirstEvents {
+  int32_t v, e;
+  double d, th, D, X;
+};
+
+__device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u64 t0) {
+  FirstEvents f{0, 0, 0.0, 0.0, 0.0, 0.0};
+  if (t0 < (u64)a.ecap) {
+    f.v = a.ev[p].v[t0];
+    f.d = a.ev[p].d[t0];
+    f.th = a.ev[p].th[t0];
+  }
+  if (t0 < (u64)a.acap) {
+    f.e = a.aev.e[t0];
+    f.D = a.aev.D[t0];
+    f.X = a.aev.X[t0];
+  }
+  return f;
+}
+
 __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 nd = min(c->ndev[p], (u64)a.ecap);
-  const u64 na = min(c->naev, (u64)a.acap);
-  for (u64 i = t0; i < nd; i += stride)
-    atomicMin(&a.s.g[a.ev[p].v[i]], bits(a.ev[p].d[i]));
-  for (u64 i = t0; i < na; i += stride)
-    atomicMin(&a.s.AD[a.aev.e[i]], bits(a.aev.D[i]));
+  const FirstEvents f = first_events(a, p, t0);
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
+  for (u64 i = t0; i < nd; i += stride) {
+    const int32_t v = i == t0 ? f.v : a.ev[p].v[i];
+    const double d = i == t0 ? f.d : a.ev[p].d[i];
+    atomicMin(&a.s.g[v], bits(d));
+  }
+  for (u64 i = t0; i < na; i += stride) {
+    const int32_t e = i == t0 ? f.e : a.aev.e[i];
+    const double D = i == t0 ? f.D : a.aev.D[i];
+    atomicMin(&a.s.AD[e], bits(D));
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
-  if (!a.ctl->active) return;
   ph_events1(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
@@ -1406,21 +1516,24 @@ __global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
 // events that reached its new distance.
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 nd = min(c->ndev[p], (u64)a.ecap);
-  const u64 na = min(c->naev, (u64)a.acap);
+  const FirstEvents f = first_events(a, p, t0);
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   for (u64 i = t0; i < na; i += stride) {
-    const int e = a.aev.e[i];
-    if (bits(a.aev.D[i]) == lda(&a.s.AD[e])) a.s.AX[e] = kAllOnes;
+    const int32_t e = i == t0 ? f.e : a.aev.e[i];
+    const double D = i == t0 ? f.D : a.aev.D[i];
+    if (bits(D) == lda(&a.s.AD[e])) a.s.AX[e] = kAllOnes;
   }
   for (u64 i = t0; i < nd; i += stride) {
-    const int v = a.ev[p].v[i];
-    if (bits(a.ev[p].d[i]) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO))
-      atomicMin(&a.s.fanth[v], ordkey(a.ev[p].th[i]));
+    const int32_t v = i == t0 ? f.v : a.ev[p].v[i];
+    const double d = i == t0 ? f.d : a.ev[p].d[i];
+    const double th = i == t0 ? f.th : a.ev[p].th[i];
+    if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO)) atomicMin(&a.s.fanth[v], ordkey(th));
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
-  if (!a.ctl->active) return;
   ph_events2(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
@@ -1429,28 +1542,55 @@ __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
 // into the next round's event buffer.
 __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const u64 nd = min(c->ndev[p], (u64)a.ecap);
-  const u64 na = min(c->naev, (u64)a.acap);
-  for (u64 i = t0; i < na; i += stride) {
-    const int e = a.aev.e[i];
-    if (bits(a.aev.D[i]) == lda(&a.s.AD[e])) atomicMin(&a.s.AX[e], ordkey(a.aev.X[i]));
-  }
-  const u32 stamp = (u32)c->round;
-  u64 kmn = kAllOnes, kmx = 0;
-  u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
-  // Events are dealt round-robin over the launch's wavefronts (event
+  // Distance events are dealt round-robin over the launch's wavefronts (event
   // w + nw * lane of each stride-wide chunk to lane `lane` of wavefront w), so
   // the few fans of a round spread over many compute units.
   const u64 nw = stride / kWave, w = t0 / kWave;
+  const u64 i0 = w + nw * (u64)lane_id();
+  // the lane's first angle event and first distance event are loaded
+  // together with the round's counters (indices below the capacities are in
+  // bounds)
+  int32_t fa_e = 0;
+  double fa_D = 0.0, fa_X = 0.0;
+  if (t0 < (u64)a.acap) {
+    fa_e = a.aev.e[t0];
+    fa_D = a.aev.D[t0];
+    fa_X = a.aev.X[t0];
+  }
+  int32_t f_v = 0;
+  double f_d = 0.0, f_th = 0.0;
+  if (i0 < (u64)a.ecap) {
+    f_v = a.ev[p].v[i0];
+    f_d = a.ev[p].d[i0];
+    f_th = a.ev[p].th[i0];
+  }
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
+  const u32 stamp = (u32)c->round;
+  for (u64 i = t0; i < na; i += stride) {
+    const int e = i == t0 ? fa_e : a.aev.e[i];
+    const double D = i == t0 ? fa_D : a.aev.D[i];
+    const double X = i == t0 ? fa_X : a.aev.X[i];
+    if (bits(D) == lda(&a.s.AD[e])) atomicMin(&a.s.AX[e], ordkey(X));
+  }
+  u64 kmn = kAllOnes, kmx = 0;
+  u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
-    const u64 i = j0 + w + nw * (u64)lane_id();
+    const u64 i = j0 + i0;
     bool has = false;
     int v = 0, q0 = 0, q1 = 0;
     double d = 0.0, th = 0.0;
     if (i < nd) {
-      v = a.ev[p].v[i];
-      d = a.ev[p].d[i];
-      th = a.ev[p].th[i];
+      if (j0 == 0) {
+        v = f_v;
+        d = f_d;
+        th = f_th;
+      } else {
+        v = a.ev[p].v[i];
+        d = a.ev[p].d[i];
+        th = a.ev[p].th[i];
+      }
       // everything that depends on v only, in one batch of loads
       const u64 gv = lda(&a.s.g[v]);
       const u64 fv = lda(&a.s.fanth[v]);
@@ -1465,21 +1605,16 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
     }
     wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
-  kmn = wave_min64(kmn);
-  kmx = wave_max64(kmx);
-  kept = wave_sum(kept);
-  tiny = wave_sum(tiny);
-  ich = wave_sum(ich);
-  fans = wave_sum(fans);
-  notwin = wave_sum(notwin);
-  if (lane_id() == 0) {
+  u32 tot[5] = {kept, tiny, ich, fans, notwin};
+  block_totals(kmn, kmx, tot);
+  if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (kept) atomicAdd(&c->cnt[C_FANWIN], (u64)kept);
-    if (tiny) atomicAdd(&c->cnt[C_TINY], (u64)tiny);
-    if (ich) atomicAdd(&c->cnt[C_ICH], (u64)ich);
-    if (fans) atomicAdd(&c->cnt[C_FANS], (u64)fans);
-    if (notwin) atomicAdd(&c->xcnt[X_NOTWIN], (u64)notwin);
+    if (tot[0]) atomicAdd(&c->cnt[C_FANWIN], (u64)tot[0]);
+    if (tot[1]) atomicAdd(&c->cnt[C_TINY], (u64)tot[1]);
+    if (tot[2]) atomicAdd(&c->cnt[C_ICH], (u64)tot[2]);
+    if (tot[3]) atomicAdd(&c->cnt[C_FANS], (u64)tot[3]);
+    if (tot[4]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[4]);
   }
 }
 
@@ -1487,7 +1622,6 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
 __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
   __shared__ int is_last;
   Ctl* c = a.ctl;
-  if (!c->active) return;
   ph_events3(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
   __threadfence();
   __syncthreads();
@@ -2647,7 +2781,7 @@ pch_status pch_batch_field_stats(pch_batch b, int64_t* out) {
 
 pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen) {
   if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
-  const int64_t ks[] = {4096, 8192, 16384};
+  const int64_t ks[] = {8192, 16384, 32768, 65536};
   const int shapes[][2] = {{256, 1}, {256, 2}, {1024, 1}};  // team threads, teams per CU
   const int hop_set[] = {1, 4};
   pch_batch_options best = b->o;
