@@ -186,7 +186,7 @@ typedef struct {
   int64_t pool_capacity; /* windows per workgroup; 0 = from the largest mesh */
   int32_t use_graph;     /* 1 = replay a captured HIP graph of the launch (default) */
   int32_t team_threads;  /* threads of the workgroup that runs one field: 256
-                            (default) or 1024 */
+                            (default), 512 or 1024 */
   int32_t hops;          /* as pch_options.hops (default 1) */
   int32_t pad;
 } pch_batch_options;
@@ -216,11 +216,13 @@ pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_ba
 
 /* Per-field record of the last run, host int64 [n_fields][8]: status (0 ok,
  * 1 rerun after pool overflow, 2 rerun after the round limit), rounds,
- * windows processed, windows created, fans, peak pool, stale windows, 0. */
+ * windows processed, windows created, fans, peak pool, stale windows, and
+ * the time the field took in its workgroup in ticks of the device's
+ * constant-rate wall clock (100 MHz on MI355X; 0 after a rerun). */
 pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
 
 /* Autotuner: times k in {8192, 16384, 32768, 65536} with workgroup shapes
- * (256 threads, 1 per CU), (256, 2) and (1024, 1) and 1 or 4 hops per round
+ * (256 threads, 1 per CU), (512, 1) and (1024, 1) and 1 or 4 hops per round
  * on the whole batch (into dist), keeps the fastest in the batch and returns
  * it in chosen (may be NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);

@@ -111,9 +111,16 @@ struct Ctl {
   u64 pad[8];
 };
 
+// A pool of windows (Section 3, Figure 2): the interval [b0, b1] of
+// half-edge e, the pseudo-source (px, py) in e's frame, its distance sg from
+// the source, the selection key and the pseudo-source vertex src, stored as
+// four arrays of pairs so that a wavefront moves each pair with one fully
+// coalesced 16-byte (8-byte for (e, src)) access per lane.
 struct Pool {
-  double *b0, *b1, *px, *py, *sg, *key;
-  int32_t *e, *src;
+  double2* bb;  // (b0, b1)
+  double2* pp;  // (px, py)
+  double2* sk;  // (sg, key)
+  int2* es;     // (e, src)
 };
 
 struct DistEv {
@@ -211,79 +218,28 @@ __device__ __forceinline__ u64 shfl64(u64 x, int src) {
   return ((u64)hi << 32) | lo;
 }
 
-// Exclusive prefix sum of n over the wavefront and one atomicAdd by the last
-// lane: returns this lane's first slot in the buffer counted by ctr. Every lane
-// of the wavefront must call it.
-__device__ __forceinline__ u64 wave_reserve(u64* ctr, u32 n, u32* total_out = nullptr) {
-  const int lane = lane_id();
-  u32 incl = n;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    u32 y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
-  }
-  const u32 total = __shfl(incl, kWave - 1, kWave);
-  u64 base = 0;
-  if (lane == kWave - 1 && total) base = atomicAdd(ctr, (u64)total);
-  base = shfl64(base, kWave - 1);
-  if (total_out) *total_out = total;
-  return base + (incl - n);
-}
-
-// Three reservations at once: the last lane issues the three atomics back to
-// back so their round trips overlap.
-__device__ __forceinline__ void wave_reserve3(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64& s0, u64& s1,
-                                              u64& s2, u32& t0, u32& t1, u32& t2) {
-  const int lane = lane_id();
-  u32 i0 = n0, i1 = n1, i2 = n2;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const u32 y0 = __shfl_up(i0, o, kWave);
-    const u32 y1 = __shfl_up(i1, o, kWave);
-    const u32 y2 = __shfl_up(i2, o, kWave);
-    if (lane >= o) {
-      i0 += y0;
-      i1 += y1;
-      i2 += y2;
-    }
-  }
-  t0 = __shfl(i0, kWave - 1, kWave);
-  t1 = __shfl(i1, kWave - 1, kWave);
-  t2 = __shfl(i2, kWave - 1, kWave);
-  u64 b0 = 0, b1 = 0, b2 = 0;
-  if (lane == kWave - 1) {
-    if (t0) b0 = atomicAdd(c0, (u64)t0);
-    if (t1) b1 = atomicAdd(c1, (u64)t1);
-    if (t2) b2 = atomicAdd(c2, (u64)t2);
-  }
-  s0 = shfl64(b0, kWave - 1) + (i0 - n0);
-  s1 = shfl64(b1, kWave - 1) + (i1 - n1);
-  s2 = shfl64(b2, kWave - 1) + (i2 - n2);
-}
-
-// Four reservations at once (the fourth may be unused: n3 = 0 on every lane).
+// Up to four reservations from one prefix sum: the last lane issues the
+// atomics back to back so that their round trips overlap. Every per-lane
+// count is at most 3, so the four counts travel packed in the bytes of one
+// 32-bit word (a wavefront's totals stay below 256). Every lane of the
+// wavefront must call it; counters with a zero total get no atomic.
 __device__ __forceinline__ void wave_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64* c3, u32 n3,
                                               u64& s0, u64& s1, u64& s2, u64& s3, u32& t0, u32& t1, u32& t2,
                                               u32& t3) {
   const int lane = lane_id();
-  u32 i0 = n0, i1 = n1, i2 = n2, i3 = n3;
+  const u32 x = n0 | (n1 << 8) | (n2 << 16) | (n3 << 24);
+  u32 incl = x;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const u32 y0 = __shfl_up(i0, o, kWave);
-    const u32 y1 = __shfl_up(i1, o, kWave);
-    const u32 y2 = __shfl_up(i2, o, kWave);
-    const u32 y3 = __shfl_up(i3, o, kWave);
-    if (lane >= o) {
-      i0 += y0;
-      i1 += y1;
-      i2 += y2;
-      i3 += y3;
-    }
+    const u32 y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
   }
-  t0 = __shfl(i0, kWave - 1, kWave);
-  t1 = __shfl(i1, kWave - 1, kWave);
-  t2 = __shfl(i2, kWave - 1, kWave);
-  t3 = __shfl(i3, kWave - 1, kWave);
+  const u32 tot = __shfl(incl, kWave - 1, kWave);
+  const u32 excl = incl - x;
+  t0 = tot & 0xffu;
+  t1 = (tot >> 8) & 0xffu;
+  t2 = (tot >> 16) & 0xffu;
+  t3 = tot >> 24;
   u64 b0 = 0, b1 = 0, b2 = 0, b3 = 0;
   if (lane == kWave - 1) {
     if (t0) b0 = atomicAdd(c0, (u64)t0);
@@ -291,10 +247,18 @@ __device__ __forceinline__ void wave_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, 
     if (t2) b2 = atomicAdd(c2, (u64)t2);
     if (t3) b3 = atomicAdd(c3, (u64)t3);
   }
-  s0 = shfl64(b0, kWave - 1) + (i0 - n0);
-  s1 = shfl64(b1, kWave - 1) + (i1 - n1);
-  s2 = shfl64(b2, kWave - 1) + (i2 - n2);
-  s3 = shfl64(b3, kWave - 1) + (i3 - n3);
+  s0 = shfl64(b0, kWave - 1) + (excl & 0xffu);
+  s1 = shfl64(b1, kWave - 1) + ((excl >> 8) & 0xffu);
+  s2 = shfl64(b2, kWave - 1) + ((excl >> 16) & 0xffu);
+  s3 = shfl64(b3, kWave - 1) + (excl >> 24);
+}
+
+// Three reservations (per-lane counts at most 3), as wave_reserve4.
+__device__ __forceinline__ void wave_reserve3(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64& s0, u64& s1,
+                                              u64& s2, u32& t0, u32& t1, u32& t2) {
+  u64 s3;
+  u32 t3;
+  wave_reserve4(c0, n0, c1, n1, c2, n2, c0, 0u, s0, s1, s2, s3, t0, t1, t2, t3);
 }
 
 __device__ __forceinline__ u32 wave_sum(u32 x) {
@@ -420,14 +384,10 @@ __device__ __forceinline__ int child_filter(double c0, double c1, double cpx, do
 
 __device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, double b1, double px, double py,
                                              double sg, double key, int32_t e, int32_t src) {
-  P.b0[i] = b0;
-  P.b1[i] = b1;
-  P.px[i] = px;
-  P.py[i] = py;
-  P.sg[i] = sg;
-  P.key[i] = key;
-  P.e[i] = e;
-  P.src[i] = src;
+  P.bb[i] = make_double2(b0, b1);
+  P.pp[i] = make_double2(px, py);
+  P.sk[i] = make_double2(sg, key);
+  P.es[i] = make_int2(e, src);
 }
 
 __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1ull); }
@@ -940,9 +900,9 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   const int s = (int)c->shift;
   const int lo = 24 - 12 * pass;
   const u64 want = c->want;
-  const double* key = a.pool[p].key;
+  const double2* sk = a.pool[p].sk;
   for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
-    const u64 t = bits(key[i]) >> s;
+    const u64 t = bits(sk[i].y) >> s;
     if ((t >> (lo + 12)) == want) atomicAdd(&h[(t >> lo) & (kHistBins - 1)], 1u);
   }
   __syncthreads();
@@ -1006,17 +966,13 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
   const Pool Q = a.pool[1 - p];
   const Pool S = a.sel;
   // the lane's first window is loaded together with the round's counters
-  double f_b0 = 0, f_b1 = 0, f_px = 0, f_py = 0, f_sg = 0, f_key = 0;
-  int32_t f_e = 0, f_src = 0;
+  double2 f_bb = make_double2(0, 0), f_pp = f_bb, f_sk = f_bb;
+  int2 f_es = make_int2(0, 0);
   if (t0 < (u64)a.cap) {
-    f_b0 = P.b0[t0];
-    f_b1 = P.b1[t0];
-    f_px = P.px[t0];
-    f_py = P.py[t0];
-    f_sg = P.sg[t0];
-    f_key = P.key[t0];
-    f_e = P.e[t0];
-    f_src = P.src[t0];
+    f_bb = P.bb[t0];
+    f_pp = P.pp[t0];
+    f_sk = P.sk[t0];
+    f_es = P.es[t0];
   }
   const bool active = c->active != 0;
   const u64 N = active ? min(c->npool[p], (u64)a.cap) : 0;
@@ -1033,25 +989,18 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
     double b0 = 0, b1 = 0, px = 0, py = 0, sg = 0, key = 0;
     int32_t e = 0, src = 0;
     if (valid) {
-      if (i == t0) {
-        b0 = f_b0;
-        b1 = f_b1;
-        px = f_px;
-        py = f_py;
-        sg = f_sg;
-        key = f_key;
-        e = f_e;
-        src = f_src;
-      } else {
-        b0 = P.b0[i];
-        b1 = P.b1[i];
-        px = P.px[i];
-        py = P.py[i];
-        sg = P.sg[i];
-        key = P.key[i];
-        e = P.e[i];
-        src = P.src[i];
-      }
+      const double2 wbb = i == t0 ? f_bb : P.bb[i];
+      const double2 wpp = i == t0 ? f_pp : P.pp[i];
+      const double2 wsk = i == t0 ? f_sk : P.sk[i];
+      const int2 wes = i == t0 ? f_es : P.es[i];
+      b0 = wbb.x;
+      b1 = wbb.y;
+      px = wpp.x;
+      py = wpp.y;
+      sg = wsk.x;
+      key = wsk.y;
+      e = wes.x;
+      src = wes.y;
       const bool stale = sg > from_bits(lda(&a.s.g[src]));
       if (stale) {
         stale_n++;
@@ -1107,16 +1056,13 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const Pool S = hop > 1 ? a.hq[hop & 1] : (a.org_shift >= 0 ? a.sorted : a.sel);
   // The lane's first window is loaded together with the round's counters (an
   // index below cap is always in bounds), so the two round trips overlap.
-  double f_b0 = 0, f_b1 = 0, f_px = 0, f_py = 0, f_sg = 0;
-  int32_t f_e = 0, f_src = 0;
+  double2 f_bb = make_double2(0, 0), f_pp = f_bb, f_sk = f_bb;
+  int2 f_es = make_int2(0, 0);
   if (t0 < (u64)a.cap) {
-    f_b0 = S.b0[t0];
-    f_b1 = S.b1[t0];
-    f_px = S.px[t0];
-    f_py = S.py[t0];
-    f_sg = S.sg[t0];
-    f_e = S.e[t0];
-    f_src = S.src[t0];
+    f_bb = S.bb[t0];
+    f_pp = S.pp[t0];
+    f_sk = S.sk[t0];
+    f_es = S.es[t0];
   }
   const bool active = c->active != 0;
   const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
@@ -1156,24 +1102,14 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     double sg = 0;
     int32_t src = 0, e = 0;
     if (i < N) {
-      double b0, b1, px, py;
-      if (i == t0) {
-        b0 = f_b0;
-        b1 = f_b1;
-        px = f_px;
-        py = f_py;
-        sg = f_sg;
-        e = f_e;
-        src = f_src;
-      } else {
-        b0 = S.b0[i];
-        b1 = S.b1[i];
-        px = S.px[i];
-        py = S.py[i];
-        sg = S.sg[i];
-        e = S.e[i];
-        src = S.src[i];
-      }
+      const double2 wbb = i == t0 ? f_bb : S.bb[i];
+      const double2 wpp = i == t0 ? f_pp : S.pp[i];
+      const double2 wsk = i == t0 ? f_sk : S.sk[i];
+      const int2 wes = i == t0 ? f_es : S.es[i];
+      const double b0 = wbb.x, b1 = wbb.y, px = wpp.x, py = wpp.y;
+      sg = wsk.x;
+      e = wes.x;
+      src = wes.y;
       // everything that depends on e only, in one batch of loads
       const pch::HalfEdge h = m.he[e];
       const pch::HalfEdgeAng ha = m.hang[e];
@@ -1269,7 +1205,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           double c0 = s0 * l02, c1 = s1 * l02;
           if (c0 < 0.0) c0 = 0.0;
           if (c1 > l02) c1 = l02;
-          const double ux = x2 / l02, uy = y2 / l02;
+          const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
           const double cpx = ux * px + uy * py;
           double cpy = ux * py - uy * px;
           if (cpy > 0.0) cpy = 0.0;
@@ -1314,7 +1250,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           double c0 = r0 * l12, c1 = r1 * l12;
           if (c0 < 0.0) c0 = 0.0;
           if (c1 > l12) c1 = l12;
-          const double ux = ex / l12, uy = (-y2) / l12;
+          const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
           const double qx = px - x2, qy = py - y2;
           const double cpx = ux * qx + uy * qy;
           double cpy = ux * qy - uy * qx;
@@ -1455,9 +1391,12 @@ __global__ void __launch_bounds__(kBlock) k_org_scatter(RoundArgs a) {
   const u64 N = min(c->nsel, (u64)a.cap);
   const Pool S = a.sel, D = a.sorted;
   for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
-    const int32_t e = S.e[i];
-    const u64 j = atomicAdd(&a.org_ofs[e >> a.org_shift], 1u);
-    store_window(D, j, S.b0[i], S.b1[i], S.px[i], S.py[i], S.sg[i], S.key[i], e, S.src[i]);
+    const int2 es = S.es[i];
+    const u64 j = atomicAdd(&a.org_ofs[es.x >> a.org_shift], 1u);
+    D.bb[j] = S.bb[i];
+    D.pp[j] = S.pp[i];
+    D.sk[j] = S.sk[i];
+    D.es[j] = es;
   }
 }
 
@@ -1653,8 +1592,8 @@ struct BatchDev {
   int64_t* fstat;             // [n_fields][kFieldStat]
   u64* queue;                 // next position in order
   // per-team buffers (team t uses slot t)
-  double *pb0, *pb1, *ppx, *ppy, *psg, *pkey;  // [n_teams][3][cap]: pool 0, pool 1, selection
-  int32_t *pe, *psrc;
+  double2 *pbb, *ppp, *psk;  // [n_teams][nslot][cap]: pool 0, pool 1, selection, hop queues
+  int2* pes;
   int32_t* ev_v;  // [n_teams][2][ecap]
   double *ev_d, *ev_th;
   int32_t* ae_e;  // [n_teams][acap]
@@ -1671,7 +1610,7 @@ struct BatchDev {
   int64_t max_rounds;
 };
 
-constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak pool, stale, reserved
+constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak pool, stale, team time
 
 // Barrier between the phases of one workgroup's field. Values updated with
 // device-scope atomics are read with agent-scope loads (lda), so the barrier
@@ -1683,7 +1622,7 @@ __device__ __forceinline__ void team_sync() {
 
 __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
   const int64_t o = ((int64_t)t * B.nslot + b) * B.cap;
-  return Pool{B.pb0 + o, B.pb1 + o, B.ppx + o, B.ppy + o, B.psg + o, B.pkey + o, B.pe + o, B.psrc + o};
+  return Pool{B.pbb + o, B.ppp + o, B.psk + o, B.pes + o};
 }
 
 // Persistent workgroups: each takes the next field from the queue and runs
@@ -1717,7 +1656,8 @@ __device__ __noinline__ void nl_init_fan(const RoundArgs& a, int v, Ctl* ctl) { 
 
 // Phases of the persistent kernel: 1024-thread teams (at most 128 VGPRs per
 // lane) call them out of line, each with its own register allocation;
-// 256-thread teams inline them into one allocation without spills.
+// 256- and 512-thread teams (up to 512 and 256 VGPRs) inline them into one
+// allocation without spills.
 template <bool kOOL>
 struct TeamPhases {
   static __device__ __forceinline__ void init_fan_(const RoundArgs& a, int v, Ctl* ctl) {
@@ -1745,7 +1685,7 @@ struct TeamPhases {
 
 template <int BS>
 __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
-  using Ph = TeamPhases<(BS > 256)>;
+  using Ph = TeamPhases<(BS > 512)>;
   __shared__ Ctl ctl;
   __shared__ RoundArgs sa;
   __shared__ int cur;
@@ -1759,6 +1699,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     __syncthreads();
     const int f = cur;
     if (f < 0) break;
+    const u64 t_start = wall_clock64();
     const int mi = B.field_mesh[f];
     const int64_t nv = B.mesh_nv[mi], nh = B.mesh_nh[mi];
     if (threadIdx.x == 0) {
@@ -1858,7 +1799,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       st[4] = (int64_t)ctl.tot[C_FANS];
       st[5] = (int64_t)ctl.peak;
       st[6] = (int64_t)ctl.tot[C_STALE];
-      st[7] = 0;
+      st[7] = (int64_t)(wall_clock64() - t_start);
     }
     team_sync();
   }
@@ -1928,21 +1869,16 @@ hipError_t dalloc(T** p, int64_t n) {
 }
 
 void free_pool(Pool& P) {
-  (void)hipFree(P.b0);
-  (void)hipFree(P.b1);
-  (void)hipFree(P.px);
-  (void)hipFree(P.py);
-  (void)hipFree(P.sg);
-  (void)hipFree(P.key);
-  (void)hipFree(P.e);
-  (void)hipFree(P.src);
+  (void)hipFree(P.bb);
+  (void)hipFree(P.pp);
+  (void)hipFree(P.sk);
+  (void)hipFree(P.es);
   P = Pool{};
 }
 
 hipError_t alloc_pool(Pool& P, int64_t n) {
   hipError_t e;
-  if ((e = dalloc(&P.b0, n)) || (e = dalloc(&P.b1, n)) || (e = dalloc(&P.px, n)) || (e = dalloc(&P.py, n)) ||
-      (e = dalloc(&P.sg, n)) || (e = dalloc(&P.key, n)) || (e = dalloc(&P.e, n)) || (e = dalloc(&P.src, n)))
+  if ((e = dalloc(&P.bb, n)) || (e = dalloc(&P.pp, n)) || (e = dalloc(&P.sk, n)) || (e = dalloc(&P.es, n)))
     return e;
   return hipSuccess;
 }
@@ -2491,8 +2427,7 @@ namespace {
 void free_slots(pch_batch_s* b) {
   if (!b->slots) return;
   BatchDev& B = b->B;
-  for (void* p : {(void*)B.pb0, (void*)B.pb1, (void*)B.ppx, (void*)B.ppy, (void*)B.psg, (void*)B.pkey, (void*)B.pe,
-                  (void*)B.psrc, (void*)B.ev_v, (void*)B.ev_d, (void*)B.ev_th, (void*)B.ae_e, (void*)B.ae_D,
+  for (void* p : {(void*)B.pbb, (void*)B.ppp, (void*)B.psk, (void*)B.pes, (void*)B.ev_v, (void*)B.ev_d, (void*)B.ev_th, (void*)B.ae_e, (void*)B.ae_D,
                   (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.AD, (void*)B.AX})
     (void)hipFree(p);
   b->slots = false;
@@ -2520,14 +2455,10 @@ pch_status alloc_slots(pch_batch_s* b) {
   B.hops = b->o.hops;
   B.nslot = B.hops > 1 ? 5 : 3;
   const int64_t np = T * B.nslot * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
-  HIP_TRY(dalloc(&B.pb0, np));
-  HIP_TRY(dalloc(&B.pb1, np));
-  HIP_TRY(dalloc(&B.ppx, np));
-  HIP_TRY(dalloc(&B.ppy, np));
-  HIP_TRY(dalloc(&B.psg, np));
-  HIP_TRY(dalloc(&B.pkey, np));
-  HIP_TRY(dalloc(&B.pe, np));
-  HIP_TRY(dalloc(&B.psrc, np));
+  HIP_TRY(dalloc(&B.pbb, np));
+  HIP_TRY(dalloc(&B.ppp, np));
+  HIP_TRY(dalloc(&B.psk, np));
+  HIP_TRY(dalloc(&B.pes, np));
   HIP_TRY(dalloc(&B.ev_v, ne));
   HIP_TRY(dalloc(&B.ev_d, ne));
   HIP_TRY(dalloc(&B.ev_th, ne));
@@ -2554,6 +2485,8 @@ void enqueue_batch(pch_batch_s* b, hipStream_t st) {
   k_reset_queue<<<1, 1, 0, st>>>(b->d_queue);
   if (b->o.team_threads == 1024)
     k_batch<1024><<<b->n_teams, 1024, 0, st>>>(b->B);
+  else if (b->o.team_threads == 512)
+    k_batch<512><<<b->n_teams, 512, 0, st>>>(b->B);
   else
     k_batch<kBlock><<<b->n_teams, kBlock, 0, st>>>(b->B);
 }
@@ -2607,6 +2540,7 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
     fs[4] = s1.fans;
     fs[5] = s1.peak_pool;
     fs[6] = s1.stale;
+    fs[7] = 0;
     reruns++;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
@@ -2666,7 +2600,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   pch_batch_options_default(&o);
   if (opts) o = *opts;
   if (o.hops == 0) o.hops = 1;
-  if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 1024) ||
+  if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 512 && o.team_threads != 1024) ||
       o.hops < 1 || o.hops > kMaxHops)
     return set_err(PCH_EINVAL, "bad batch option");
   int dev = 0;
@@ -2782,7 +2716,7 @@ pch_status pch_batch_field_stats(pch_batch b, int64_t* out) {
 pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen) {
   if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
   const int64_t ks[] = {8192, 16384, 32768, 65536};
-  const int shapes[][2] = {{256, 1}, {256, 2}, {1024, 1}};  // team threads, teams per CU
+  const int shapes[][2] = {{256, 1}, {512, 1}, {1024, 1}};  // team threads, teams per CU
   const int hop_set[] = {1, 4};
   pch_batch_options best = b->o;
   double best_ms = INFINITY;

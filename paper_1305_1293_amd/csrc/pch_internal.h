@@ -24,15 +24,19 @@ struct alignas(64) HalfEdge {
 };
 static_assert(sizeof(HalfEdge) == 64, "half-edge record must be 64 bytes");
 
-// Angular positions a window on half-edge e needs for the incoming angle of
-// its distance events (only read when the vertex is a pseudo-source): around
-// v0 the position of e, around v1 the position of v1 -> v0 (that of next(e)
-// plus its corner angle), around v2 the position of prev(e).
-struct alignas(32) HalfEdgeAng {
+// Per-half-edge constants of the propagation beyond the frame itself.
+// th0, th1, th2: the angular positions a window on half-edge e needs for the
+// incoming angle of its distance events (only read when the vertex is a
+// pseudo-source): around v0 the position of e, around v1 the position of
+// v1 -> v0 (that of next(e) plus its corner angle), around v2 the position of
+// prev(e). (ulx, uly) = (x2, y2) / l02 and (urx, ury) = (L - x2, -y2) / l12:
+// the unit vectors along the two edges a window's children live on.
+struct alignas(64) HalfEdgeAng {
   double th0, th1, th2;
+  double ulx, uly, urx, ury;
   double pad;
 };
-static_assert(sizeof(HalfEdgeAng) == 32, "half-edge angle record must be 32 bytes");
+static_assert(sizeof(HalfEdgeAng) == 64, "half-edge constant record must be 64 bytes");
 
 // Everything a fan needs about one corner of a vertex v (outgoing half-edge
 // j = v -> a, face (v, a, b)), stored in CCW order per vertex so that a fan

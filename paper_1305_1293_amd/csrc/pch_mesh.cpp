@@ -211,7 +211,10 @@ int build_host_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* 
     HalfEdge& h = M.he[j];
     h.pflags = ((M.flags[h.v0] & VF_PSEUDO) ? 1 : 0) | ((M.flags[h.v1] & VF_PSEUDO) ? 2 : 0) |
                ((M.flags[h.v2] & VF_PSEUDO) ? 4 : 0);
-    M.hang[j] = HalfEdgeAng{M.phi[j], M.phi[n] + M.alpha[n], M.phi[p], 0.0};
+    // the same divisions the propagation would make per window
+    M.hang[j] = HalfEdgeAng{M.phi[j],          M.phi[n] + M.alpha[n],  M.phi[p],
+                            h.x2 / h.l02,      h.y2 / h.l02,           (h.L - h.x2) / h.l12,
+                            (-h.y2) / h.l12,   0.0};
   }
   // corner records (after every phi is known)
   M.crec.resize(nh);
