@@ -123,9 +123,15 @@ struct Pool {
   int2* es;     // (e, src)
 };
 
+// Distance events: vertex v reached at distance d, and the incoming angle a
+// fan at a pseudo-source needs. An event from propagation stores how to get
+// the angle, q = 4 e + k for vertex k of half-edge e and (x, y) the window's
+// pseudo-source in e's frame; the second event pass evaluates it for the
+// events that win their vertex and stores it back as q = -1, x = angle.
 struct DistEv {
-  int32_t* v;
-  double *d, *th;
+  int2* vq;     // (v, q)
+  double* d;
+  double2* xy;
 };
 
 struct AngEv {
@@ -392,6 +398,22 @@ __device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, do
 
 __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1ull); }
 
+// Incoming angle of a propagation event (q = 4 e + k, pseudo-source (px, py)
+// in e's frame): the angular position around vertex k of half-edge e of the
+// direction back towards the pseudo-source.
+__device__ __forceinline__ double event_angle(const DevMesh& m, int q, double px, double py) {
+  const int e = q >> 2, k = q & 3;
+  const pch::HalfEdge h = m.he[e];
+  const pch::HalfEdgeAng ha = m.hang[e];
+  if (k == 0) return ha.th0 - dev_atan2(-py, px);
+  if (k == 1) return ha.th1 + dev_atan2(-py, h.L - px);
+  const double x2 = h.x2, y2 = h.y2;
+  const double ux = -x2, uy = -y2, wx = px - x2, wy = py - y2;
+  const double cr = ux * wy - uy * wx;
+  const double dt = ux * wx + uy * wy;
+  return ha.th2 + dev_atan2(cr, dt);
+}
+
 // One corner of a fan of windows from pseudo-source vertex v reached at
 // distance d, the incoming ray's back direction at angular position th
 // (Figure 3(c)). A corner that meets the sector of directions at least pi away
@@ -582,9 +604,9 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
     }
     if (o.ea) {
       if (je < (u64)a.ecap) {
-        E.v[je] = o.va;
+        E.vq[je] = make_int2(o.va, -1);
         E.d[je] = o.da;
-        E.th[je] = o.tha;
+        E.xy[je] = make_double2(o.tha, 0.0);
       } else {
         flag_overflow(c);
       }
@@ -592,9 +614,9 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
     }
     if (o.eb) {
       if (je < (u64)a.ecap) {
-        E.v[je] = o.vb;
+        E.vq[je] = make_int2(o.vb, -1);
         E.d[je] = o.db;
-        E.th[je] = o.thb;
+        E.xy[je] = make_double2(o.thb, 0.0);
       } else {
         flag_overflow(c);
       }
@@ -1096,7 +1118,8 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     int32_t le = 0, re = 0;
     bool e0 = false, e1 = false, e2 = false;
     int32_t ev0 = 0, ev1 = 0, ev2 = 0;
-    double ed0 = 0, ed1 = 0, ed2 = 0, et0 = 0, et1 = 0, et2 = 0;
+    double ed0 = 0, ed1 = 0, ed2 = 0, epx = 0, epy = 0;
+    int32_t eq0 = -1, eq1 = -1, eq2 = -1;  // angle recipes (see DistEv)
     bool has_aev = false;
     double aD = 0, aX = 0;
     double sg = 0;
@@ -1107,6 +1130,8 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       const double2 wsk = i == t0 ? f_sk : S.sk[i];
       const int2 wes = i == t0 ? f_es : S.es[i];
       const double b0 = wbb.x, b1 = wbb.y, px = wpp.x, py = wpp.y;
+      epx = px;
+      epy = py;
       sg = wsk.x;
       e = wes.x;
       src = wes.y;
@@ -1130,7 +1155,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           e0 = true;
           ev0 = v0;
           ed0 = d;
-          et0 = (h.pflags & 1) ? ha.th0 - dev_atan2(-py, px) : 0.0;
+          eq0 = (h.pflags & 1) ? (e << 2) : -1;
         }
       }
       if (b1 >= L - tol) {
@@ -1140,7 +1165,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
           e1 = true;
           ev1 = v1;
           ed1 = d;
-          et1 = (h.pflags & 2) ? ha.th1 + dev_atan2(-py, L - px) : 0.0;
+          eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
         }
       }
       bool doL = false, doR = false;
@@ -1148,17 +1173,10 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
         const double dx = x2 - px, dy = y2 - py;
         const double d2 = sg + sqrt(dx * dx + dy * dy);
         if (d2 < g2 * kEv) {
-          double th = 0.0;
-          if (h.pflags & 4) {
-            const double ux = -x2, uy = -y2, wx = px - x2, wy = py - y2;
-            const double cr = ux * wy - uy * wx;
-            const double dt = ux * wx + uy * wy;
-            th = ha.th2 + dev_atan2(cr, dt);
-          }
           e2 = true;
           ev2 = v2;
           ed2 = d2;
-          et2 = th;
+          eq2 = (h.pflags & 4) ? ((e << 2) | 2) : -1;
         }
         if (!a.ch_on) {
           doL = doR = true;
@@ -1307,19 +1325,21 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     };
     if (cl) put_child(ql, lb0, lb1, lpx, lpy, lkey, le);
     if (cr) put_child(qr, rb0, rb1, rpx, rpy, rkey, re);
-    auto put_event = [&](int32_t v, double dv, double th) {
+    // the incoming angle of an event at a pseudo-source is evaluated later,
+    // only for the events that win their vertex (event_angle)
+    auto put_event = [&](int32_t v, double dv, int32_t q) {
       const u64 j = jd++;
       if (j < (u64)a.ecap) {
-        E.v[j] = v;
+        E.vq[j] = make_int2(v, q);
         E.d[j] = dv;
-        E.th[j] = th;
+        E.xy[j] = q >= 0 ? make_double2(epx, epy) : make_double2(0.0, 0.0);
       } else {
         flag_overflow(c);
       }
     };
-    if (e0) put_event(ev0, ed0, et0);
-    if (e1) put_event(ev1, ed1, et1);
-    if (e2) put_event(ev2, ed2, et2);
+    if (e0) put_event(ev0, ed0, eq0);
+    if (e1) put_event(ev1, ed1, eq1);
+    if (e2) put_event(ev2, ed2, eq2);
     if (has_aev) {
       if (ja < (u64)a.acap) {
         a.aev.e[ja] = e;
@@ -1409,16 +1429,19 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int ho
 // The lane's first distance event and first angle event, loaded together
 // with the round's counters (indices below the capacities are in bounds).
 struct FirstEvents {
-  int32_t v, e;
-  double d, th, D, X;
+  int2 vq;
+  double d;
+  double2 xy;
+  int32_t e;
+  double D, X;
 };
 
 __device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u64 t0) {
-  FirstEvents f{0, 0, 0.0, 0.0, 0.0, 0.0};
+  FirstEvents f{make_int2(0, -1), 0.0, make_double2(0.0, 0.0), 0, 0.0, 0.0};
   if (t0 < (u64)a.ecap) {
-    f.v = a.ev[p].v[t0];
+    f.vq = a.ev[p].vq[t0];
     f.d = a.ev[p].d[t0];
-    f.th = a.ev[p].th[t0];
+    f.xy = a.ev[p].xy[t0];
   }
   if (t0 < (u64)a.acap) {
     f.e = a.aev.e[t0];
@@ -1435,7 +1458,7 @@ __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u6
   const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
   const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   for (u64 i = t0; i < nd; i += stride) {
-    const int32_t v = i == t0 ? f.v : a.ev[p].v[i];
+    const int32_t v = i == t0 ? f.vq.x : a.ev[p].vq[i].x;
     const double d = i == t0 ? f.d : a.ev[p].d[i];
     atomicMin(&a.s.g[v], bits(d));
   }
@@ -1465,10 +1488,20 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     if (bits(D) == lda(&a.s.AD[e])) a.s.AX[e] = kAllOnes;
   }
   for (u64 i = t0; i < nd; i += stride) {
-    const int32_t v = i == t0 ? f.v : a.ev[p].v[i];
+    const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
     const double d = i == t0 ? f.d : a.ev[p].d[i];
-    const double th = i == t0 ? f.th : a.ev[p].th[i];
-    if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO)) atomicMin(&a.s.fanth[v], ordkey(th));
+    const double2 xy = i == t0 ? f.xy : a.ev[p].xy[i];
+    const int32_t v = vq.x;
+    if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO)) {
+      double th = xy.x;
+      if (vq.y >= 0) {
+        // evaluate the angle of a winning event and keep it for the fan pass
+        th = event_angle(a.m, vq.y, xy.x, xy.y);
+        a.ev[p].vq[i] = make_int2(v, -1);
+        a.ev[p].xy[i] = make_double2(th, 0.0);
+      }
+      atomicMin(&a.s.fanth[v], ordkey(th));
+    }
   }
 }
 
@@ -1499,9 +1532,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   int32_t f_v = 0;
   double f_d = 0.0, f_th = 0.0;
   if (i0 < (u64)a.ecap) {
-    f_v = a.ev[p].v[i0];
+    f_v = a.ev[p].vq[i0].x;
     f_d = a.ev[p].d[i0];
-    f_th = a.ev[p].th[i0];
+    f_th = a.ev[p].xy[i0].x;
   }
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
@@ -1526,9 +1559,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
         d = f_d;
         th = f_th;
       } else {
-        v = a.ev[p].v[i];
+        v = a.ev[p].vq[i].x;
         d = a.ev[p].d[i];
-        th = a.ev[p].th[i];
+        th = a.ev[p].xy[i].x;  // set by the second pass for every candidate
       }
       // everything that depends on v only, in one batch of loads
       const u64 gv = lda(&a.s.g[v]);
@@ -1594,8 +1627,9 @@ struct BatchDev {
   // per-team buffers (team t uses slot t)
   double2 *pbb, *ppp, *psk;  // [n_teams][nslot][cap]: pool 0, pool 1, selection, hop queues
   int2* pes;
-  int32_t* ev_v;  // [n_teams][2][ecap]
-  double *ev_d, *ev_th;
+  int2* ev_vq;  // [n_teams][2][ecap]
+  double* ev_d;
+  double2* ev_xy;
   int32_t* ae_e;  // [n_teams][acap]
   double *ae_D, *ae_X;
   u64 *g, *fanth;  // [n_teams][max_nv]
@@ -1719,7 +1753,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.org_ofs = nullptr;
       for (int i = 0; i < 2; ++i) {
         const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
-        a.ev[i] = DistEv{B.ev_v + o, B.ev_d + o, B.ev_th + o};
+        a.ev[i] = DistEv{B.ev_vq + o, B.ev_d + o, B.ev_xy + o};
       }
       const int64_t oa = (int64_t)t * B.acap;
       a.aev = AngEv{B.ae_e + oa, B.ae_D + oa, B.ae_X + oa};
@@ -1886,9 +1920,9 @@ hipError_t alloc_pool(Pool& P, int64_t n) {
 void free_work(pch_mesh_s* M) {
   for (int i = 0; i < 2; ++i) {
     free_pool(M->pool[i]);
-    (void)hipFree(M->ev[i].v);
+    (void)hipFree(M->ev[i].vq);
     (void)hipFree(M->ev[i].d);
-    (void)hipFree(M->ev[i].th);
+    (void)hipFree(M->ev[i].xy);
     M->ev[i] = DistEv{};
   }
   free_pool(M->sel);
@@ -1917,9 +1951,9 @@ pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
   const int64_t ecap = 4 * cap, acap = cap;
   for (int i = 0; i < 2; ++i) {
     HIP_TRY(alloc_pool(M->pool[i], cap));
-    HIP_TRY(dalloc(&M->ev[i].v, ecap));
+    HIP_TRY(dalloc(&M->ev[i].vq, ecap));
     HIP_TRY(dalloc(&M->ev[i].d, ecap));
-    HIP_TRY(dalloc(&M->ev[i].th, ecap));
+    HIP_TRY(dalloc(&M->ev[i].xy, ecap));
   }
   HIP_TRY(alloc_pool(M->sel, cap));
   if (hop_queues) {
@@ -1938,6 +1972,8 @@ pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
 
 pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   const pch::HostMesh& H = M->host;
+  // distance events name their half-edge as 4 e + k in 32 bits
+  if (H.nh >= ((int64_t)1 << 29)) return set_err(PCH_EINVAL, "mesh too large: at most 2^29 - 1 half-edges");
   HIP_TRY(dalloc(&M->he, H.nh));
   HIP_TRY(dalloc(&M->phi, H.nh));
   HIP_TRY(dalloc(&M->alpha, H.nh));
@@ -2427,7 +2463,7 @@ namespace {
 void free_slots(pch_batch_s* b) {
   if (!b->slots) return;
   BatchDev& B = b->B;
-  for (void* p : {(void*)B.pbb, (void*)B.ppp, (void*)B.psk, (void*)B.pes, (void*)B.ev_v, (void*)B.ev_d, (void*)B.ev_th, (void*)B.ae_e, (void*)B.ae_D,
+  for (void* p : {(void*)B.pbb, (void*)B.ppp, (void*)B.psk, (void*)B.pes, (void*)B.ev_vq, (void*)B.ev_d, (void*)B.ev_xy, (void*)B.ae_e, (void*)B.ae_D,
                   (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.AD, (void*)B.AX})
     (void)hipFree(p);
   b->slots = false;
@@ -2459,9 +2495,9 @@ pch_status alloc_slots(pch_batch_s* b) {
   HIP_TRY(dalloc(&B.ppp, np));
   HIP_TRY(dalloc(&B.psk, np));
   HIP_TRY(dalloc(&B.pes, np));
-  HIP_TRY(dalloc(&B.ev_v, ne));
+  HIP_TRY(dalloc(&B.ev_vq, ne));
   HIP_TRY(dalloc(&B.ev_d, ne));
-  HIP_TRY(dalloc(&B.ev_th, ne));
+  HIP_TRY(dalloc(&B.ev_xy, ne));
   HIP_TRY(dalloc(&B.ae_e, na));
   HIP_TRY(dalloc(&B.ae_D, na));
   HIP_TRY(dalloc(&B.ae_X, na));
