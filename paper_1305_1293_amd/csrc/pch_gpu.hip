@@ -139,8 +139,22 @@ struct AngEv {
   double *D, *X;
 };
 
+// The half-edge record and its constants share one 128-byte cache line, so a
+// window's propagation gathers one line for its half-edge.
+struct alignas(128) HalfEdgeLine {
+  pch::HalfEdge h;
+  pch::HalfEdgeAng a;
+};
+static_assert(sizeof(HalfEdgeLine) == 128, "half-edge line must be 128 bytes");
+
+// angle_split of one corner (oriented edge): the best apex distance (bit
+// pattern) and its crossing (order-preserving key), side by side in 16 bytes.
+struct alignas(16) Split {
+  u64 D, X;
+};
+
 struct DevMesh {
-  const pch::HalfEdge* he;
+  const HalfEdgeLine* hl;
   const double* phi;
   const double* alpha;
   const int32_t* twin;
@@ -150,13 +164,11 @@ struct DevMesh {
   const int32_t* coff;
   const int32_t* corner;
   const pch::Corner* crec;
-  const pch::HalfEdgeAng* hang;
 };
 
 struct DevState {
   u64* g;      // geod_dist as bit patterns (non-negative doubles order as u64)
-  u64* AD;     // angle_split distance to the apex (bit pattern)
-  u64* AX;     // angle_split apex crossing (order-preserving key)
+  Split* as;   // angle_split per oriented edge
   u64* fanth;  // smallest incoming angle key among this round's winning events
   u32* claim;  // round stamp of the last fan expanded at a vertex
 };
@@ -403,8 +415,8 @@ __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1
 // direction back towards the pseudo-source.
 __device__ __forceinline__ double event_angle(const DevMesh& m, int q, double px, double py) {
   const int e = q >> 2, k = q & 3;
-  const pch::HalfEdge h = m.he[e];
-  const pch::HalfEdgeAng ha = m.hang[e];
+  const pch::HalfEdge h = m.hl[e].h;
+  const pch::HalfEdgeAng ha = m.hl[e].a;
   if (k == 0) return ha.th0 - dev_atan2(-py, px);
   if (k == 1) return ha.th1 + dev_atan2(-py, h.L - px);
   const double x2 = h.x2, y2 = h.y2;
@@ -828,6 +840,11 @@ __global__ void k_fill_u64(u64* p, int64_t n, u64 v) {
     p[i] = v;
 }
 
+__global__ void k_fill_split(Split* p, int64_t n, u64 d, u64 x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = Split{d, x};
+}
+
 __global__ void k_fill_u32(u32* p, int64_t n, u32 v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1136,10 +1153,10 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       e = wes.x;
       src = wes.y;
       // everything that depends on e only, in one batch of loads
-      const pch::HalfEdge h = m.he[e];
-      const pch::HalfEdgeAng ha = m.hang[e];
-      const u64 ad_bits = lda(&a.s.AD[e]);
-      const u64 ax_bits = lda(&a.s.AX[e]);
+      const pch::HalfEdge h = m.hl[e].h;
+      const pch::HalfEdgeAng ha = m.hl[e].a;
+      const u64 ad_bits = lda(&a.s.as[e].D);
+      const u64 ax_bits = lda(&a.s.as[e].X);
       const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
       const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
       const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
@@ -1465,7 +1482,7 @@ __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u6
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
-    atomicMin(&a.s.AD[e], bits(D));
+    atomicMin(&a.s.as[e].D, bits(D));
   }
 }
 
@@ -1485,7 +1502,7 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
-    if (bits(D) == lda(&a.s.AD[e])) a.s.AX[e] = kAllOnes;
+    if (bits(D) == lda(&a.s.as[e].D)) a.s.as[e].X = kAllOnes;
   }
   for (u64 i = t0; i < nd; i += stride) {
     const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
@@ -1544,7 +1561,7 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
     const int e = i == t0 ? fa_e : a.aev.e[i];
     const double D = i == t0 ? fa_D : a.aev.D[i];
     const double X = i == t0 ? fa_X : a.aev.X[i];
-    if (bits(D) == lda(&a.s.AD[e])) atomicMin(&a.s.AX[e], ordkey(X));
+    if (bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
   }
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
@@ -1634,7 +1651,7 @@ struct BatchDev {
   double *ae_D, *ae_X;
   u64 *g, *fanth;  // [n_teams][max_nv]
   u32* claim;      // [n_teams][max_nv]
-  u64 *AD, *AX;    // [n_teams][max_nh]
+  Split* as;       // [n_teams][max_nh]
   int64_t cap, ecap, acap, max_nv, max_nh;
   int64_t k;
   double eps;
@@ -1739,7 +1756,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     if (threadIdx.x == 0) {
       RoundArgs a;
       a.m = B.meshes[mi];
-      a.s = DevState{B.g + t * B.max_nv, B.AD + t * B.max_nh, B.AX + t * B.max_nh, B.fanth + t * B.max_nv,
+      a.s = DevState{B.g + t * B.max_nv, B.as + t * B.max_nh, B.fanth + t * B.max_nv,
                      B.claim + t * B.max_nv};
       a.pool[0] = slot_pool(B, t, 0);
       a.pool[1] = slot_pool(B, t, 1);
@@ -1790,8 +1807,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       a.s.claim[i] = 0u;
     }
     for (u64 i = t0; i < (u64)nh; i += stride) {
-      a.s.AD[i] = 0x7ff0000000000000ull;
-      a.s.AX[i] = kAllOnes;
+      a.s.as[i] = Split{0x7ff0000000000000ull, kAllOnes};
     }
     team_sync();
     if (threadIdx.x < (u32)kWave) Ph::init_fan_(a, B.field_src[f], &ctl);
@@ -1856,14 +1872,14 @@ struct pch_mesh_s {
   pch::HostMesh host;
   int device = 0;
   // device copies
-  pch::HalfEdge* he = nullptr;
+  HalfEdgeLine* hl = nullptr;
   double *phi = nullptr, *alpha = nullptr, *theta = nullptr;
   int32_t *twin = nullptr, *hv = nullptr, *coff = nullptr, *corner = nullptr;
   pch::Corner* crec = nullptr;
-  pch::HalfEdgeAng* hang = nullptr;
   uint8_t* flags = nullptr;
   // state (sized with the mesh)
-  u64 *g = nullptr, *AD = nullptr, *AX = nullptr, *fanth = nullptr;
+  u64 *g = nullptr, *fanth = nullptr;
+  Split* as = nullptr;
   u32* claim = nullptr;
   // work buffers (grow on demand)
   int64_t cap = 0, ecap = 0, acap = 0;
@@ -1974,32 +1990,34 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   const pch::HostMesh& H = M->host;
   // distance events name their half-edge as 4 e + k in 32 bits
   if (H.nh >= ((int64_t)1 << 29)) return set_err(PCH_EINVAL, "mesh too large: at most 2^29 - 1 half-edges");
-  HIP_TRY(dalloc(&M->he, H.nh));
+  HIP_TRY(dalloc(&M->hl, H.nh));
   HIP_TRY(dalloc(&M->phi, H.nh));
   HIP_TRY(dalloc(&M->alpha, H.nh));
   HIP_TRY(dalloc(&M->twin, H.nh));
   HIP_TRY(dalloc(&M->hv, H.nh));
   HIP_TRY(dalloc(&M->corner, H.nh));
   HIP_TRY(dalloc(&M->crec, H.nh));
-  HIP_TRY(dalloc(&M->hang, H.nh));
   HIP_TRY(dalloc(&M->theta, H.nv));
   HIP_TRY(dalloc(&M->flags, H.nv));
   HIP_TRY(dalloc(&M->coff, H.nv + 1));
   HIP_TRY(dalloc(&M->g, H.nv));
-  HIP_TRY(dalloc(&M->AD, H.nh));
-  HIP_TRY(dalloc(&M->AX, H.nh));
+  HIP_TRY(dalloc(&M->as, H.nh));
   HIP_TRY(dalloc(&M->fanth, H.nv));
   HIP_TRY(dalloc(&M->claim, H.nv));
   HIP_TRY(dalloc(&M->ctl, 1));
   HIP_TRY(dalloc(&M->hist, kHistBins));
-  HIP_TRY(hipMemcpyAsync(M->he, H.he.data(), sizeof(pch::HalfEdge) * H.nh, hipMemcpyHostToDevice, st));
+  {
+    std::vector<HalfEdgeLine> lines((size_t)H.nh);
+    for (int64_t j = 0; j < H.nh; ++j) lines[j] = HalfEdgeLine{H.he[j], H.hang[j]};
+    HIP_TRY(hipMemcpyAsync(M->hl, lines.data(), sizeof(HalfEdgeLine) * H.nh, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // before the staging vector goes away
+  }
   HIP_TRY(hipMemcpyAsync(M->phi, H.phi.data(), sizeof(double) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->alpha, H.alpha.data(), sizeof(double) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->twin, H.twin.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->hv, H.hv.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->corner, H.corner.data(), sizeof(int32_t) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->crec, H.crec.data(), sizeof(pch::Corner) * H.nh, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(M->hang, H.hang.data(), sizeof(pch::HalfEdgeAng) * H.nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->theta, H.theta.data(), sizeof(double) * H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->flags, H.flags.data(), H.nv, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(M->coff, H.coff.data(), sizeof(int32_t) * (H.nv + 1), hipMemcpyHostToDevice, st));
@@ -2010,20 +2028,18 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
 
 void free_mesh(pch_mesh_s* M) {
   free_work(M);
-  (void)hipFree(M->he);
+  (void)hipFree(M->hl);
   (void)hipFree(M->phi);
   (void)hipFree(M->alpha);
   (void)hipFree(M->twin);
   (void)hipFree(M->hv);
   (void)hipFree(M->corner);
   (void)hipFree(M->crec);
-  (void)hipFree(M->hang);
   (void)hipFree(M->theta);
   (void)hipFree(M->flags);
   (void)hipFree(M->coff);
   (void)hipFree(M->g);
-  (void)hipFree(M->AD);
-  (void)hipFree(M->AX);
+  (void)hipFree(M->as);
   (void)hipFree(M->fanth);
   (void)hipFree(M->claim);
   (void)hipFree(M->ctl);
@@ -2051,8 +2067,8 @@ pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
 
 RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   RoundArgs a;
-  a.m = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec, M->hang};
-  a.s = DevState{M->g, M->AD, M->AX, M->fanth, M->claim};
+  a.m = DevMesh{M->hl, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+  a.s = DevState{M->g, M->as, M->fanth, M->claim};
   a.pool[0] = M->pool[0];
   a.pool[1] = M->pool[1];
   a.sel = M->sel;
@@ -2331,8 +2347,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     a.pbin = pbin;
     const int fill_blocks = 1024;
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->g, H.nv, bits_host(INFINITY));
-    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->AD, H.nh, bits_host(INFINITY));
-    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->AX, H.nh, kAllOnes);
+    k_fill_split<<<fill_blocks, kBlock, 0, st>>>(M->as, H.nh, bits_host(INFINITY), kAllOnes);
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->fanth, H.nv, kAllOnes);
     k_fill_u32<<<fill_blocks, kBlock, 0, st>>>(M->claim, H.nv, 0u);
     std::memset(&ctl_init, 0, sizeof(ctl_init));
@@ -2464,7 +2479,7 @@ void free_slots(pch_batch_s* b) {
   if (!b->slots) return;
   BatchDev& B = b->B;
   for (void* p : {(void*)B.pbb, (void*)B.ppp, (void*)B.psk, (void*)B.pes, (void*)B.ev_vq, (void*)B.ev_d, (void*)B.ev_xy, (void*)B.ae_e, (void*)B.ae_D,
-                  (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.AD, (void*)B.AX})
+                  (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.as})
     (void)hipFree(p);
   b->slots = false;
 }
@@ -2504,8 +2519,7 @@ pch_status alloc_slots(pch_batch_s* b) {
   HIP_TRY(dalloc(&B.g, T * b->max_nv));
   HIP_TRY(dalloc(&B.fanth, T * b->max_nv));
   HIP_TRY(dalloc(&B.claim, T * b->max_nv));
-  HIP_TRY(dalloc(&B.AD, T * b->max_nh));
-  HIP_TRY(dalloc(&B.AX, T * b->max_nh));
+  HIP_TRY(dalloc(&B.as, T * b->max_nh));
   b->slots = true;
   B.max_nv = b->max_nv;
   B.max_nh = b->max_nh;
@@ -2672,8 +2686,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   b->delta0.resize(n_meshes);
   for (int i = 0; i < n_meshes; ++i) {
     pch_mesh_s* M = meshes[i];
-    dm[i] = DevMesh{M->he, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec,
-                    M->hang};
+    dm[i] = DevMesh{M->hl, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
     nv[i] = M->host.nv;
     nh[i] = M->host.nh;
     double sum = 0.0;
