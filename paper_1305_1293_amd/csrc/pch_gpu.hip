@@ -1482,7 +1482,9 @@ __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u6
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
-    atomicMin(&a.s.as[e].D, bits(D));
+    // a corner whose apex distance improves forgets its old crossing (the
+    // crossings are only compared in the next pass)
+    if (atomicMin(&a.s.as[e].D, bits(D)) > bits(D)) a.s.as[e].X = kAllOnes;
   }
 }
 
@@ -1490,9 +1492,11 @@ __global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
   ph_events1(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
-// Second pass: corners whose distance changed forget their old crossing; each
-// improved pseudo-source vertex records the smallest incoming angle among the
-// events that reached its new distance.
+// Second pass: each corner keeps the smallest crossing among the angle events
+// that reached its (new or unchanged) apex distance, together with a kept old
+// crossing: the lexicographic minimum of (distance, crossing). Each improved
+// pseudo-source vertex records the smallest incoming angle among the events
+// that reached its new distance.
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
@@ -1502,7 +1506,8 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
-    if (bits(D) == lda(&a.s.as[e].D)) a.s.as[e].X = kAllOnes;
+    const double X = i == t0 ? f.X : a.aev.X[i];
+    if (bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
   }
   for (u64 i = t0; i < nd; i += stride) {
     const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
@@ -1526,9 +1531,8 @@ __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
   ph_events2(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
-// Third pass: the winning crossing per corner; one fan per improved
-// pseudo-source vertex, windows into the next pool, deferred endpoint events
-// into the next round's event buffer.
+// Third pass: one fan per improved pseudo-source vertex, windows into the
+// next pool, deferred endpoint events into the next round's event buffer.
 __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   // Distance events are dealt round-robin over the launch's wavefronts (event
@@ -1536,16 +1540,8 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   // the few fans of a round spread over many compute units.
   const u64 nw = stride / kWave, w = t0 / kWave;
   const u64 i0 = w + nw * (u64)lane_id();
-  // the lane's first angle event and first distance event are loaded
-  // together with the round's counters (indices below the capacities are in
-  // bounds)
-  int32_t fa_e = 0;
-  double fa_D = 0.0, fa_X = 0.0;
-  if (t0 < (u64)a.acap) {
-    fa_e = a.aev.e[t0];
-    fa_D = a.aev.D[t0];
-    fa_X = a.aev.X[t0];
-  }
+  // the lane's first distance event is loaded together with the round's
+  // counters (indices below the capacity are in bounds)
   int32_t f_v = 0;
   double f_d = 0.0, f_th = 0.0;
   if (i0 < (u64)a.ecap) {
@@ -1555,14 +1551,7 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   }
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
-  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   const u32 stamp = (u32)c->round;
-  for (u64 i = t0; i < na; i += stride) {
-    const int e = i == t0 ? fa_e : a.aev.e[i];
-    const double D = i == t0 ? fa_D : a.aev.D[i];
-    const double X = i == t0 ? fa_X : a.aev.X[i];
-    if (bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
-  }
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
@@ -2360,7 +2349,9 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, M->dsrc, nsrc);
     k_begin<<<1, kWave, 0, st>>>(a, 0);
     HIP_TRY(hipGetLastError());
-    const int pool_blocks = grid_for(std::max<int64_t>(cap, 1), 1024);
+    // the pool scan is sized from the largest pool seen so far (twice it, at
+    // least 2k windows); its grid-stride loop covers any larger pool
+    int pool_blocks = grid_for(std::max<int64_t>(2 * o.k, (int64_t)1 << 16), 1024);
     const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
     const bool kth = o.select_mode != PCH_SELECT_DELTA;
     int p = 0;
@@ -2391,6 +2382,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
         }
       }
       rounds_before = host_ctl.round;
+      pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
       if (host_ctl.overflow) {
         overflow = true;
         break;

@@ -97,7 +97,9 @@ def test_small_config_vs_ich(pch, oracle, k):
                                   ("grid48", 100, 2048, 0.01),
                                   ("sinusoid64", 0, 256, None, 3), ("sphere4", 17, 1 << 20, None, 4),
                                   ("lshape", -1, 16, None, 16), ("cone7", 5, 64, None, 2),
-                                  ("grid48", 100, 2048, 0.01, 4), ("sinusoid64", 0, 1024, 0.02, 8)])
+                                  ("grid48", 100, 2048, 0.01, 4), ("sinusoid64", 0, 1024, 0.02, 8),
+                                  ("cube6", -2, 64), ("plane15", 112, 32), ("plane15", 112, 256, None, 4),
+                                  ("cube6", -2, 512, 0.05, 3)])
 def test_round_log_matches_replica(pch, oracle, case):
     name, s, k = case[:3]
     delta0 = case[3] if len(case) > 3 else None
@@ -107,8 +109,11 @@ def test_round_log_matches_replica(pch, oracle, case):
     sel["hops"] = gsel["hops"] = hops
     m = {"sinusoid64": lambda: G.config_mesh(1), "sphere4": lambda: G.bumpy_icosphere(4, seed=9),
          "lshape": lambda: G.lshape(6), "cone7": lambda: G.cone_fan(7, 6),
-         "grid48": lambda: G.bump_grid(48, seed=4)}[name]()
-    if s < 0:
+         "grid48": lambda: G.bump_grid(48, seed=4), "cube6": lambda: G.cube(6),
+         "plane15": lambda: G.jittered_plane(15, 0, jitter=0.0)}[name]()
+    if s == -2:  # a cube corner: symmetric paths tie exactly
+        s = int(np.argmin(np.linalg.norm(m.xyz, axis=1)))
+    elif s < 0:
         s = int(np.argmin(np.linalg.norm(m.xyz[:, :2] - [2.0, 0.0], axis=1)))
     say(f"round log parity {name} source {s} k {k} delta0 {delta0} hops {hops}")
     dr, st_r, log_r = oracle.replica(m, [s], k, **sel)
