@@ -3,18 +3,25 @@
 //
 // One round (Section 4.2, Algorithm 1) is a fixed sequence of kernels on one
 // stream; counts live in device memory, so rounds are enqueued back to back
-// and the host only polls a done flag every few rounds:
-//   begin      - close the previous round's log record, set up selection
+// and the host only polls a control block every few rounds:
 //   hist/scan  - three 12-bit histogram passes give the k-th smallest key
-//                (selection, step 1)
+//                (selection, step 1; only for the k-th-key rule)
 //   partition  - drop stale windows, split the pool into selected windows and
 //                survivors (the gap-free pool of Section 4.1 and Algorithm 3)
+//   org        - optional: group the selected windows by edge
 //   propagate  - Algorithm 2 for every selected window against the round-start
-//                state; children and events are appended with one atomic per
-//                wavefront (Algorithm 3's prefix sum, done per wave)
-//   events 1-3 - Algorithm 4: per-vertex minimum of distance events, per-corner
-//                lexicographic minimum of angle events, then one fan of
-//                windows per improved pseudo-source vertex (Figure 3(c))
+//                state, once per hop (children that pass the round's selection
+//                test propagate again in the same round); children and events
+//                are appended with one reservation per wavefront (Algorithm 3's
+//                prefix sum, done per wave)
+//   events 1-3 - Algorithm 4: per-vertex minimum of distance events and
+//                per-corner lexicographic minimum of angle events, the
+//                incoming angles of the winning events, then one fan of
+//                windows per improved pseudo-source vertex (Figure 3(c)); the
+//                last workgroup of the third pass closes the round's log
+//                record and sets up the next round's selection
+// The batched form runs the same phases for one field per workgroup inside a
+// persistent kernel, separated by workgroup barriers.
 //
 // All window geometry is FP64; the file is compiled with FP contraction off so
 // results do not depend on instruction selection.

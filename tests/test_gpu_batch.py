@@ -62,6 +62,7 @@ def test_batch_equals_single_fields(pch, oracle, setup, use_graph, hops):
     assert st["fields"] == b.n_fields
     fstat = b.field_stats()
     assert np.all(fstat[:, 0] == 0), fstat[:, 0]
+    assert np.all(fstat[:, 7] > 0)  # each field's time in its workgroup
     for f in range(b.n_fields):
         ref = single(pch, meshes[fm[f]], int(fs[f]), k, hops)
         gf = got[b.offsets[f]:b.offsets[f + 1]]

@@ -89,12 +89,12 @@ def test_learned_cutoff_exact_and_replayable(pch, oracle, trained):
     import torch
     from paper_1305_1293_amd import learned as Lr
     mlp, _ = trained
-    for m, s, k in [(G.bumpy_icosphere(4, seed=31), 7, 512), (G.bump_grid(64, seed=12), 0, 1024),
-                    (G.sinusoid_grid(48, 3), 100, 256)]:
-        say(f"learned cutoff {m.name} source {s} k {k}")
+    for m, s, k, hops in [(G.bumpy_icosphere(4, seed=31), 7, 512, 1), (G.bump_grid(64, seed=12), 0, 1024, 1),
+                          (G.sinusoid_grid(48, 3), 100, 256, 1), (G.bumpy_icosphere(4, seed=31), 7, 512, 3)]:
+        say(f"learned cutoff {m.name} source {s} k {k} hops {hops}")
         dm = pch.Mesh.from_generated(m)
         xyz = torch.from_numpy(m.xyz).cuda()
-        d, st = Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k, collect_stats=1)
+        d, st = Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k, collect_stats=1, hops=hops)
         torch.cuda.synchronize()
         got = d.cpu().numpy()
         log = dm.round_log()
@@ -105,7 +105,7 @@ def test_learned_cutoff_exact_and_replayable(pch, oracle, trained):
         assert learned_rounds.any()
         cut = log[:, 1].astype(np.uint64).view(np.float64).copy()
         cut[~learned_rounds] = np.inf  # rounds that took the whole pool
-        dr, _, log_r = oracle.replica(m, [s], k, cutoffs=cut)
+        dr, _, log_r = oracle.replica(m, [s], k, cutoffs=cut, hops=hops)
         assert np.array_equal(got.view(np.uint64), dr.view(np.uint64))
         assert np.array_equal(log[:, 0], log_r[:, 0]) and np.array_equal(log[:, 3:], log_r[:, 3:])
         dm.close()

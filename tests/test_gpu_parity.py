@@ -192,6 +192,10 @@ def test_argument_errors(pch):
     with pytest.raises(pch.PchError) as e:
         pch.geodesic(dm, [0], k=0)
     assert e.value.code == -1
+    for hops in (-1, 17):
+        with pytest.raises(pch.PchError) as e:
+            pch.geodesic(dm, [0], hops=hops)
+        assert e.value.code == -1
     info = dm.info()
     assert info["nv"] == m.nv and info["nf"] == m.nf and info["n_boundary_he"] == 4 * 63
     dm.close()
