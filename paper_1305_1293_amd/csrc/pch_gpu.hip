@@ -1608,12 +1608,17 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
   __shared__ int is_last;
   Ctl* c = a.ctl;
   ph_events3(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
-  __threadfence();
+  // The set-up reads only counters, which every workgroup updates with
+  // device-scope atomics and the set-up reads with device-scope atomic loads;
+  // waiting until this wavefront's memory operations have completed orders
+  // its counter updates before the ticket. (A device-scope fence would also
+  // write back the L2 caches, which the set-up does not need: it reads no
+  // plain stores of this kernel.)
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
   __syncthreads();
   if (is_last && threadIdx.x < kWave) {
-    __threadfence();
     if (threadIdx.x == 0) c->ticket = 0;
     round_begin(a, 1 - p);
   }
@@ -1661,11 +1666,11 @@ constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak
 
 // Barrier between the phases of one workgroup's field. Values updated with
 // device-scope atomics are read with agent-scope loads (lda), so the barrier
-// only has to order this workgroup's plain stores before the next phase.
-__device__ __forceinline__ void team_sync() {
-  __threadfence();
-  __syncthreads();
-}
+// only has to order this workgroup's plain stores before the next phase: the
+// workgroup-scope release and acquire of the barrier itself do that (the
+// compute unit's L1 is shared by the workgroup's wavefronts). A device-scope
+// fence would also write back the L2 cache at every phase.
+__device__ __forceinline__ void team_sync() { __syncthreads(); }
 
 __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
   const int64_t o = ((int64_t)t * B.nslot + b) * B.cap;
