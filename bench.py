@@ -85,7 +85,7 @@ def measure_batched(pch, G, torch):
     meshes = [pch.Mesh.from_generated(m) for m in gens]
     fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
     fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
-    opts = dict(k=32768, team_threads=256, teams_per_cu=1, hops=4)
+    opts = dict(k=32768, team_threads=512, teams_per_cu=1, hops=4)
     b = pch.Batch(meshes, fm, fs, **opts)
     out, _ = b.run()  # first run captures the graph
     dt, (out, st) = _timed(torch, lambda: b.run(out))

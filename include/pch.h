@@ -183,7 +183,8 @@ typedef struct {
   int32_t teams_per_cu;  /* resident workgroups per compute unit (default 2) */
   int32_t filters;       /* as pch_options.filters (default 3) */
   double eps_tiny;       /* as pch_options.eps_tiny (default 0) */
-  int64_t pool_capacity; /* windows per workgroup; 0 = from the largest mesh */
+  int64_t pool_capacity; /* windows per workgroup; 0 = from the largest mesh
+                            and k (at least 3 k, at most 2^21) */
   int32_t use_graph;     /* 1 = replay a captured HIP graph of the launch (default) */
   int32_t team_threads;  /* threads of the workgroup that runs one field: 256
                             (default), 512 or 1024 */

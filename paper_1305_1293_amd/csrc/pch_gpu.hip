@@ -954,12 +954,14 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   __syncthreads();
   for (int i = threadIdx.x; i < kHistBins; i += kBlock)
     if (h[i]) atomicAdd(&a.hist[i], h[i]);
-  __threadfence();
+  // The last workgroup reads the histogram with device-scope atomic loads:
+  // waiting for this wavefront's atomics orders them before the ticket (as in
+  // k_events3; no cache write-back is needed).
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) is_last = atomicAdd(&c->ticket, 1ull) == (u64)(gridDim.x - 1);
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   constexpr int per = kHistBins / kBlock;
   u32 loc[per];
   u32 sum = 0;
@@ -2502,7 +2504,8 @@ pch_status alloc_slots(pch_batch_s* b) {
   const int nf = (int)b->fmesh.size();
   b->n_teams = std::max(1, std::min(nf, b->o.teams_per_cu * b->n_cu));
   int64_t cap = b->o.pool_capacity;
-  if (cap <= 0) cap = std::min<int64_t>(std::max<int64_t>(32768, b->max_nh / 12), 1 << 20);
+  // a team's pool holds at least three rounds' worth of windows (3 k)
+  if (cap <= 0) cap = std::min<int64_t>(std::max<int64_t>({32768, b->max_nh / 12, 3 * b->o.k}), 1 << 21);
   B.cap = cap;
   B.ecap = cap;
   B.acap = std::max<int64_t>(cap / 2, 1024);
