@@ -171,10 +171,14 @@ pch_status pch_round_log(pch_mesh mesh, int64_t* out, int64_t max_rounds, int64_
 /* ------------------------------------------------------------------------
  * Batched fields: many independent single-source fields on meshes of uneven
  * size in one persistent launch. Each workgroup takes the next field from a
- * device queue (largest meshes first) and runs all of its rounds alone with
- * the adaptive-step selection (PCH_SELECT_DELTA); results equal pch_geodesic
- * with the same k and delta0 bit for bit. Fields whose windows outgrow a
- * workgroup's pool are rerun with pch_geodesic.
+ * device queue (most expected windows first: 24 per half-edge before the
+ * first run, then the windows each field took in the previous run) and runs
+ * its rounds with the adaptive-step selection (PCH_SELECT_DELTA); results
+ * equal pch_geodesic with the same k and delta0 bit for bit. With gang > 1 a
+ * workgroup may instead join a running field of its own XCD when that field's
+ * remaining windows per workgroup exceed the next queued field's; the field's
+ * rounds are then split over its workgroups from the next round on. Fields
+ * whose windows outgrow a workgroup's pool are rerun with pch_geodesic.
  * ---------------------------------------------------------------------- */
 typedef struct pch_batch_s* pch_batch;
 
@@ -189,7 +193,10 @@ typedef struct {
   int32_t team_threads;  /* threads of the workgroup that runs one field: 256
                             (default), 512 or 1024 */
   int32_t hops;          /* as pch_options.hops (default 1) */
-  int32_t pad;
+  int32_t gang;          /* most workgroups on one field, 1..32 (default 1):
+                            with more than 1, a workgroup that finds no field
+                            left joins a running field of its own XCD, whose
+                            rounds are then split over its workgroups */
 } pch_batch_options;
 
 typedef struct {
@@ -215,17 +222,22 @@ pch_status pch_batch_offsets(pch_batch batch, int64_t* offsets);
 /* dist: device double [offsets[n_fields]] (caller-owned). */
 pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_batch_stats* stats);
 
-/* Per-field record of the last run, host int64 [n_fields][8]: status (0 ok,
- * 1 rerun after pool overflow, 2 rerun after the round limit), rounds,
- * windows processed, windows created, fans, peak pool, stale windows, and
- * the time the field took in its workgroup in ticks of the device's
- * constant-rate wall clock (100 MHz on MI355X; 0 after a rerun). */
+/* Per-field record of the last run, host int64 [n_fields][9]: status (0 ok;
+ * rerun with pch_geodesic after 1 pool overflow, 2 the round limit, 3 a
+ * shared field whose workgroups stopped waiting for each other, 4 a field no
+ * workgroup finished), rounds, windows processed, windows created, fans,
+ * peak pool, stale windows, the time from the start of the field to its end
+ * in ticks of the device's constant-rate wall clock (100 MHz on MI355X; 0
+ * after a rerun), and the helper workgroups that joined it. The windows
+ * processed also set the next run's order (most first) and how helpers
+ * choose among running fields. */
 pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
 
 /* Autotuner: times k in {8192, 16384, 32768, 65536} with workgroup shapes
- * (256 threads, 1 per CU), (512, 1) and (1024, 1) and 1 or 4 hops per round
- * on the whole batch (into dist), keeps the fastest in the batch and returns
- * it in chosen (may be NULL). */
+ * (256 threads, 1 per CU), (512, 1) and (1024, 1) and 1 or 4 hops per round,
+ * with up to 8 workgroups per field, then gang sizes 1, 2, 4 and 16 at the
+ * best of those, each on the whole batch (into dist); keeps the fastest in
+ * the batch and returns it in chosen (may be NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
 
 /* ------------------------------------------------------------------------

@@ -679,6 +679,7 @@ __device__ __forceinline__ void block_totals(u64& kmn, u64& kmx, u32 (&v)[NV]) {
 __device__ __forceinline__ u64 ld(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ double ldd(const double* p) { return from_bits(ld((const u64*)p)); }
 
 // Lane 0's part of the round set-up for input parity p: log and total the
 // previous round, stop when nothing is left, reset this round's output buffers
@@ -1022,13 +1023,13 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
     f_sk = P.sk[t0];
     f_es = P.es[t0];
   }
-  const bool active = c->active != 0;
-  const u64 N = active ? min(c->npool[p], (u64)a.cap) : 0;
-  const int s = (int)c->shift;
-  const u64 T = c->want;
-  const bool all = c->sel_all;
-  const bool tab = c->use_table;
-  const double cv = c->cutval;
+  const bool active = ld(&c->active) != 0;
+  const u64 N = active ? min(ld(&c->npool[p]), (u64)a.cap) : 0;
+  const int s = (int)ld(&c->shift);
+  const u64 T = ld(&c->want);
+  const bool all = ld(&c->sel_all);
+  const bool tab = ld(&c->use_table);
+  const double cv = ldd(&c->cutval);
   u32 stale_n = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
@@ -1112,18 +1113,18 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     f_sk = S.sk[t0];
     f_es = S.es[t0];
   }
-  const bool active = c->active != 0;
-  const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
+  const bool active = ld(&c->active) != 0;
+  const u64 n_in = ld(hop <= 1 ? &c->nsel : &c->nhop[hop - 1]);
   const u64 N = active ? min(n_in, (u64)a.cap) : 0;
   const Pool Q = a.pool[1 - p];
   const bool to_hop = hop < a.hops;
   const Pool HQ = a.hq[(hop + 1) & 1];
   u64* nq_ctr = &c->nhop[hop < kMaxHops ? hop : kMaxHops];
-  const int sh = (int)c->shift;
-  const u64 T = c->want;
-  const bool all = c->sel_all;
-  const bool tab = c->use_table;
-  const double cv = c->cutval;
+  const int sh = (int)ld(&c->shift);
+  const u64 T = ld(&c->want);
+  const bool all = ld(&c->sel_all);
+  const bool tab = ld(&c->use_table);
+  const double cv = ldd(&c->cutval);
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
@@ -1131,7 +1132,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     if (hop <= 1)
       c->cnt[C_SEL] = n_in;
     else
-      c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
+      c->cnt[C_SEL] = ld(&c->cnt[C_SEL]) + n_in;
   }
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
   u64 kmn = kAllOnes, kmx = 0;
@@ -1480,9 +1481,9 @@ __device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u
 __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
-  const bool active = c->active != 0;
-  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
-  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
+  const bool active = ld(&c->active) != 0;
+  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
+  const u64 na = active ? min(ld(&c->naev), (u64)a.acap) : 0;
   for (u64 i = t0; i < nd; i += stride) {
     const int32_t v = i == t0 ? f.vq.x : a.ev[p].vq[i].x;
     const double d = i == t0 ? f.d : a.ev[p].d[i];
@@ -1509,9 +1510,9 @@ __global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
-  const bool active = c->active != 0;
-  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
-  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
+  const bool active = ld(&c->active) != 0;
+  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
+  const u64 na = active ? min(ld(&c->naev), (u64)a.acap) : 0;
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
@@ -1558,9 +1559,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
     f_d = a.ev[p].d[i0];
     f_th = a.ev[p].xy[i0].x;
   }
-  const bool active = c->active != 0;
-  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
-  const u32 stamp = (u32)c->round;
+  const bool active = ld(&c->active) != 0;
+  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
+  const u32 stamp = (u32)ld(&c->round);
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
@@ -1631,6 +1632,8 @@ __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
 // batched fields: one workgroup runs every round of one field at a time
 // ---------------------------------------------------------------------------
 
+struct alignas(256) GangRec;
+
 struct BatchDev {
   const DevMesh* meshes;      // [n_meshes]
   const int64_t* mesh_nv;     // [n_meshes]
@@ -1639,11 +1642,14 @@ struct BatchDev {
   const int32_t* field_mesh;  // [n_fields]
   const int32_t* field_src;   // [n_fields]
   const int64_t* field_off;   // [n_fields] offset of the field in out
-  const int32_t* order;       // [n_fields] processing order (largest first)
+  const int32_t* order;       // [n_fields] processing order (largest cost first)
+  const u64* cost;            // [n_fields] expected windows of the field
   int32_t n_fields;           // fields taken from the queue
   double* out;                // concatenated distance fields
   int64_t* fstat;             // [n_fields][kFieldStat]
   u64* queue;                 // next position in order
+  GangRec* gang;              // [n_fields] round handshake of the field's workgroups
+  u32* board;                 // [kMaxXcc][kBoard] field + 1 of a running field that takes helpers, or 0
   // per-team buffers (team t uses slot t)
   double2 *pbb, *ppp, *psk;  // [n_teams][nslot][cap]: pool 0, pool 1, selection, hop queues
   int2* pes;
@@ -1659,12 +1665,39 @@ struct BatchDev {
   int64_t k;
   double eps;
   int32_t ch_on, ich_on, full_fan;
-  int32_t hops;   // propagation hops per round
-  int32_t nslot;  // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
+  int32_t hops;      // propagation hops per round
+  int32_t nslot;     // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
+  int32_t gang_max;  // workgroups per field (1: no helpers)
   int64_t max_rounds;
 };
 
-constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak pool, stale, team time
+// status, rounds, processed, created, fans, peak pool, stale, team time, helpers
+constexpr int kFieldStat = 9;
+constexpr int kMaxXcc = 16;    // XCD ids covered by the board
+constexpr int kBoard = 64;     // running fields per XCD that helpers can find
+constexpr int kMaxGang = 32;   // workgroups on one field
+// Longest wait of a gang member for the others, in ticks of the 100 MHz wall
+// clock (2 s): far above any round, so it only ends a wait that cannot end.
+constexpr u64 kGangWait = 200000000ull;
+// field status before a workgroup finishes it (the host reruns such fields)
+constexpr int64_t kFieldNotRun = 4;
+
+// The workgroups that share one field once the field queue is empty: the
+// leader (the workgroup that took the field, whose buffers hold it) and the
+// helpers of the same XCD that joined it between rounds. All of them reach
+// the field's buffers through the one L2 of their XCD.
+struct alignas(256) GangRec {
+  u64 word;   // round handshake: (count << 8) | (done << 7) | (parity << 6) | members
+  u64 join;   // helpers that joined
+  u64 left;   // helpers that left
+  u64 abort;  // 1 after a member's wait ran out of time
+  u64 team;   // the leader's workgroup
+  u64 prog;   // windows processed so far (published by the leader each round)
+  u64 pad0[10];
+  u64 cnt[2];  // barrier arrivals in rounds of even and odd count
+  u64 pad1[14];
+  Ctl ctl;  // round counters from the first round with helpers on
+};
 
 // Barrier between the phases of one workgroup's field. Values updated with
 // device-scope atomics are read with agent-scope loads (lda), so the barrier
@@ -1674,15 +1707,97 @@ constexpr int kFieldStat = 8;  // status, rounds, processed, created, fans, peak
 // fence would also write back the L2 cache at every phase.
 __device__ __forceinline__ void team_sync() { __syncthreads(); }
 
+__device__ __forceinline__ void sta(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the XCD (accelerator complex die) this wavefront runs on
+__device__ __forceinline__ u32 xcc_id() {
+  u32 x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & 0xfu;
+}
+// Agent-scope acquire: drops the compute unit's vector L1 lines (buffer_inv
+// sc1), so that later plain loads see what other compute units stored. The
+// workgroup-scope invalidate (sc0) leaves those lines in place on gfx950: a
+// reader on another compute unit of the same XCD kept reading its stale
+// copies after it.
+__device__ __forceinline__ void l1_invalidate() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Barrier of the nm workgroups of a gang round. Every wavefront first waits
+// for its own stores and atomics (they are then in the XCD's L2, which every
+// member reads through), one lane per workgroup arrives, and after the wait
+// the compute unit's L1 is dropped so that the next phase sees what the other
+// members wrote. Returns 0 when the gang gave up: some member's wait ran out
+// of time, which sets the gang's abort flag for all of them.
+__device__ __forceinline__ int gang_sync(GangRec* R, int slot, u64 target, int* s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&R->cnt[slot], 1ull);
+    int ok = 1;
+    const u64 t_end = wall_clock64() + kGangWait;
+    while (ld(&R->cnt[slot]) < target) {
+      if (ld(&R->abort) || wall_clock64() > t_end) {
+        sta(&R->abort, 1ull);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    l1_invalidate();
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok;
+}
+
 __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
   const int64_t o = ((int64_t)t * B.nslot + b) * B.cap;
   return Pool{B.pbb + o, B.ppp + o, B.psk + o, B.pes + o};
 }
 
-// Persistent workgroups: each takes the next field from the queue and runs
-// Algorithm 1 on it alone, the phases separated by workgroup barriers and
-// the round counters in LDS. Fields never wait for each other; a field
-// that outgrows the team's pool is flagged for a rerun by the host.
+// Round arguments of field f in the buffers of workgroup t (without the
+// control block), written straight into the workgroup's LDS copy.
+__device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, RoundArgs& a) {
+  const int mi = B.field_mesh[f];
+  a.m = B.meshes[mi];
+  a.s = DevState{B.g + t * B.max_nv, B.as + t * B.max_nh, B.fanth + t * B.max_nv, B.claim + t * B.max_nv};
+  a.pool[0] = slot_pool(B, t, 0);
+  a.pool[1] = slot_pool(B, t, 1);
+  a.sel = slot_pool(B, t, 2);
+  a.hq[0] = B.hops > 1 ? slot_pool(B, t, 3) : Pool{};
+  a.hq[1] = B.hops > 1 ? slot_pool(B, t, 4) : Pool{};
+  a.hops = B.hops;
+  a.org_shift = -1;  // batched fields are not organized by edge
+  a.sorted = Pool{};
+  a.org_hist = nullptr;
+  a.org_ofs = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
+    a.ev[i] = DistEv{B.ev_vq + o, B.ev_d + o, B.ev_xy + o};
+  }
+  const int64_t oa = (int64_t)t * B.acap;
+  a.aev = AngEv{B.ae_e + oa, B.ae_D + oa, B.ae_X + oa};
+  a.ctl = nullptr;
+  a.hist = nullptr;
+  a.log = nullptr;
+  a.max_log = 0;
+  a.cap = B.cap;
+  a.ecap = B.ecap;
+  a.acap = B.acap;
+  a.k = B.k;
+  a.mode = PCH_SELECT_DELTA;
+  a.eps = B.eps;
+  a.ch_on = B.ch_on;
+  a.ich_on = B.ich_on;
+  a.full_fan = B.full_fan;
+  a.table = nullptr;
+  a.n_table = 0;
+  a.cdf = nullptr;
+  a.pbin = 0.0;
+  a.w0 = 4.0;
+}
+
 // Out-of-line phases for the persistent kernel: each gets its own register
 // allocation instead of the union of all phases in one function.
 __device__ __noinline__ void nl_partition(const RoundArgs& a, int p, u64 t0, u64 s) { ph_partition(a, p, t0, s); }
@@ -1737,128 +1852,308 @@ struct TeamPhases {
   }
 };
 
+// The phases of one round (Algorithm 1) as member idx of nm workgroups: the
+// member's threads take every nm-th block of the work. With one member the
+// phases are separated by workgroup barriers, otherwise by gang barriers on
+// arrival counter `slot`. Returns 0 when the gang gave up.
+template <class Ph, int BS>
+__device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, int nm, GangRec* R, int slot, int* s_ok) {
+  const u64 t0 = (u64)idx * BS + threadIdx.x, stride = (u64)nm * BS;
+  u64 nb = 0;
+  auto bar = [&]() -> int {
+    if (nm == 1) {
+      team_sync();
+      return 1;
+    }
+    return gang_sync(R, slot, (u64)nm * ++nb, s_ok);
+  };
+  Ph::partition(a, p, t0, stride);
+  if (!bar()) return 0;
+  Ph::propagate(a, p, 1, t0, stride);
+  if (!bar()) return 0;
+  for (int h = 2; h <= a.hops; ++h) {
+    if (ld(&a.ctl->nhop[h - 1]) == 0) break;
+    Ph::propagate(a, p, h, t0, stride);
+    if (!bar()) return 0;
+  }
+  Ph::events1(a, p, t0, stride);
+  if (!bar()) return 0;
+  Ph::events2(a, p, t0, stride);
+  if (!bar()) return 0;
+  Ph::events3(a, p, t0, stride);
+  return bar();
+}
+
+// A helper's share of gang R as member idx: between rounds it waits for the
+// leader's handshake, which names the round's parity and member count and
+// whether the field is finished.
+template <class Ph, int BS>
+__device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int idx, RoundArgs& sa, int* s_ok, u64* s_word) {
+  if (threadIdx.x == 0) {
+    team_args(B, (int)ld(&R->team), (int)(R - B.gang), sa);
+    sa.ctl = &R->ctl;
+  }
+  u64 seen = 0;
+  for (;;) {
+    __syncthreads();  // every wavefront has read the previous handshake
+    if (threadIdx.x == 0) {
+      const u64 t_end = wall_clock64() + kGangWait;
+      u64 w;
+      for (;;) {
+        w = ld(&R->word);
+        if (w != seen) break;
+        if (ld(&R->abort) || wall_clock64() > t_end) {
+          sta(&R->abort, 1ull);
+          w = 1ull << 7;  // treat as finished
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      l1_invalidate();
+      *s_word = w;
+    }
+    __syncthreads();
+    const u64 w = *s_word;
+    if (w & (1ull << 7)) break;
+    seen = w;
+    const int nm = (int)(w & 63);
+    if (idx >= nm) continue;
+    if (!team_round<Ph, BS>(sa, (int)((w >> 6) & 1), idx, nm, R, (int)((w >> 8) & 1), s_ok)) break;
+  }
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    atomicAdd(&R->left, 1ull);
+  }
+  __syncthreads();
+}
+
+// Persistent workgroups: each takes the next field from the queue and runs
+// Algorithm 1 on it, the phases separated by workgroup barriers and the round
+// counters in LDS; fields never wait for each other. A field that outgrows
+// the team's pool is flagged for a rerun by the host. With gang_max > 1 a
+// running field accepts helpers: a workgroup that finds the queue empty joins
+// a running field of its own XCD, and from the next round on the field's
+// rounds are split over its members (the counters then live in the field's
+// gang record).
 template <int BS>
 __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
   using Ph = TeamPhases<(BS > 512)>;
-  __shared__ Ctl ctl;
+  __shared__ Ctl lctl;
   __shared__ RoundArgs sa;
-  __shared__ int cur;
+  __shared__ int cur, s_ok, s_nm, s_slot, s_done, s_stop, s_pick, s_idx;
+  __shared__ u64 s_word;
   const int t = blockIdx.x;
   const u64 t0 = threadIdx.x, stride = BS;
+  const u32 xcc = xcc_id();
+  const bool gangs = B.gang_max > 1 && xcc < (u32)kMaxXcc;
+  u32* board = B.board + (size_t)(xcc < (u32)kMaxXcc ? xcc : 0) * kBoard;
+  int fails = 0;
   for (;;) {
-    if (threadIdx.x == 0) {
-      const u64 q = atomicAdd(B.queue, 1ull);
-      cur = q < (u64)B.n_fields ? B.order[q] : -1;
+    // Next work: the next field of the queue (longest expected first), or a
+    // running field of this XCD whose remaining windows per workgroup, with
+    // this one joined, exceed the next queued field's.
+    __syncthreads();  // every wavefront has read the previous choice
+    if (threadIdx.x < (u32)kWave) {
+      u64 key = 0;  // (remaining windows per member << 32) | ~field
+      if (gangs) {
+        // lane l looks at board entry l
+        const u32 e = lane_id() < kBoard ? __hip_atomic_load(&board[lane_id()], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        if (e != 0u) {
+          GangRec* Rc = B.gang + (e - 1u);
+          const u64 j = ld(&Rc->join);
+          if (j < (u64)(B.gang_max - 1) && !(ld(&Rc->word) & (1ull << 7))) {
+            const u64 cf = B.cost[e - 1u], pr = ld(&Rc->prog);
+            const u64 rem = cf > pr ? cf - pr : 1;
+            key = (min(rem / (j + 2), (u64)0xffffffffu) << 32) | (u64)(0xffffffffu - (e - 1u));
+          }
+        }
+        key = wave_max64(key);
+      }
+      if (threadIdx.x == 0) {
+        int pick = -1;  // >= 0: help that field; -1: no work left; -2: look again; -3: lead `cur`
+        const u64 q = ld(B.queue);
+        const bool queued = q < (u64)B.n_fields;
+        const u64 cq = queued ? B.cost[B.order[q]] : 0;
+        if (key != 0 && (!queued || (key >> 32) > cq)) {
+          const u32 f = 0xffffffffu - (u32)key;
+          GangRec* Rc = B.gang + f;
+          const u64 j = ld(&Rc->join);
+          pick = -2;  // the field changed meanwhile
+          if (j < (u64)(B.gang_max - 1) && atomicCAS(&Rc->join, j, j + 1) == j) {
+            pick = (int)f;
+            s_idx = (int)j + 1;
+          }
+        } else if (queued) {
+          const u64 q2 = atomicAdd(B.queue, 1ull);
+          pick = -2;  // the queue ran out meanwhile
+          if (q2 < (u64)B.n_fields) {
+            cur = B.order[q2];
+            pick = -3;
+          }
+        }
+        s_pick = pick;
+      }
     }
     __syncthreads();
+    const int pick = s_pick;
+    if (pick == -1) return;
+    if (pick == -2) {
+      if (++fails > 4096) return;
+      continue;
+    }
+    fails = 0;
+    if (pick >= 0) {
+      help_field<Ph, BS>(B, B.gang + pick, s_idx, sa, &s_ok, &s_word);
+      continue;
+    }
     const int f = cur;
-    if (f < 0) break;
     const u64 t_start = wall_clock64();
     const int mi = B.field_mesh[f];
     const int64_t nv = B.mesh_nv[mi], nh = B.mesh_nh[mi];
+    GangRec* R = gangs ? B.gang + f : nullptr;
     if (threadIdx.x == 0) {
-      RoundArgs a;
-      a.m = B.meshes[mi];
-      a.s = DevState{B.g + t * B.max_nv, B.as + t * B.max_nh, B.fanth + t * B.max_nv,
-                     B.claim + t * B.max_nv};
-      a.pool[0] = slot_pool(B, t, 0);
-      a.pool[1] = slot_pool(B, t, 1);
-      a.sel = slot_pool(B, t, 2);
-      a.hq[0] = B.hops > 1 ? slot_pool(B, t, 3) : Pool{};
-      a.hq[1] = B.hops > 1 ? slot_pool(B, t, 4) : Pool{};
-      a.hops = B.hops;
-      a.org_shift = -1;  // fields of one workgroup are not organized by edge
-      a.sorted = Pool{};
-      a.org_hist = nullptr;
-      a.org_ofs = nullptr;
-      for (int i = 0; i < 2; ++i) {
-        const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
-        a.ev[i] = DistEv{B.ev_vq + o, B.ev_d + o, B.ev_xy + o};
-      }
-      const int64_t oa = (int64_t)t * B.acap;
-      a.aev = AngEv{B.ae_e + oa, B.ae_D + oa, B.ae_X + oa};
-      a.ctl = &ctl;
-      a.hist = nullptr;
-      a.log = nullptr;
-      a.max_log = 0;
-      a.cap = B.cap;
-      a.ecap = B.ecap;
-      a.acap = B.acap;
-      a.k = B.k;
-      a.mode = PCH_SELECT_DELTA;
-      a.eps = B.eps;
-      a.ch_on = B.ch_on;
-      a.ich_on = B.ich_on;
-      a.full_fan = B.full_fan;
-      a.table = nullptr;
-      a.n_table = 0;
-      a.cdf = nullptr;
-      a.pbin = 0.0;
-      a.w0 = 4.0;
-      sa = a;
+      team_args(B, t, f, sa);
+      sa.ctl = &lctl;
       // zero the control block
-      u64* cw = (u64*)&ctl;
+      u64* cw = (u64*)&lctl;
       for (size_t w = 0; w < sizeof(Ctl) / sizeof(u64); ++w) cw[w] = 0;
-      ctl.kmin[0] = ctl.kmin[1] = kAllOnes;
-      ctl.delta = B.mesh_delta0[mi];
+      lctl.kmin[0] = lctl.kmin[1] = kAllOnes;
+      lctl.delta = B.mesh_delta0[mi];
+      s_slot = -1;
+      s_stop = 0;
     }
     team_sync();
-    const RoundArgs& a = sa;
     for (u64 i = t0; i < (u64)nv; i += stride) {
-      a.s.g[i] = i == (u64)B.field_src[f] ? 0ull : 0x7ff0000000000000ull;
-      a.s.fanth[i] = kAllOnes;
-      a.s.claim[i] = 0u;
+      sa.s.g[i] = i == (u64)B.field_src[f] ? 0ull : 0x7ff0000000000000ull;
+      sa.s.fanth[i] = kAllOnes;
+      sa.s.claim[i] = 0u;
     }
     for (u64 i = t0; i < (u64)nh; i += stride) {
-      a.s.as[i] = Split{0x7ff0000000000000ull, kAllOnes};
+      sa.s.as[i] = Split{0x7ff0000000000000ull, kAllOnes};
+    }
+    // every wavefront's initial values are in the L2 before the field is
+    // offered to helpers
+    __builtin_amdgcn_s_waitcnt(0);
+    team_sync();
+    if (threadIdx.x < (u32)kWave) Ph::init_fan_(sa, B.field_src[f], &lctl);
+    team_sync();
+    if (threadIdx.x < (u32)kWave) Ph::begin(sa, 0);
+    if (R && threadIdx.x == 0) {
+      // offer the field to helpers: the record first, then a board entry
+      sta(&R->team, (u64)t);
+      __builtin_amdgcn_s_waitcnt(0);
+      for (int b = 0; b < kBoard; ++b)
+        if (atomicCAS(&board[b], 0u, (u32)f + 1u) == 0u) {
+          s_slot = b;
+          break;
+        }
     }
     team_sync();
-    if (threadIdx.x < (u32)kWave) Ph::init_fan_(a, B.field_src[f], &ctl);
-    team_sync();
-    if (threadIdx.x < (u32)kWave) Ph::begin(a, 0);
-    team_sync();
-    int p = 0;
-    while (!ctl.done) {
-      Ph::partition(a, p, t0, stride);
-      team_sync();
-      Ph::propagate(a, p, 1, t0, stride);
-      team_sync();
-      for (int h = 2; h <= B.hops; ++h) {
-        if (ctl.nhop[h - 1] == 0) break;
-        Ph::propagate(a, p, h, t0, stride);
-        team_sync();
+    const int slot = s_slot;
+    bool global = false;  // counters in the gang record
+    u64 count = 0;        // handshakes published
+    int p = 0, ok = 1;
+    for (;;) {
+      if (threadIdx.x == 0) {
+        const u64 done = ld(&sa.ctl->done);
+        int nm = 1;
+        if (slot >= 0) {
+          sta(&R->prog, ld(&sa.ctl->tot[C_SEL]));
+          nm = 1 + (int)min(ld(&R->join), (u64)(B.gang_max - 1));
+          if (nm > 1 && !global) {
+            // the first round with helpers: move the counters to the record
+            const u64* src = (const u64*)&lctl;
+            u64* dst = (u64*)&R->ctl;
+            for (size_t w = 0; w < sizeof(Ctl) / sizeof(u64); ++w) dst[w] = src[w];
+            sa.ctl = &R->ctl;
+            global = true;
+          }
+          if (global && !done) {
+            ++count;
+            sta(&R->cnt[count & 1], 0ull);
+            __builtin_amdgcn_s_waitcnt(0);
+            sta(&R->word, (count << 8) | ((u64)p << 6) | (u64)nm);
+          }
+        }
+        s_nm = nm;
+        s_done = (int)done;
+        s_word = count;
       }
-      Ph::events1(a, p, t0, stride);
-      team_sync();
-      Ph::events2(a, p, t0, stride);
-      team_sync();
-      Ph::events3(a, p, t0, stride);
-      team_sync();
+      __syncthreads();
+      if (s_done) break;
+      if (!team_round<Ph, BS>(sa, p, 0, s_nm, R, (int)(s_word & 1), &s_ok)) {
+        ok = 0;
+        break;
+      }
       if (threadIdx.x < (u32)kWave) {
-        Ph::begin(a, 1 - p);
-        if (threadIdx.x == 0 && (int64_t)ctl.round > B.max_rounds) ctl.done = 1;
+        Ph::begin(sa, 1 - p);
+        if (threadIdx.x == 0 && (int64_t)ld(&sa.ctl->round) > B.max_rounds) sta(&sa.ctl->done, 1ull);
       }
-      team_sync();
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
       p ^= 1;
     }
-    const int64_t off = B.field_off[f];
-    for (u64 i = t0; i < (u64)nv; i += stride) B.out[off + i] = from_bits(lda(&a.s.g[i]));
+    if (slot >= 0 && threadIdx.x == 0) {
+      // release the helpers, withdraw the offer, and wait until every helper
+      // has left before the buffers take another field
+      ++count;
+      __builtin_amdgcn_s_waitcnt(0);
+      sta(&R->word, (count << 8) | (1ull << 7));
+      atomicExch(&board[slot], 0u);
+      const u64 t_end = wall_clock64() + kGangWait;
+      while (ld(&R->left) < ld(&R->join)) {
+        if (wall_clock64() > t_end) {
+          s_stop = 1;  // a helper may still run: leave these buffers alone
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      l1_invalidate();
+    }
+    __syncthreads();
+    const Ctl* c = sa.ctl;
+    if (ok) {
+      const int64_t off = B.field_off[f];
+      for (u64 i = t0; i < (u64)nv; i += stride) B.out[off + i] = from_bits(lda(&sa.s.g[i]));
+    }
     if (threadIdx.x == 0) {
       int64_t* st = B.fstat + (int64_t)f * kFieldStat;
-      st[0] = ctl.overflow ? 1 : ((int64_t)ctl.round > B.max_rounds ? 2 : 0);
-      st[1] = (int64_t)ctl.round;
-      st[2] = (int64_t)ctl.tot[C_SEL];
-      st[3] = (int64_t)(ctl.tot[C_KIDS] + ctl.tot[C_FANWIN]);
-      st[4] = (int64_t)ctl.tot[C_FANS];
-      st[5] = (int64_t)ctl.peak;
-      st[6] = (int64_t)ctl.tot[C_STALE];
+      const u64 rounds = ld(&c->round);
+      st[0] = !ok ? 3 : (ld(&c->overflow) ? 1 : ((int64_t)rounds > B.max_rounds ? 2 : 0));
+      st[1] = (int64_t)rounds;
+      st[2] = (int64_t)ld(&c->tot[C_SEL]);
+      st[3] = (int64_t)(ld(&c->tot[C_KIDS]) + ld(&c->tot[C_FANWIN]));
+      st[4] = (int64_t)ld(&c->tot[C_FANS]);
+      st[5] = (int64_t)ld(&c->peak);
+      st[6] = (int64_t)ld(&c->tot[C_STALE]);
       st[7] = (int64_t)(wall_clock64() - t_start);
+      st[8] = R ? (int64_t)ld(&R->join) : 0;
     }
     team_sync();
+    if (s_stop) return;
   }
 }
 
-__global__ void k_reset_queue(u64* q) { *q = 0ull; }
+// Start of a batch launch: empty queue, fresh gang records and board, every
+// field marked as not run (a kernel, not a memset, so that the launch can be
+// captured in a graph and replayed).
+__global__ void k_batch_reset(BatchDev B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *B.queue = 0ull;
+  if (i < B.n_fields) {
+    GangRec* R = B.gang + i;
+    R->word = 0ull;
+    R->join = 0ull;
+    R->left = 0ull;
+    R->abort = 0ull;
+    R->team = 0ull;
+    R->prog = 0ull;
+    R->cnt[0] = R->cnt[1] = 0ull;
+    B.fstat[(int64_t)i * kFieldStat] = kFieldNotRun;
+  }
+  if (i < kMaxXcc * kBoard) B.board[i] = 0u;
+}
 
 }  // namespace
 
@@ -2459,6 +2754,7 @@ struct pch_batch_s {
   std::vector<int32_t> fmesh, fsrc;
   std::vector<int64_t> off;  // n_fields + 1
   std::vector<int32_t> order;
+  std::vector<u64> cost;  // expected windows per field: the last run's, else 24 per half-edge
   std::vector<double> delta0;
   pch_batch_options o;
   int device = 0;
@@ -2471,7 +2767,10 @@ struct pch_batch_s {
   int64_t *d_nv = nullptr, *d_nh = nullptr, *d_off = nullptr, *d_fstat = nullptr;
   double* d_delta0 = nullptr;
   int32_t *d_fmesh = nullptr, *d_fsrc = nullptr, *d_order = nullptr;
+  u64* d_cost = nullptr;
   u64* d_queue = nullptr;
+  GangRec* d_gang = nullptr;
+  u32* d_board = nullptr;
   bool slots = false;
   hipStream_t stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -2494,6 +2793,14 @@ void drop_graph(pch_batch_s* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   b->gexec = nullptr;
   b->g_out = nullptr;
+}
+
+// Longest expected field first (longest processing time first).
+void sort_by_cost(pch_batch_s* b) {
+  const int nf = (int)b->cost.size();
+  b->order.resize(nf);
+  for (int f = 0; f < nf; ++f) b->order[f] = f;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
 }
 
 // (Re)allocates the per-workgroup buffers for the current options.
@@ -2528,6 +2835,7 @@ pch_status alloc_slots(pch_batch_s* b) {
   HIP_TRY(dalloc(&B.claim, T * b->max_nv));
   HIP_TRY(dalloc(&B.as, T * b->max_nh));
   b->slots = true;
+  B.gang_max = b->o.gang;
   B.max_nv = b->max_nv;
   B.max_nh = b->max_nh;
   B.k = b->o.k;
@@ -2539,7 +2847,8 @@ pch_status alloc_slots(pch_batch_s* b) {
 }
 
 void enqueue_batch(pch_batch_s* b, hipStream_t st) {
-  k_reset_queue<<<1, 1, 0, st>>>(b->d_queue);
+  const int nr = std::max<int>((int)b->fmesh.size(), kMaxXcc * kBoard);
+  k_batch_reset<<<(nr + 255) / 256, 256, 0, st>>>(b->B);
   if (b->o.team_threads == 1024)
     k_batch<1024><<<b->n_teams, 1024, 0, st>>>(b->B);
   else if (b->o.team_threads == 512)
@@ -2555,6 +2864,9 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
   HIP_TRY(hipStreamSynchronize(user));
   b->B.out = out;
   const int nf = (int)b->fmesh.size();
+  // the processing order and expected costs of this run (outside the graph)
+  HIP_TRY(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_cost, b->cost.data(), sizeof(u64) * nf, hipMemcpyHostToDevice, b->stream));
   if (b->o.use_graph) {
     if (!b->gexec || b->g_out != out) {
       drop_graph(b);
@@ -2598,9 +2910,13 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
     fs[5] = s1.peak_pool;
     fs[6] = s1.stale;
     fs[7] = 0;
+    fs[8] = 0;
     reruns++;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
+  // the next run orders and shares the fields by the windows they took now
+  for (int f = 0; f < nf; ++f) b->cost[f] = std::max<u64>(1, (u64)b->fstat[(size_t)f * kFieldStat + 2]);
+  sort_by_cost(b);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->fields = nf;
@@ -2634,6 +2950,7 @@ void pch_batch_options_default(pch_batch_options* o) {
   o->use_graph = 1;
   o->team_threads = 256;
   o->hops = 1;
+  o->gang = 1;
 }
 
 void pch_batch_destroy(pch_batch b) {
@@ -2641,7 +2958,8 @@ void pch_batch_destroy(pch_batch b) {
   drop_graph(b);
   free_slots(b);
   for (void* p : {(void*)b->d_meshes, (void*)b->d_nv, (void*)b->d_nh, (void*)b->d_off, (void*)b->d_fstat,
-                  (void*)b->d_delta0, (void*)b->d_fmesh, (void*)b->d_fsrc, (void*)b->d_order, (void*)b->d_queue})
+                  (void*)b->d_delta0, (void*)b->d_fmesh, (void*)b->d_fsrc, (void*)b->d_order, (void*)b->d_queue,
+                  (void*)b->d_gang, (void*)b->d_board, (void*)b->d_cost})
     (void)hipFree(p);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -2657,8 +2975,9 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   pch_batch_options_default(&o);
   if (opts) o = *opts;
   if (o.hops == 0) o.hops = 1;
+  if (o.gang == 0) o.gang = 1;
   if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 512 && o.team_threads != 1024) ||
-      o.hops < 1 || o.hops > kMaxHops)
+      o.hops < 1 || o.hops > kMaxHops || o.gang < 1 || o.gang > kMaxGang)
     return set_err(PCH_EINVAL, "bad batch option");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -2705,11 +3024,9 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   b->off.resize(n_fields + 1);
   b->off[0] = 0;
   for (int f = 0; f < n_fields; ++f) b->off[f + 1] = b->off[f] + nv[field_mesh[f]];
-  // largest meshes first (longest processing time first)
-  b->order.resize(n_fields);
-  for (int f = 0; f < n_fields; ++f) b->order[f] = f;
-  std::stable_sort(b->order.begin(), b->order.end(),
-                   [&](int x, int y) { return meshes[field_mesh[x]]->host.nf > meshes[field_mesh[y]]->host.nf; });
+  b->cost.resize(n_fields);
+  for (int f = 0; f < n_fields; ++f) b->cost[f] = 24 * (u64)nh[field_mesh[f]];
+  sort_by_cost(b);
   HIP_TRY(dalloc(&b->d_meshes, n_meshes));
   HIP_TRY(dalloc(&b->d_nv, n_meshes));
   HIP_TRY(dalloc(&b->d_nh, n_meshes));
@@ -2718,8 +3035,11 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   HIP_TRY(dalloc(&b->d_fsrc, n_fields));
   HIP_TRY(dalloc(&b->d_off, n_fields));
   HIP_TRY(dalloc(&b->d_order, n_fields));
+  HIP_TRY(dalloc(&b->d_cost, n_fields));
   HIP_TRY(dalloc(&b->d_fstat, (int64_t)n_fields * kFieldStat));
   HIP_TRY(dalloc(&b->d_queue, 1));
+  HIP_TRY(dalloc(&b->d_gang, n_fields));
+  HIP_TRY(dalloc(&b->d_board, kMaxXcc * kBoard));
   HIP_TRY(hipMemcpy(b->d_meshes, dm.data(), sizeof(DevMesh) * n_meshes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_nv, nv.data(), sizeof(int64_t) * n_meshes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_nh, nh.data(), sizeof(int64_t) * n_meshes, hipMemcpyHostToDevice));
@@ -2728,6 +3048,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   HIP_TRY(hipMemcpy(b->d_fsrc, field_source, sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * n_fields, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_cost, b->cost.data(), sizeof(u64) * n_fields, hipMemcpyHostToDevice));
   BatchDev& B = b->B;
   B.meshes = b->d_meshes;
   B.mesh_nv = b->d_nv;
@@ -2737,9 +3058,12 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   B.field_src = b->d_fsrc;
   B.field_off = b->d_off;
   B.order = b->d_order;
+  B.cost = b->d_cost;
   B.n_fields = n_fields;
   B.fstat = b->d_fstat;
   B.queue = b->d_queue;
+  B.gang = b->d_gang;
+  B.board = b->d_board;
   B.max_rounds = kMaxRounds;
   pch_status s = alloc_slots(b);
   if (s != PCH_OK) return s;
@@ -2774,8 +3098,23 @@ pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch
   const int64_t ks[] = {8192, 16384, 32768, 65536};
   const int shapes[][2] = {{256, 1}, {512, 1}, {1024, 1}};  // team threads, teams per CU
   const int hop_set[] = {1, 4};
+  const int gangs[] = {1, 2, 4, 16};
   pch_batch_options best = b->o;
   double best_ms = INFINITY;
+  auto trial = [&]() -> pch_status {
+    pch_status s = alloc_slots(b);
+    if (s != PCH_OK) return s;
+    pch_batch_stats st;
+    s = batch_run(b, dist, (hipStream_t)hip_stream, &st);
+    if (s != PCH_OK) return s;
+    if (st.ms_total < best_ms) {
+      best_ms = st.ms_total;
+      best = b->o;
+    }
+    return PCH_OK;
+  };
+  // k, workgroup shape and hops with up to 8 workgroups per field, then the
+  // gang size at the best of those
   for (const auto& sh : shapes) {
     for (int64_t k : ks) {
       for (int hops : hop_set) {
@@ -2783,17 +3122,17 @@ pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch
         b->o.team_threads = sh[0];
         b->o.teams_per_cu = sh[1];
         b->o.hops = hops;
-        pch_status s = alloc_slots(b);
+        b->o.gang = 8;
+        pch_status s = trial();
         if (s != PCH_OK) return s;
-        pch_batch_stats st;
-        s = batch_run(b, dist, (hipStream_t)hip_stream, &st);
-        if (s != PCH_OK) return s;
-        if (st.ms_total < best_ms) {
-          best_ms = st.ms_total;
-          best = b->o;
-        }
       }
     }
+  }
+  for (int gang : gangs) {
+    b->o = best;
+    b->o.gang = gang;
+    pch_status s = trial();
+    if (s != PCH_OK) return s;
   }
   b->o = best;
   pch_status s = alloc_slots(b);

@@ -202,7 +202,7 @@ def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_s
 class BatchOptions(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("teams_per_cu", ctypes.c_int32), ("filters", ctypes.c_int32),
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64), ("use_graph", ctypes.c_int32),
-                ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("gang", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -216,7 +216,8 @@ class BatchStats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
-BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "reserved"]
+BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "team_ticks",
+                     "helpers"]
 EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
             "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune"]
 

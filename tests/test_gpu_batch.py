@@ -79,6 +79,62 @@ def test_batch_equals_single_fields(pch, oracle, setup, use_graph, hops):
     b.close()
 
 
+@pytest.mark.parametrize("gang,tpc,threads", [(2, 1, 256), (8, 2, 256), (32, 1, 256), (4, 1, 1024), (8, 1, 512)])
+def test_batch_gangs_equal_single_fields(pch, setup, gang, tpc, threads):
+    """Workgroups that find the queue empty join running fields of their XCD;
+    the shared rounds give the single-field bits, on every replay."""
+    import torch
+    gens, meshes, fm, fs = setup
+    k = 256
+    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=tpc, team_threads=threads, hops=4, gang=gang)
+    say(f"batch of {b.n_fields} fields, gang {gang}, teams per CU {tpc}, {threads} threads")
+    refs = [single(pch, meshes[fm[f]], int(fs[f]), k, 4) for f in range(b.n_fields)]
+    out = None
+    for rep in range(3):
+        out, st = b.run(out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        fstat = b.field_stats()
+        assert st["reruns"] == 0 and np.all(fstat[:, 0] == 0), fstat[:, 0]
+        for f in range(b.n_fields):
+            gf = got[b.offsets[f]:b.offsets[f + 1]]
+            assert np.array_equal(gf.view(np.uint64), refs[f].view(np.uint64)), f"run {rep} field {f}"
+    b.close()
+
+
+def test_batch_gangs_many_fields(pch):
+    """More fields than workgroups (every XCD runs 32 or more teams): the last
+    fields are shared by the teams that ran out of work."""
+    import torch
+    gens = [G.bumpy_icosphere(2, seed=40 + i) for i in range(3)] + [G.bump_grid(40, seed=43)]
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    rng = np.random.default_rng(5)
+    fm = np.repeat(np.arange(len(gens)), 160)
+    fs = np.concatenate([rng.choice(m.nv, 160) for m in gens])
+    k = 512
+    say(f"{fm.size} fields, gang 8")
+    b1 = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, hops=4, gang=1)
+    b8 = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, hops=4, gang=8)
+    o1, st1 = b1.run()
+    f1 = b1.field_stats()
+    say(f"gang 1: status counts {np.bincount(f1[:, 0], minlength=5).tolist()}")
+    for rep in range(3):
+        o8, st = b8.run()
+        torch.cuda.synchronize()
+        f8 = b8.field_stats()
+        say(f"gang 8 run {rep}: status counts {np.bincount(f8[:, 0], minlength=5).tolist()}, "
+            f"rerun fields {np.nonzero(f8[:, 0])[0].tolist()}, helpers {int(f8[:, 8].sum())}")
+        # the shared rounds never give up (status 3) or leave a field unrun (4);
+        # pool overflows rerun the same fields as without helpers
+        assert np.array_equal(f8[:, 0] != 0, f1[:, 0] != 0), rep
+        assert np.array_equal(o8.cpu().numpy().view(np.uint64), o1.cpu().numpy().view(np.uint64)), rep
+    for f in rng.choice(fm.size, 6, replace=False):
+        ref = single(pch, meshes[fm[f]], int(fs[f]), k, 4)
+        assert np.array_equal(b1.field(o1, f).cpu().numpy().view(np.uint64), ref.view(np.uint64)), f
+    b1.close()
+    b8.close()
+
+
 @pytest.mark.parametrize("hops", [1, 3])
 def test_batch_overflow_reruns(pch, setup, hops):
     import torch
@@ -100,12 +156,15 @@ def test_batch_argument_errors(pch, setup):
         pch.Batch(meshes, [0], [gens[0].nv])
     with pytest.raises(pch.PchError):
         pch.Batch(meshes, [len(meshes)], [0])
+    for gang in (-1, 33):
+        with pytest.raises(pch.PchError):
+            pch.Batch(meshes, [0], [0], gang=gang)
 
 
 def test_tune_keeps_fields_exact(pch, setup):
-    """The autotuner times its grid of (k, workgroup shape, hops) settings on the
-    batch and keeps the fastest; the batch then still equals the single-field
-    runs with the chosen k and hops, bit for bit."""
+    """The autotuner times its grid of (k, workgroup shape, hops, gang size)
+    settings on the batch and keeps the fastest; the batch then still equals
+    the single-field runs with the chosen k and hops, bit for bit."""
     import torch
     gens, meshes, fm, fs = setup
     b = pch.Batch(meshes[:3], fm[fm < 3], fs[fm < 3], k=256, teams_per_cu=1)
@@ -114,6 +173,7 @@ def test_tune_keeps_fields_exact(pch, setup):
     say(f"tuned: {chosen}")
     assert chosen["k"] in (8192, 16384, 32768, 65536) and chosen["hops"] in (1, 4)
     assert (chosen["team_threads"], chosen["teams_per_cu"]) in ((256, 1), (512, 1), (1024, 1))
+    assert chosen["gang"] in (1, 2, 4, 8, 16)
     out, st = b.run(out)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
