@@ -171,12 +171,13 @@ pch_status pch_round_log(pch_mesh mesh, int64_t* out, int64_t max_rounds, int64_
 /* ------------------------------------------------------------------------
  * Batched fields: many independent single-source fields on meshes of uneven
  * size in one persistent launch. Each workgroup takes the next field from a
- * device queue (most expected windows first: 24 per half-edge before the
- * first run, then the windows each field took in the previous run) and runs
+ * device queue (most expected time first: 24 windows per half-edge before
+ * the first run, then the workgroup time each field took in the previous
+ * run) and runs
  * its rounds with the adaptive-step selection (PCH_SELECT_DELTA); results
  * equal pch_geodesic with the same k and delta0 bit for bit. With gang > 1 a
  * workgroup may instead join a running field of its own XCD when that field's
- * remaining windows per workgroup exceed the next queued field's; the field's
+ * expected time left per workgroup exceeds the next queued field's; the field's
  * rounds are then split over its workgroups from the next round on. Fields
  * whose windows outgrow a workgroup's pool are rerun with pch_geodesic.
  * ---------------------------------------------------------------------- */
@@ -222,15 +223,16 @@ pch_status pch_batch_offsets(pch_batch batch, int64_t* offsets);
 /* dist: device double [offsets[n_fields]] (caller-owned). */
 pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_batch_stats* stats);
 
-/* Per-field record of the last run, host int64 [n_fields][9]: status (0 ok;
- * rerun with pch_geodesic after 1 pool overflow, 2 the round limit, 3 a
+/* Per-field record of the last run, host int64 [n_fields][10]: status (0
+ * ok; rerun with pch_geodesic after 1 pool overflow, 2 the round limit, 3 a
  * shared field whose workgroups stopped waiting for each other, 4 a field no
  * workgroup finished), rounds, windows processed, windows created, fans,
  * peak pool, stale windows, the time from the start of the field to its end
  * in ticks of the device's constant-rate wall clock (100 MHz on MI355X; 0
- * after a rerun), and the helper workgroups that joined it. The windows
- * processed also set the next run's order (most first) and how helpers
- * choose among running fields. */
+ * after a rerun), the helper workgroups that joined it, and the ticks they
+ * spent in it. The time of leader and helpers and the windows processed set
+ * the next run's order (most time first) and how helpers choose among
+ * running fields. */
 pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
 
 /* Autotuner: times k in {8192, 16384, 32768, 65536} with workgroup shapes

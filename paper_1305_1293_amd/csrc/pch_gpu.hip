@@ -1643,11 +1643,12 @@ struct BatchDev {
   const int32_t* field_src;   // [n_fields]
   const int64_t* field_off;   // [n_fields] offset of the field in out
   const int32_t* order;       // [n_fields] processing order (largest cost first)
-  const u64* cost;            // [n_fields] expected windows of the field
+  const u64* cost;            // [n_fields] expected workgroup time of the field (any unit)
+  const u64* wins;            // [n_fields] expected windows of the field
   int32_t n_fields;           // fields taken from the queue
   double* out;                // concatenated distance fields
   int64_t* fstat;             // [n_fields][kFieldStat]
-  u64* queue;                 // next position in order
+  u64* queue;                 // [2]: next position in order, fields taken but not yet offered
   GangRec* gang;              // [n_fields] round handshake of the field's workgroups
   u32* board;                 // [kMaxXcc][kBoard] field + 1 of a running field that takes helpers, or 0
   // per-team buffers (team t uses slot t)
@@ -1671,8 +1672,9 @@ struct BatchDev {
   int64_t max_rounds;
 };
 
-// status, rounds, processed, created, fans, peak pool, stale, team time, helpers
-constexpr int kFieldStat = 9;
+// status, rounds, processed, created, fans, peak pool, stale, leader time,
+// helpers, helper time
+constexpr int kFieldStat = 10;
 constexpr int kMaxXcc = 16;    // XCD ids covered by the board
 constexpr int kBoard = 64;     // running fields per XCD that helpers can find
 constexpr int kMaxGang = 32;   // workgroups on one field
@@ -1693,7 +1695,8 @@ struct alignas(256) GangRec {
   u64 abort;  // 1 after a member's wait ran out of time
   u64 team;   // the leader's workgroup
   u64 prog;   // windows processed so far (published by the leader each round)
-  u64 pad0[10];
+  u64 hticks; // wall-clock ticks the helpers spent in the field
+  u64 pad0[9];
   u64 cnt[2];  // barrier arrivals in rounds of even and odd count
   u64 pad1[14];
   Ctl ctl;  // round counters from the first round with helpers on
@@ -1889,6 +1892,7 @@ __device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, in
 // whether the field is finished.
 template <class Ph, int BS>
 __device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int idx, RoundArgs& sa, int* s_ok, u64* s_word) {
+  const u64 t_join = wall_clock64();
   if (threadIdx.x == 0) {
     team_args(B, (int)ld(&R->team), (int)(R - B.gang), sa);
     sa.ctl = &R->ctl;
@@ -1921,6 +1925,7 @@ __device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int id
     if (!team_round<Ph, BS>(sa, (int)((w >> 6) & 1), idx, nm, R, (int)((w >> 8) & 1), s_ok)) break;
   }
   if (threadIdx.x == 0) {
+    atomicAdd(&R->hticks, wall_clock64() - t_join);
     __builtin_amdgcn_s_waitcnt(0);
     atomicAdd(&R->left, 1ull);
   }
@@ -1947,7 +1952,13 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
   const u32 xcc = xcc_id();
   const bool gangs = B.gang_max > 1 && xcc < (u32)kMaxXcc;
   u32* board = B.board + (size_t)(xcc < (u32)kMaxXcc ? xcc : 0) * kBoard;
-  int fails = 0;
+  int fails = 0, idle = 0;
+  if (gangs) {
+    // Stagger the first choice (about 0.8 us per eight workgroups), so that
+    // the leaders of the first fields have offered them when the later
+    // workgroups choose between joining one and taking the next field.
+    for (int i = 0; i < (t >> 3); ++i) __builtin_amdgcn_s_sleep(30);
+  }
   for (;;) {
     // Next work: the next field of the queue (longest expected first), or a
     // running field of this XCD whose remaining windows per workgroup, with
@@ -1963,15 +1974,20 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
           GangRec* Rc = B.gang + (e - 1u);
           const u64 j = ld(&Rc->join);
           if (j < (u64)(B.gang_max - 1) && !(ld(&Rc->word) & (1ull << 7))) {
-            const u64 cf = B.cost[e - 1u], pr = ld(&Rc->prog);
-            const u64 rem = cf > pr ? cf - pr : 1;
+            // expected time left: the cost times the share of its windows
+            // not processed yet
+            const u64 wf = B.wins[e - 1u], pr = ld(&Rc->prog);
+            const double left = wf > pr ? (double)(wf - pr) / (double)wf : 0.0;
+            const u64 rem = (u64)((double)B.cost[e - 1u] * left) + 1;
             key = (min(rem / (j + 2), (u64)0xffffffffu) << 32) | (u64)(0xffffffffu - (e - 1u));
           }
         }
         key = wave_max64(key);
       }
       if (threadIdx.x == 0) {
-        int pick = -1;  // >= 0: help that field; -1: no work left; -2: look again; -3: lead `cur`
+        // >= 0: help that field; -1: no work left; -2: look again; -3: lead
+        // `cur`; -4: a field was taken and is about to be offered
+        int pick = -1;
         const u64 q = ld(B.queue);
         const bool queued = q < (u64)B.n_fields;
         const u64 cq = queued ? B.cost[B.order[q]] : 0;
@@ -1991,7 +2007,10 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
             cur = B.order[q2];
             pick = -3;
           }
+        } else if (gangs && ld(B.queue + 1) > 0) {
+          pick = -4;
         }
+        if (pick == -3 && gangs) atomicAdd(B.queue + 1, 1ull);
         s_pick = pick;
       }
     }
@@ -2002,7 +2021,14 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       if (++fails > 4096) return;
       continue;
     }
+    if (pick == -4) {
+      // about 3.4 us per look; stop looking after about 2 s without work
+      if (++idle > 600000) return;
+      __builtin_amdgcn_s_sleep(127);
+      continue;
+    }
     fails = 0;
+    idle = 0;
     if (pick >= 0) {
       help_field<Ph, BS>(B, B.gang + pick, s_idx, sa, &s_ok, &s_word);
       continue;
@@ -2022,6 +2048,18 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       lctl.delta = B.mesh_delta0[mi];
       s_slot = -1;
       s_stop = 0;
+      if (R) {
+        // offer the field to helpers right away (they start with the first
+        // handshake): the record first, then a board entry
+        sta(&R->team, (u64)t);
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int b = 0; b < kBoard; ++b)
+          if (atomicCAS(&board[b], 0u, (u32)f + 1u) == 0u) {
+            s_slot = b;
+            break;
+          }
+        atomicSub(B.queue + 1, 1ull);
+      }
     }
     team_sync();
     for (u64 i = t0; i < (u64)nv; i += stride) {
@@ -2039,16 +2077,6 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     if (threadIdx.x < (u32)kWave) Ph::init_fan_(sa, B.field_src[f], &lctl);
     team_sync();
     if (threadIdx.x < (u32)kWave) Ph::begin(sa, 0);
-    if (R && threadIdx.x == 0) {
-      // offer the field to helpers: the record first, then a board entry
-      sta(&R->team, (u64)t);
-      __builtin_amdgcn_s_waitcnt(0);
-      for (int b = 0; b < kBoard; ++b)
-        if (atomicCAS(&board[b], 0u, (u32)f + 1u) == 0u) {
-          s_slot = b;
-          break;
-        }
-    }
     team_sync();
     const int slot = s_slot;
     bool global = false;  // counters in the gang record
@@ -2129,6 +2157,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       st[6] = (int64_t)ld(&c->tot[C_STALE]);
       st[7] = (int64_t)(wall_clock64() - t_start);
       st[8] = R ? (int64_t)ld(&R->join) : 0;
+      st[9] = R ? (int64_t)ld(&R->hticks) : 0;
     }
     team_sync();
     if (s_stop) return;
@@ -2140,7 +2169,10 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
 // captured in a graph and replayed).
 __global__ void k_batch_reset(BatchDev B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *B.queue = 0ull;
+  if (i == 0) {
+    B.queue[0] = 0ull;
+    B.queue[1] = 0ull;
+  }
   if (i < B.n_fields) {
     GangRec* R = B.gang + i;
     R->word = 0ull;
@@ -2149,6 +2181,7 @@ __global__ void k_batch_reset(BatchDev B) {
     R->abort = 0ull;
     R->team = 0ull;
     R->prog = 0ull;
+    R->hticks = 0ull;
     R->cnt[0] = R->cnt[1] = 0ull;
     B.fstat[(int64_t)i * kFieldStat] = kFieldNotRun;
   }
@@ -2754,7 +2787,8 @@ struct pch_batch_s {
   std::vector<int32_t> fmesh, fsrc;
   std::vector<int64_t> off;  // n_fields + 1
   std::vector<int32_t> order;
-  std::vector<u64> cost;  // expected windows per field: the last run's, else 24 per half-edge
+  std::vector<u64> cost;  // expected workgroup time per field: the last run's, else 24 per half-edge
+  std::vector<u64> wins;  // expected windows per field: the last run's, else 24 per half-edge
   std::vector<double> delta0;
   pch_batch_options o;
   int device = 0;
@@ -2767,7 +2801,7 @@ struct pch_batch_s {
   int64_t *d_nv = nullptr, *d_nh = nullptr, *d_off = nullptr, *d_fstat = nullptr;
   double* d_delta0 = nullptr;
   int32_t *d_fmesh = nullptr, *d_fsrc = nullptr, *d_order = nullptr;
-  u64* d_cost = nullptr;
+  u64 *d_cost = nullptr, *d_wins = nullptr;
   u64* d_queue = nullptr;
   GangRec* d_gang = nullptr;
   u32* d_board = nullptr;
@@ -2809,7 +2843,10 @@ pch_status alloc_slots(pch_batch_s* b) {
   drop_graph(b);
   BatchDev& B = b->B;
   const int nf = (int)b->fmesh.size();
-  b->n_teams = std::max(1, std::min(nf, b->o.teams_per_cu * b->n_cu));
+  // without helpers a workgroup per field at most; with them every resident
+  // slot, since the spare workgroups share the running fields
+  const int slots = b->o.teams_per_cu * b->n_cu;
+  b->n_teams = std::max(1, b->o.gang > 1 ? slots : std::min(nf, slots));
   int64_t cap = b->o.pool_capacity;
   // a team's pool holds at least three rounds' worth of windows (3 k)
   if (cap <= 0) cap = std::min<int64_t>(std::max<int64_t>({32768, b->max_nh / 12, 3 * b->o.k}), 1 << 21);
@@ -2867,6 +2904,7 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
   // the processing order and expected costs of this run (outside the graph)
   HIP_TRY(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_cost, b->cost.data(), sizeof(u64) * nf, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_wins, b->wins.data(), sizeof(u64) * nf, hipMemcpyHostToDevice, b->stream));
   if (b->o.use_graph) {
     if (!b->gexec || b->g_out != out) {
       drop_graph(b);
@@ -2911,11 +2949,29 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
     fs[6] = s1.stale;
     fs[7] = 0;
     fs[8] = 0;
+    fs[9] = 0;
     reruns++;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
-  // the next run orders and shares the fields by the windows they took now
-  for (int f = 0; f < nf; ++f) b->cost[f] = std::max<u64>(1, (u64)b->fstat[(size_t)f * kFieldStat + 2]);
+  // The next run orders and shares the fields by what they took now: the
+  // workgroup time of leader and helpers and the windows (a rerun field
+  // keeps its time at the batch's time per window).
+  {
+    double tk = 0.0, wn = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      const int64_t* fs = &b->fstat[(size_t)f * kFieldStat];
+      if (fs[7] > 0) {
+        tk += (double)(fs[7] + fs[9]);
+        wn += (double)fs[2];
+      }
+    }
+    const double per_win = wn > 0.0 ? tk / wn : 1.0;
+    for (int f = 0; f < nf; ++f) {
+      const int64_t* fs = &b->fstat[(size_t)f * kFieldStat];
+      b->wins[f] = std::max<u64>(1, (u64)fs[2]);
+      b->cost[f] = fs[7] > 0 ? (u64)(fs[7] + fs[9]) : std::max<u64>(1, (u64)(per_win * (double)fs[2]));
+    }
+  }
   sort_by_cost(b);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
@@ -2959,7 +3015,7 @@ void pch_batch_destroy(pch_batch b) {
   free_slots(b);
   for (void* p : {(void*)b->d_meshes, (void*)b->d_nv, (void*)b->d_nh, (void*)b->d_off, (void*)b->d_fstat,
                   (void*)b->d_delta0, (void*)b->d_fmesh, (void*)b->d_fsrc, (void*)b->d_order, (void*)b->d_queue,
-                  (void*)b->d_gang, (void*)b->d_board, (void*)b->d_cost})
+                  (void*)b->d_gang, (void*)b->d_board, (void*)b->d_cost, (void*)b->d_wins})
     (void)hipFree(p);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -3025,7 +3081,8 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   b->off[0] = 0;
   for (int f = 0; f < n_fields; ++f) b->off[f + 1] = b->off[f] + nv[field_mesh[f]];
   b->cost.resize(n_fields);
-  for (int f = 0; f < n_fields; ++f) b->cost[f] = 24 * (u64)nh[field_mesh[f]];
+  b->wins.resize(n_fields);
+  for (int f = 0; f < n_fields; ++f) b->cost[f] = b->wins[f] = 24 * (u64)nh[field_mesh[f]];
   sort_by_cost(b);
   HIP_TRY(dalloc(&b->d_meshes, n_meshes));
   HIP_TRY(dalloc(&b->d_nv, n_meshes));
@@ -3036,8 +3093,9 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   HIP_TRY(dalloc(&b->d_off, n_fields));
   HIP_TRY(dalloc(&b->d_order, n_fields));
   HIP_TRY(dalloc(&b->d_cost, n_fields));
+  HIP_TRY(dalloc(&b->d_wins, n_fields));
   HIP_TRY(dalloc(&b->d_fstat, (int64_t)n_fields * kFieldStat));
-  HIP_TRY(dalloc(&b->d_queue, 1));
+  HIP_TRY(dalloc(&b->d_queue, 2));
   HIP_TRY(dalloc(&b->d_gang, n_fields));
   HIP_TRY(dalloc(&b->d_board, kMaxXcc * kBoard));
   HIP_TRY(hipMemcpy(b->d_meshes, dm.data(), sizeof(DevMesh) * n_meshes, hipMemcpyHostToDevice));
@@ -3049,6 +3107,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   HIP_TRY(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * n_fields, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * n_fields, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_cost, b->cost.data(), sizeof(u64) * n_fields, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_wins, b->wins.data(), sizeof(u64) * n_fields, hipMemcpyHostToDevice));
   BatchDev& B = b->B;
   B.meshes = b->d_meshes;
   B.mesh_nv = b->d_nv;
@@ -3059,6 +3118,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   B.field_off = b->d_off;
   B.order = b->d_order;
   B.cost = b->d_cost;
+  B.wins = b->d_wins;
   B.n_fields = n_fields;
   B.fstat = b->d_fstat;
   B.queue = b->d_queue;

@@ -217,7 +217,7 @@ class BatchStats(ctypes.Structure):
 
 
 BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "team_ticks",
-                     "helpers"]
+                     "helpers", "helper_ticks"]
 EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
             "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune"]
 
