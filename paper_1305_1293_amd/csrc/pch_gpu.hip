@@ -679,7 +679,6 @@ __device__ __forceinline__ void block_totals(u64& kmn, u64& kmx, u32 (&v)[NV]) {
 __device__ __forceinline__ u64 ld(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ldd(const double* p) { return from_bits(ld((const u64*)p)); }
 
 // Lane 0's part of the round set-up for input parity p: log and total the
 // previous round, stop when nothing is left, reset this round's output buffers
@@ -1023,13 +1022,13 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
     f_sk = P.sk[t0];
     f_es = P.es[t0];
   }
-  const bool active = ld(&c->active) != 0;
-  const u64 N = active ? min(ld(&c->npool[p]), (u64)a.cap) : 0;
-  const int s = (int)ld(&c->shift);
-  const u64 T = ld(&c->want);
-  const bool all = ld(&c->sel_all);
-  const bool tab = ld(&c->use_table);
-  const double cv = ldd(&c->cutval);
+  const bool active = c->active != 0;
+  const u64 N = active ? min(c->npool[p], (u64)a.cap) : 0;
+  const int s = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
   u32 stale_n = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
@@ -1113,18 +1112,18 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     f_sk = S.sk[t0];
     f_es = S.es[t0];
   }
-  const bool active = ld(&c->active) != 0;
-  const u64 n_in = ld(hop <= 1 ? &c->nsel : &c->nhop[hop - 1]);
+  const bool active = c->active != 0;
+  const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
   const u64 N = active ? min(n_in, (u64)a.cap) : 0;
   const Pool Q = a.pool[1 - p];
   const bool to_hop = hop < a.hops;
   const Pool HQ = a.hq[(hop + 1) & 1];
   u64* nq_ctr = &c->nhop[hop < kMaxHops ? hop : kMaxHops];
-  const int sh = (int)ld(&c->shift);
-  const u64 T = ld(&c->want);
-  const bool all = ld(&c->sel_all);
-  const bool tab = ld(&c->use_table);
-  const double cv = ldd(&c->cutval);
+  const int sh = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
   const DistEv E = a.ev[p];
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
@@ -1132,7 +1131,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
     if (hop <= 1)
       c->cnt[C_SEL] = n_in;
     else
-      c->cnt[C_SEL] = ld(&c->cnt[C_SEL]) + n_in;
+      c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
   }
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
   u64 kmn = kAllOnes, kmx = 0;
@@ -1481,9 +1480,9 @@ __device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u
 __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
-  const bool active = ld(&c->active) != 0;
-  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
-  const u64 na = active ? min(ld(&c->naev), (u64)a.acap) : 0;
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   for (u64 i = t0; i < nd; i += stride) {
     const int32_t v = i == t0 ? f.vq.x : a.ev[p].vq[i].x;
     const double d = i == t0 ? f.d : a.ev[p].d[i];
@@ -1510,9 +1509,9 @@ __global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
-  const bool active = ld(&c->active) != 0;
-  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
-  const u64 na = active ? min(ld(&c->naev), (u64)a.acap) : 0;
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
@@ -1559,9 +1558,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
     f_d = a.ev[p].d[i0];
     f_th = a.ev[p].xy[i0].x;
   }
-  const bool active = ld(&c->active) != 0;
-  const u64 nd = active ? min(ld(&c->ndev[p]), (u64)a.ecap) : 0;
-  const u32 stamp = (u32)ld(&c->round);
+  const bool active = c->active != 0;
+  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u32 stamp = (u32)c->round;
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
@@ -1729,9 +1728,10 @@ __device__ __forceinline__ void l1_invalidate() { __builtin_amdgcn_fence(__ATOMI
 // Barrier of the nm workgroups of a gang round. Every wavefront first waits
 // for its own stores and atomics (they are then in the XCD's L2, which every
 // member reads through), one lane per workgroup arrives, and after the wait
-// the compute unit's L1 is dropped so that the next phase sees what the other
-// members wrote. Returns 0 when the gang gave up: some member's wait ran out
-// of time, which sets the gang's abort flag for all of them.
+// the compute unit's L1 is dropped, so that the next phase's plain loads (the
+// round counters included) see what the other members stored and updated
+// atomically. Returns 0 when the gang gave up: some member's wait ran out of
+// time, which sets the gang's abort flag for all of them.
 __device__ __forceinline__ int gang_sync(GangRec* R, int slot, u64 target, int* s_ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
