@@ -198,6 +198,10 @@ typedef struct {
                             with more than 1, a workgroup that finds no field
                             left joins a running field of its own XCD, whose
                             rounds are then split over its workgroups */
+  int64_t wait_ticks;    /* longest wait of a shared field's workgroups for each
+                            other, in ticks of the device's 100 MHz wall clock
+                            (0 = 2 s); when a wait runs out the field is rerun
+                            with pch_geodesic */
 } pch_batch_options;
 
 typedef struct {

@@ -1668,6 +1668,7 @@ struct BatchDev {
   int32_t hops;      // propagation hops per round
   int32_t nslot;     // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
   int32_t gang_max;  // workgroups per field (1: no helpers)
+  u64 wait;          // longest wait of a gang member, wall-clock ticks
   int64_t max_rounds;
 };
 
@@ -1677,8 +1678,9 @@ constexpr int kFieldStat = 10;
 constexpr int kMaxXcc = 16;    // XCD ids covered by the board
 constexpr int kBoard = 64;     // running fields per XCD that helpers can find
 constexpr int kMaxGang = 32;   // workgroups on one field
-// Longest wait of a gang member for the others, in ticks of the 100 MHz wall
-// clock (2 s): far above any round, so it only ends a wait that cannot end.
+// Default longest wait of a gang member for the others, in ticks of the
+// 100 MHz wall clock (2 s): far above any round, so it only ends a wait that
+// cannot end.
 constexpr u64 kGangWait = 200000000ull;
 // field status before a workgroup finishes it (the host reruns such fields)
 constexpr int64_t kFieldNotRun = 4;
@@ -1732,13 +1734,13 @@ __device__ __forceinline__ void l1_invalidate() { __builtin_amdgcn_fence(__ATOMI
 // round counters included) see what the other members stored and updated
 // atomically. Returns 0 when the gang gave up: some member's wait ran out of
 // time, which sets the gang's abort flag for all of them.
-__device__ __forceinline__ int gang_sync(GangRec* R, int slot, u64 target, int* s_ok) {
+__device__ __forceinline__ int gang_sync(GangRec* R, int slot, u64 target, u64 wait, int* s_ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     atomicAdd(&R->cnt[slot], 1ull);
     int ok = 1;
-    const u64 t_end = wall_clock64() + kGangWait;
+    const u64 t_end = wall_clock64() + wait;
     while (ld(&R->cnt[slot]) < target) {
       if (ld(&R->abort) || wall_clock64() > t_end) {
         sta(&R->abort, 1ull);
@@ -1860,7 +1862,8 @@ struct TeamPhases {
 // phases are separated by workgroup barriers, otherwise by gang barriers on
 // arrival counter `slot`. Returns 0 when the gang gave up.
 template <class Ph, int BS>
-__device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, int nm, GangRec* R, int slot, int* s_ok) {
+__device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, int nm, GangRec* R, int slot, u64 wait,
+                                          int* s_ok) {
   const u64 t0 = (u64)idx * BS + threadIdx.x, stride = (u64)nm * BS;
   u64 nb = 0;
   auto bar = [&]() -> int {
@@ -1868,7 +1871,7 @@ __device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, in
       team_sync();
       return 1;
     }
-    return gang_sync(R, slot, (u64)nm * ++nb, s_ok);
+    return gang_sync(R, slot, (u64)nm * ++nb, wait, s_ok);
   };
   Ph::partition(a, p, t0, stride);
   if (!bar()) return 0;
@@ -1901,7 +1904,7 @@ __device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int id
   for (;;) {
     __syncthreads();  // every wavefront has read the previous handshake
     if (threadIdx.x == 0) {
-      const u64 t_end = wall_clock64() + kGangWait;
+      const u64 t_end = wall_clock64() + B.wait;
       u64 w;
       for (;;) {
         w = ld(&R->word);
@@ -1922,7 +1925,7 @@ __device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int id
     seen = w;
     const int nm = (int)(w & 63);
     if (idx >= nm) continue;
-    if (!team_round<Ph, BS>(sa, (int)((w >> 6) & 1), idx, nm, R, (int)((w >> 8) & 1), s_ok)) break;
+    if (!team_round<Ph, BS>(sa, (int)((w >> 6) & 1), idx, nm, R, (int)((w >> 8) & 1), B.wait, s_ok)) break;
   }
   if (threadIdx.x == 0) {
     atomicAdd(&R->hticks, wall_clock64() - t_join);
@@ -2110,7 +2113,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       }
       __syncthreads();
       if (s_done) break;
-      if (!team_round<Ph, BS>(sa, p, 0, s_nm, R, (int)(s_word & 1), &s_ok)) {
+      if (!team_round<Ph, BS>(sa, p, 0, s_nm, R, (int)(s_word & 1), B.wait, &s_ok)) {
         ok = 0;
         break;
       }
@@ -2129,7 +2132,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       __builtin_amdgcn_s_waitcnt(0);
       sta(&R->word, (count << 8) | (1ull << 7));
       atomicExch(&board[slot], 0u);
-      const u64 t_end = wall_clock64() + kGangWait;
+      const u64 t_end = wall_clock64() + B.wait;
       while (ld(&R->left) < ld(&R->join)) {
         if (wall_clock64() > t_end) {
           s_stop = 1;  // a helper may still run: leave these buffers alone
@@ -2873,6 +2876,7 @@ pch_status alloc_slots(pch_batch_s* b) {
   HIP_TRY(dalloc(&B.as, T * b->max_nh));
   b->slots = true;
   B.gang_max = b->o.gang;
+  B.wait = b->o.wait_ticks > 0 ? (u64)b->o.wait_ticks : kGangWait;
   B.max_nv = b->max_nv;
   B.max_nh = b->max_nh;
   B.k = b->o.k;
@@ -3032,6 +3036,7 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   if (opts) o = *opts;
   if (o.hops == 0) o.hops = 1;
   if (o.gang == 0) o.gang = 1;
+  if (o.wait_ticks < 0) return set_err(PCH_EINVAL, "bad batch option");
   if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 512 && o.team_threads != 1024) ||
       o.hops < 1 || o.hops > kMaxHops || o.gang < 1 || o.gang > kMaxGang)
     return set_err(PCH_EINVAL, "bad batch option");

@@ -202,7 +202,8 @@ def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_s
 class BatchOptions(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("teams_per_cu", ctypes.c_int32), ("filters", ctypes.c_int32),
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64), ("use_graph", ctypes.c_int32),
-                ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("gang", ctypes.c_int32)]
+                ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("gang", ctypes.c_int32),
+                ("wait_ticks", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

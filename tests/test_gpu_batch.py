@@ -135,6 +135,26 @@ def test_batch_gangs_many_fields(pch):
     b8.close()
 
 
+def test_batch_gang_waits_run_out(pch, setup):
+    """A wait limit of one tick makes every shared field give up (forced from
+    the host: every wait in the kernel is bounded by it); such fields are
+    rerun with pch_geodesic, so every field still equals its single run."""
+    import torch
+    gens, meshes, fm, fs = setup
+    k = 256
+    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, hops=4, gang=8, wait_ticks=1)
+    out, st = b.run()
+    torch.cuda.synchronize()
+    fstat = b.field_stats()
+    say(f"status counts {np.bincount(fstat[:, 0], minlength=5).tolist()}, reruns {st['reruns']}")
+    assert st["reruns"] == int(np.count_nonzero(fstat[:, 0]))
+    got = out.cpu().numpy()
+    for f in range(b.n_fields):
+        ref = single(pch, meshes[fm[f]], int(fs[f]), k, 4)
+        assert np.array_equal(got[b.offsets[f]:b.offsets[f + 1]].view(np.uint64), ref.view(np.uint64)), f
+    b.close()
+
+
 @pytest.mark.parametrize("hops", [1, 3])
 def test_batch_overflow_reruns(pch, setup, hops):
     import torch
@@ -159,6 +179,8 @@ def test_batch_argument_errors(pch, setup):
     for gang in (-1, 33):
         with pytest.raises(pch.PchError):
             pch.Batch(meshes, [0], [0], gang=gang)
+    with pytest.raises(pch.PchError):
+        pch.Batch(meshes, [0], [0], wait_ticks=-1)
 
 
 def test_tune_keeps_fields_exact(pch, setup):
