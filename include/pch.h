@@ -132,7 +132,12 @@ typedef struct {
                                  sort on the half-edge index, 4096 buckets;
                                  data organization, Algorithm 3); the order
                                  changes no result (default 0) */
-  int32_t pad;
+  int32_t counts;             /* 1 = count windows created, events, fans and
+                                 dropped windows for pch_stats (default); 0 =
+                                 skip these statistics counters (fewer
+                                 same-address atomics per launch); rounds,
+                                 processed windows and timing are still
+                                 filled. collect_stats implies 1. */
 } pch_options;
 
 /* Fill opts with the defaults above. */

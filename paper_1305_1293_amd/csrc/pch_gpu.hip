@@ -205,6 +205,7 @@ struct RoundArgs {
   double pbin;          // width of a cdf bin
   double w0;            // windows per vertex before the first learned round
   int32_t hops;         // propagation hops per round (1 = each selected window once)
+  int32_t counts;       // 1 = count windows, events and drops (statistics only)
   // organization by edge: the selected windows are grouped by the bucket
   // e >> org_shift of their half-edge before they propagate (org_shift < 0: off)
   int32_t org_shift;
@@ -1084,7 +1085,7 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
   if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (tot[0]) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
+    if (tot[0] && a.counts) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
   }
 }
 
@@ -1387,13 +1388,15 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (tot[0]) atomicAdd(&c->cnt[C_TINY], (u64)tot[0]);
-    if (tot[1]) atomicAdd(&c->cnt[C_ICH], (u64)tot[1]);
-    if (tot[2]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[2]);
     if (tot[3]) atomicAdd(&c->nonfinite, (u64)tot[3]);
-    if (tot[4]) atomicAdd(&c->cnt[C_KIDS], (u64)tot[4]);
-    if (tot[5]) atomicAdd(&c->cnt[C_DEV], (u64)tot[5]);
-    if (tot[6]) atomicAdd(&c->cnt[C_AEV], (u64)tot[6]);
+    if (a.counts) {
+      if (tot[0]) atomicAdd(&c->cnt[C_TINY], (u64)tot[0]);
+      if (tot[1]) atomicAdd(&c->cnt[C_ICH], (u64)tot[1]);
+      if (tot[2]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[2]);
+      if (tot[4]) atomicAdd(&c->cnt[C_KIDS], (u64)tot[4]);
+      if (tot[5]) atomicAdd(&c->cnt[C_DEV], (u64)tot[5]);
+      if (tot[6]) atomicAdd(&c->cnt[C_AEV], (u64)tot[6]);
+    }
   }
 }
 
@@ -1597,11 +1600,13 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (tot[0]) atomicAdd(&c->cnt[C_FANWIN], (u64)tot[0]);
-    if (tot[1]) atomicAdd(&c->cnt[C_TINY], (u64)tot[1]);
-    if (tot[2]) atomicAdd(&c->cnt[C_ICH], (u64)tot[2]);
-    if (tot[3]) atomicAdd(&c->cnt[C_FANS], (u64)tot[3]);
-    if (tot[4]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[4]);
+    if (a.counts) {
+      if (tot[0]) atomicAdd(&c->cnt[C_FANWIN], (u64)tot[0]);
+      if (tot[1]) atomicAdd(&c->cnt[C_TINY], (u64)tot[1]);
+      if (tot[2]) atomicAdd(&c->cnt[C_ICH], (u64)tot[2]);
+      if (tot[3]) atomicAdd(&c->cnt[C_FANS], (u64)tot[3]);
+      if (tot[4]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[4]);
+    }
   }
 }
 
@@ -1801,6 +1806,7 @@ __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, Round
   a.cdf = nullptr;
   a.pbin = 0.0;
   a.w0 = 4.0;
+  a.counts = 1;
 }
 
 // Out-of-line phases for the persistent kernel: each gets its own register
@@ -2439,6 +2445,7 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.cdf = M->dcdf;
   a.pbin = 0.0;
   a.w0 = o.w0 > 0.0 ? o.w0 : 4.0;
+  a.counts = (o.counts != 0 || o.collect_stats != 0) ? 1 : 0;
   return a;
 }
 
@@ -2509,6 +2516,7 @@ void pch_options_default(pch_options* o) {
   o->cutoff_table = nullptr;
   o->n_cutoff = 0;
   o->hops = 1;
+  o->counts = 1;
 }
 
 pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len,

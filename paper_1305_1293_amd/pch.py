@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
                 ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("hops", ctypes.c_int32),
                 ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double),
-                ("organize", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("organize", ctypes.c_int32), ("counts", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -144,6 +144,23 @@ def test_organize_by_edge_changes_nothing(pch, oracle, hops):
         assert np.array_equal(log1, log_r)
 
 
+def test_counts_off_changes_no_result(pch):
+    """Without the statistics counters the rounds, the processed windows and
+    the distance bits are those of a run with them; the skipped counts read 0."""
+    import torch
+    for m, s, kw in [(G.bumpy_icosphere(4, seed=9), 17, dict(k=512, hops=4)),
+                     (G.bump_grid(48, seed=4), 100, dict(k=2048, select_mode=1, hops=1))]:
+        say(f"counts off {m.name} source {s} {kw}")
+        dm = pch.Mesh.from_generated(m)
+        d1, s1 = pch.geodesic(dm, [s], return_stats=True, counts=1, **kw)
+        d0, s0 = pch.geodesic(dm, [s], return_stats=True, counts=0, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(d0, d1)
+        assert (s0["rounds"], s0["processed"]) == (s1["rounds"], s1["processed"])
+        assert s1["created"] > 0 and s0["created"] == 0 and s0["dist_events"] == 0
+        dm.close()
+
+
 def test_grazing_boundary_regression(pch, oracle):
     m = G.bump_grid(96, seed=23)
     say("bump grid 96 seed 23 (grazing convex boundary)")
