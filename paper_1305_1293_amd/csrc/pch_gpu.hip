@@ -1690,10 +1690,10 @@ constexpr u64 kGangWait = 200000000ull;
 // field status before a workgroup finishes it (the host reruns such fields)
 constexpr int64_t kFieldNotRun = 4;
 
-// The workgroups that share one field once the field queue is empty: the
-// leader (the workgroup that took the field, whose buffers hold it) and the
-// helpers of the same XCD that joined it between rounds. All of them reach
-// the field's buffers through the one L2 of their XCD.
+// The workgroups that share one field: the leader (the workgroup that took
+// the field, whose buffers hold it) and the helpers of the same XCD that
+// joined it between rounds. All of them reach the field's buffers through the
+// one L2 of their XCD.
 struct alignas(256) GangRec {
   u64 word;   // round handshake: (count << 8) | (done << 7) | (parity << 6) | members
   u64 join;   // helpers that joined
@@ -1708,12 +1708,11 @@ struct alignas(256) GangRec {
   Ctl ctl;  // round counters from the first round with helpers on
 };
 
-// Barrier between the phases of one workgroup's field. Values updated with
-// device-scope atomics are read with agent-scope loads (lda), so the barrier
-// only has to order this workgroup's plain stores before the next phase: the
-// workgroup-scope release and acquire of the barrier itself do that (the
-// compute unit's L1 is shared by the workgroup's wavefronts). A device-scope
-// fence would also write back the L2 cache at every phase.
+// Barrier between the phases of a field that one workgroup runs alone: the
+// workgroup's wavefronts share the compute unit's L1 and its in-order vector
+// memory pipeline, so a plain workgroup barrier orders one phase's stores and
+// atomics before the next phase's loads. A device-scope fence would also
+// write back the L2 cache at every phase.
 __device__ __forceinline__ void team_sync() { __syncthreads(); }
 
 __device__ __forceinline__ void sta(u64* p, u64 v) {
@@ -1945,10 +1944,11 @@ __device__ __forceinline__ void help_field(const BatchDev& B, GangRec* R, int id
 // Algorithm 1 on it, the phases separated by workgroup barriers and the round
 // counters in LDS; fields never wait for each other. A field that outgrows
 // the team's pool is flagged for a rerun by the host. With gang_max > 1 a
-// running field accepts helpers: a workgroup that finds the queue empty joins
-// a running field of its own XCD, and from the next round on the field's
-// rounds are split over its members (the counters then live in the field's
-// gang record).
+// running field accepts helpers: a free workgroup joins a running field of
+// its own XCD when that field's expected time left per member exceeds the
+// next queued field's (or the queue is empty), and from the next round on the
+// field's rounds are split over its members (the counters then live in the
+// field's gang record).
 template <int BS>
 __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
   using Ph = TeamPhases<(BS > 512)>;
