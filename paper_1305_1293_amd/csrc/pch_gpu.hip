@@ -1673,6 +1673,7 @@ struct BatchDev {
   int32_t hops;      // propagation hops per round
   int32_t nslot;     // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
   int32_t gang_max;  // workgroups per field (1: no helpers)
+  int32_t n_store;   // workgroups with buffers of their own; the others only help
   u64 wait;          // longest wait of a gang member, wall-clock ticks
   int64_t max_rounds;
 };
@@ -1995,7 +1996,8 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       }
       if (threadIdx.x == 0) {
         // >= 0: help that field; -1: no work left; -2: look again; -3: lead
-        // `cur`; -4: a field was taken and is about to be offered
+        // `cur`; -4: a field is queued or about to be offered, and only a
+        // workgroup with buffers may lead it
         int pick = -1;
         const u64 q = ld(B.queue);
         const bool queued = q < (u64)B.n_fields;
@@ -2009,6 +2011,8 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
             pick = (int)f;
             s_idx = (int)j + 1;
           }
+        } else if (queued && t >= B.n_store) {
+          pick = -4;  // no buffers of its own: wait for a field to share
         } else if (queued) {
           const u64 q2 = atomicAdd(B.queue, 1ull);
           pick = -2;  // the queue ran out meanwhile
@@ -2864,7 +2868,9 @@ pch_status alloc_slots(pch_batch_s* b) {
   B.cap = cap;
   B.ecap = cap;
   B.acap = std::max<int64_t>(cap / 2, 1024);
-  const int64_t T = b->n_teams;
+  // buffers for the workgroups that may lead a field: one per field at most
+  const int64_t T = std::min<int64_t>(b->n_teams, nf);
+  B.n_store = (int32_t)T;
   B.hops = b->o.hops;
   B.nslot = B.hops > 1 ? 5 : 3;
   const int64_t np = T * B.nslot * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
