@@ -86,7 +86,7 @@ enum {
                            k / selected (clamped to [1/2, 2]); no histogram */
   PCH_SELECT_TABLE = 2,  /* per-round cutoff values from options.cutoff_table
                            (select key <= cutoff); after the table, KTH */
-  PCH_SELECT_LEARNED = 3 /* cutoff from predicted vertex distances
+  PCH_SELECT_LEARNED = 3, /* cutoff from predicted vertex distances
                            (options.predicted): with C(r) the number of
                            vertices predicted within r, m the pool's smallest
                            key and w the windows processed per vertex within m
@@ -95,6 +95,14 @@ enum {
                            1 and is scaled after each such round by
                            k / selected (clamped to [1/2, 2]); predictions
                            only steer the rounds, the distances stay exact */
+  PCH_SELECT_STRIDED = 4 /* the paper's approximate selection (Section 6):
+                           the pool scan runs on T = k threads (rounded up to
+                           whole workgroups) and thread i selects the nearest
+                           non-stale window among pool positions i, i + T,
+                           i + 2T, ...; one launch, no histogram; children
+                           of its rounds take no further hop. The result
+                           depends on the pool's layout (the distances do
+                           not) */
 };
 
 typedef struct {
@@ -166,8 +174,9 @@ pch_status pch_geodesic(pch_mesh mesh, const int32_t* sources, int32_t m, double
 
 /* Per-round integer log of the last pch_geodesic call on this mesh that had
  * opts->collect_stats set, one int64 [14] record per round:
- *   pool size at round start, cutoff (bit pattern >> shift, -1 = all),
- *   shift, selected, stale dropped, children kept, tiny dropped, ICH
+ *   pool size at round start, cutoff (bit pattern >> shift, -1 = all or
+ *   strided), shift (-2 table, -3 adaptive step, -4 learned, -5 strided
+ *   selection), selected, stale dropped, children kept, tiny dropped, ICH
  *   dropped, distance events from propagation, angle events, fans,
  *   fan windows kept, deferred fan events, pool size at round end.
  * Writes min(max_rounds, rounds) records to out (host); *n_rounds = rounds. */

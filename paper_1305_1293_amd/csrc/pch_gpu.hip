@@ -115,7 +115,8 @@ struct Ctl {
   u64 xcnt[X_NUM];
   u64 tot[C_NUM];   // totals over all rounds
   u64 peak;
-  u64 pad[8];
+  u64 smode;        // current round uses the strided selection
+  u64 pad[7];
 };
 
 // A pool of windows (Section 3, Figure 2): the interval [b0, b1] of
@@ -750,6 +751,7 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
   c->sel_all = 0;
   c->dmode = 0;
   c->lmode = 0;
+  c->smode = 0;
   c->rank = 0;
   const u64 r = round;  // index of the round being set up
   if (a.table && (int64_t)r < a.n_table) {
@@ -786,6 +788,13 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
     c->cutval = from_bits(mn) + delta;
     c->cnt[C_CUT] = bits(c->cutval);
     c->cnt[C_SHIFT] = (u64)(int64_t)-3;
+    return 0;
+  }
+  if (a.mode == PCH_SELECT_STRIDED) {
+    // each thread of the partition launch selects the nearest of its windows
+    c->smode = 1;
+    c->cnt[C_CUT] = (u64)(int64_t)-1;
+    c->cnt[C_SHIFT] = (u64)(int64_t)-5;
     return 0;
   }
   const u64 dif = mn ^ mx;
@@ -1030,6 +1039,23 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
   const bool all = c->sel_all;
   const bool tab = c->use_table;
   const double cv = c->cutval;
+  // Strided selection (Section 6, the approximate k-selection): the thread
+  // owns windows t0, t0 + stride, t0 + 2 stride, ... and selects the nearest
+  // of those that are not stale (the first one on equal keys).
+  const bool strided = c->smode != 0;
+  u64 imin = kAllOnes;
+  if (strided) {
+    double kbest = 0.0;
+    for (u64 i = t0; i < N; i += stride) {
+      const double2 wsk = i == t0 ? f_sk : P.sk[i];
+      const int32_t src = i == t0 ? f_es.y : P.es[i].y;
+      if (wsk.x > from_bits(lda(&a.s.g[src]))) continue;  // stale
+      if (imin == kAllOnes || wsk.y < kbest) {
+        kbest = wsk.y;
+        imin = i;
+      }
+    }
+  }
   u32 stale_n = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
@@ -1054,7 +1080,7 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
       if (stale) {
         stale_n++;
       } else {
-        sel = tab ? (key <= cv) : (all || ((bits(key) >> s) <= T));
+        sel = strided ? (all || i == imin) : (tab ? (key <= cv) : (all || ((bits(key) >> s) <= T)));
         keep = !sel;
       }
     }
@@ -1117,7 +1143,9 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
   const u64 N = active ? min(n_in, (u64)a.cap) : 0;
   const Pool Q = a.pool[1 - p];
-  const bool to_hop = hop < a.hops;
+  // children hop on when they pass the round's selection test; a strided
+  // round has no key test, so its children wait for the next round
+  const bool to_hop = hop < a.hops && c->smode == 0;
   const Pool HQ = a.hq[(hop + 1) & 1];
   u64* nq_ctr = &c->nhop[hop < kMaxHops ? hop : kMaxHops];
   const int sh = (int)c->shift;
@@ -2590,7 +2618,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   pch_options_default(&o);
   if (opts) o = *opts;
   if (o.select_mode != PCH_SELECT_KTH && o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_TABLE &&
-      o.select_mode != PCH_SELECT_LEARNED)
+      o.select_mode != PCH_SELECT_LEARNED && o.select_mode != PCH_SELECT_STRIDED)
     return set_err(PCH_EINVAL, "unknown select_mode");
   if (o.select_mode == PCH_SELECT_LEARNED && !o.predicted)
     return set_err(PCH_EINVAL, "learned selection needs predicted distances");
@@ -2710,7 +2738,11 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     // least 2k windows); its grid-stride loop covers any larger pool
     int pool_blocks = grid_for(std::max<int64_t>(2 * o.k, (int64_t)1 << 16), 1024);
     const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
-    const bool kth = o.select_mode != PCH_SELECT_DELTA;
+    const bool kth = o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_STRIDED;
+    // the strided selection runs the pool scan on k threads (whole
+    // workgroups): each selects the nearest of its windows
+    const bool strided = o.select_mode == PCH_SELECT_STRIDED;
+    if (strided) pool_blocks = grid_for(o.k, 1 << 30);
     int p = 0;
     bool overflow = false;
     prop_ms = 0.0;
@@ -2739,7 +2771,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
         }
       }
       rounds_before = host_ctl.round;
-      pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
+      if (!strided) pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
       if (host_ctl.overflow) {
         overflow = true;
         break;

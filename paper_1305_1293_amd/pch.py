@@ -20,6 +20,7 @@ PCH_SELECT_KTH = 0
 PCH_SELECT_DELTA = 1
 PCH_SELECT_TABLE = 2
 PCH_SELECT_LEARNED = 3
+PCH_SELECT_STRIDED = 4
 
 ROUND_LOG_FIELDS = ["N", "cutbits", "shift", "sel", "stale", "kids", "tiny", "ich", "dev", "aev",
                     "fans", "fanwin", "defer", "nend"]

@@ -144,6 +144,25 @@ def test_organize_by_edge_changes_nothing(pch, oracle, hops):
         assert np.array_equal(log1, log_r)
 
 
+@pytest.mark.parametrize("k,hops", [(64, 1), (1024, 1), (1024, 4)])
+def test_strided_selection_exact(pch, oracle, k, hops):
+    """The paper's approximate (strided) selection changes which windows a
+    round takes, not the distances: every vertex within 1e-9 of ICH; the
+    round log marks its rounds (shift -5), and such a round takes at most
+    one window per thread of its scan and no further hop."""
+    for m, s in [(G.config_mesh(1), 0), (G.bumpy_icosphere(4, seed=9), 17), (G.bump_grid(48, seed=4), 100),
+                 (G.cone_fan(7, 5), 5)]:
+        say(f"strided selection {m.name} source {s} k {k} hops {hops}")
+        d, st, log = gpu_field(pch, m, [s], k=k, hops=hops, select_mode=pch.PCH_SELECT_STRIDED, collect_stats=1)
+        ref, _ = oracle.ich(m, [s])
+        assert_close(d, ref, mean_edge(oracle, m), what=f"{m.name} strided k={k}")
+        strided = log[:, 2] == -5
+        if (log[:, 0] > k).any():
+            assert strided.any()
+        threads = ((k + 255) // 256) * 256
+        assert np.all(log[strided, 3] <= threads)
+
+
 def test_counts_off_changes_no_result(pch):
     """Without the statistics counters the rounds, the processed windows and
     the distance bits are those of a run with them; the skipped counts read 0."""
