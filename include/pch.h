@@ -260,6 +260,19 @@ pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
  * the batch and returns it in chosen (may be NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
 
+/* Geodesic Voronoi labels (the multi-source setting of Section 4 and the
+ * paper's outlook on Voronoi diagrams): for every vertex the index in
+ * sources[0..m) of its nearest source (ties to the lowest index; -1 when no
+ * source reaches it) and the distance to it. Computed as the m single-source
+ * fields in one batched launch (opts as for pch_batch_create; NULL =
+ * defaults) and a per-vertex minimum, so every distance is exact. dist
+ * (double) and label (int32) are caller-owned device arrays of nv entries;
+ * the call allocates m * nv doubles of device memory for the fields and
+ * returns after the work on hip_stream is done. Errors: as pch_batch_create,
+ * PCH_ENOMEM, PCH_EDEVICE. */
+pch_status pch_voronoi(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist, int32_t* label,
+                       void* hip_stream, const pch_batch_options* opts);
+
 /* ------------------------------------------------------------------------
  * Learned distance predictor for PCH_SELECT_LEARNED: an MLP 7 -> 64 -> 64 -> 1
  * (ReLU) on features [(v - c) / R, (s - c) / R, |v - s| / R] of vertex v,

@@ -2208,6 +2208,24 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
 // Start of a batch launch: empty queue, fresh gang records and board, every
 // field marked as not run (a kernel, not a memset, so that the launch can be
 // captured in a graph and replayed).
+// Geodesic Voronoi labels: per vertex the nearest of m fields (stored one
+// after another, nv values each) and its index, ties to the lowest index.
+__global__ void k_voronoi(const double* fields, int32_t m, int64_t nv, double* dist, int32_t* label) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    double best = fields[v];
+    int32_t arg = 0;
+    for (int32_t i = 1; i < m; ++i) {
+      const double d = fields[(int64_t)i * nv + v];
+      if (d < best) {
+        best = d;
+        arg = i;
+      }
+    }
+    dist[v] = best;
+    label[v] = isfinite(best) ? arg : -1;
+  }
+}
+
 __global__ void k_batch_reset(BatchDev B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
@@ -3250,6 +3268,34 @@ pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch
   if (s != PCH_OK) return s;
   if (chosen) *chosen = best;
   return PCH_OK;
+}
+
+pch_status pch_voronoi(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist, int32_t* label,
+                       void* hip_stream, const pch_batch_options* opts) {
+  if (!mesh || !sources || !dist || !label) return set_err(PCH_EINVAL, "null pointer argument");
+  if (m < 1) return set_err(PCH_EINVAL, "need at least one source");
+  const int64_t nv = mesh->host.nv;
+  std::vector<int32_t> fmesh(m, 0);
+  pch_batch b = nullptr;
+  pch_status s = pch_batch_create(&mesh, 1, fmesh.data(), sources, m, opts, &b);
+  if (s != PCH_OK) return s;
+  double* fields = nullptr;
+  hipError_t e = hipMalloc(&fields, sizeof(double) * (size_t)m * (size_t)nv);
+  if (e != hipSuccess) {
+    pch_batch_destroy(b);
+    return set_err(PCH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  s = pch_batch_run(b, fields, hip_stream, nullptr);
+  if (s == PCH_OK) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    k_voronoi<<<grid_for(nv, 1024), kBlock, 0, st>>>(fields, m, nv, dist, label);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = set_err(PCH_EDEVICE, std::string("voronoi: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(fields);
+  pch_batch_destroy(b);
+  return s;
 }
 
 }  // extern "C"

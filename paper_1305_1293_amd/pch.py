@@ -221,7 +221,7 @@ class BatchStats(ctypes.Structure):
 BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "team_ticks",
                      "helpers", "helper_ticks"]
 EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
-            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune"]
+            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune", "pch_voronoi"]
 
 
 def _batch_lib():
@@ -237,6 +237,7 @@ def _batch_lib():
         L.pch_batch_run.argtypes = [P, P, P, ctypes.POINTER(BatchStats)]
         L.pch_batch_field_stats.argtypes = [P, P]
         L.pch_batch_tune.argtypes = [P, P, P, ctypes.POINTER(BatchOptions)]
+        L.pch_voronoi.argtypes = [P, P, i32, P, P, P, ctypes.POINTER(BatchOptions)]
         L._batch_ready = True
     return L
 
@@ -305,6 +306,29 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def voronoi(mesh: Mesh, sources, stream=None, **opts):
+    """Geodesic Voronoi labels: per vertex the index of the nearest of
+    ``sources`` (-1 if none reaches it) and the distance to it, from the
+    single-source fields of all sources in one batched launch. Batch options
+    default to k 16384, 512-thread teams, 4 hops, up to 16 workgroups per
+    field."""
+    import torch
+    L = _batch_lib()
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    o = BatchOptions()
+    L.pch_batch_options_default(ctypes.byref(o))
+    for k, v in dict(dict(k=16384, team_threads=512, teams_per_cu=1, hops=4, gang=16), **opts).items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown batch option {k}")
+        setattr(o, k, v)
+    nv = int(mesh.nv)
+    dist = torch.empty(nv, dtype=torch.float64, device="cuda")
+    label = torch.empty(nv, dtype=torch.int32, device="cuda")
+    _check(L.pch_voronoi(mesh.handle, src.ctypes.data, src.size, dist.data_ptr(), label.data_ptr(),
+                         _stream_handle(stream), ctypes.byref(o)))
+    return dist, label
 
 
 # ---------------------------------------------------------------------------

@@ -170,6 +170,28 @@ def test_batch_overflow_reruns(pch, setup, hops):
     b1.close()
 
 
+def test_voronoi_labels(pch, oracle):
+    """Voronoi labels: each vertex's label is the first nearest source of the
+    single-source fields (argmin, ties to the lowest index) and its distance
+    their minimum, bit for bit; the minimum is the multi-source field of ICH
+    within 1e-9."""
+    import torch
+    for m, k in [(G.bumpy_icosphere(4, seed=9), 512), (G.bump_grid(48, seed=4), 1024)]:
+        srcs = np.random.default_rng(11).choice(m.nv, 7, replace=False).astype(np.int32)
+        say(f"voronoi {m.name}, {srcs.size} sources")
+        dm = pch.Mesh.from_generated(m)
+        dist, label = pch.voronoi(dm, srcs, k=k)
+        torch.cuda.synchronize()
+        fields = np.stack([single(pch, dm, int(s), k, 4) for s in srcs])
+        assert np.array_equal(label.cpu().numpy(), np.argmin(fields, axis=0).astype(np.int32))
+        assert np.array_equal(dist.cpu().numpy().view(np.uint64), fields.min(axis=0).view(np.uint64))
+        assert np.array_equal(label.cpu().numpy()[srcs], np.arange(srcs.size, dtype=np.int32))
+        ref, _ = oracle.ich(m, [int(s) for s in srcs])
+        hbar = float(oracle.lengths(m).mean())
+        assert np.max(np.abs(dist.cpu().numpy() - ref) / np.maximum(ref, hbar)) <= 1e-9
+        dm.close()
+
+
 def test_batch_argument_errors(pch, setup):
     gens, meshes, fm, fs = setup
     with pytest.raises(pch.PchError):
@@ -181,6 +203,8 @@ def test_batch_argument_errors(pch, setup):
             pch.Batch(meshes, [0], [0], gang=gang)
     with pytest.raises(pch.PchError):
         pch.Batch(meshes, [0], [0], wait_ticks=-1)
+    with pytest.raises(pch.PchError):
+        pch.voronoi(meshes[0], [gens[0].nv])
 
 
 def test_tune_keeps_fields_exact(pch, setup):
