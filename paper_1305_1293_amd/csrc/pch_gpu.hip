@@ -116,7 +116,8 @@ struct Ctl {
   u64 tot[C_NUM];   // totals over all rounds
   u64 peak;
   u64 smode;        // current round uses the strided selection
-  u64 pad[7];
+  u64 ncand;        // fan candidates of the current round
+  u64 pad[6];
 };
 
 // A pool of windows (Section 3, Figure 2): the interval [b0, b1] of
@@ -188,6 +189,7 @@ struct RoundArgs {
   Pool sel;
   Pool hq[2];      // hop queues: hop h reads hq[h & 1] (h >= 2), writes hq[(h + 1) & 1]
   DistEv ev[2];
+  DistEv cand;     // the round's events that won a pseudo-source vertex: (v, d, angle)
   AngEv aev;
   Ctl* ctl;
   u32* hist;
@@ -744,6 +746,7 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
   c->ndev[1 - p] = 0;
   c->nsel = 0;
   c->naev = 0;
+  c->ncand = 0;
   for (int h = 1; h < a.hops; ++h) c->nhop[h] = 0;
   c->kmin[1 - p] = kAllOnes;
   c->kmax[1 - p] = 0;
@@ -1554,15 +1557,29 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     const double d = i == t0 ? f.d : a.ev[p].d[i];
     const double2 xy = i == t0 ? f.xy : a.ev[p].xy[i];
     const int32_t v = vq.x;
-    if (bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO)) {
-      double th = xy.x;
-      if (vq.y >= 0) {
-        // evaluate the angle of a winning event and keep it for the fan pass
-        th = event_angle(a.m, vq.y, xy.x, xy.y);
-        a.ev[p].vq[i] = make_int2(v, -1);
-        a.ev[p].xy[i] = make_double2(th, 0.0);
-      }
+    const bool win = bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO);
+    double th = 0.0;
+    if (win) {
+      // the incoming angle of an event that wins a pseudo-source vertex
+      th = vq.y >= 0 ? event_angle(a.m, vq.y, xy.x, xy.y) : xy.x;
       atomicMin(&a.s.fanth[v], ordkey(th));
+    }
+    // the winners go to the fan pass's candidate list, one reservation per
+    // wavefront (lanes that already left the loop take no part)
+    const u64 mask = __ballot(win);
+    if (mask) {
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      u64 base = 0;
+      if (lane_id() == leader) base = atomicAdd(&c->ncand, (u64)__popcll(mask));
+      base = shfl64(base, leader);
+      if (win) {
+        const u64 j = base + (u64)__popcll(mask & ((1ull << lane_id()) - 1ull));
+        if (j < (u64)a.ecap) {
+          a.cand.vq[j] = make_int2(v, -1);
+          a.cand.d[j] = d;
+          a.cand.xy[j] = make_double2(th, 0.0);
+        }
+      }
     }
   }
 }
@@ -1580,17 +1597,17 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   // the few fans of a round spread over many compute units.
   const u64 nw = stride / kWave, w = t0 / kWave;
   const u64 i0 = w + nw * (u64)lane_id();
-  // the lane's first distance event is loaded together with the round's
-  // counters (indices below the capacity are in bounds)
+  // the lane's first candidate is loaded together with the round's counters
+  // (indices below the capacity are in bounds)
   int32_t f_v = 0;
   double f_d = 0.0, f_th = 0.0;
   if (i0 < (u64)a.ecap) {
-    f_v = a.ev[p].vq[i0].x;
-    f_d = a.ev[p].d[i0];
-    f_th = a.ev[p].xy[i0].x;
+    f_v = a.cand.vq[i0].x;
+    f_d = a.cand.d[i0];
+    f_th = a.cand.xy[i0].x;
   }
   const bool active = c->active != 0;
-  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
+  const u64 nd = active ? min(c->ncand, (u64)a.ecap) : 0;
   const u32 stamp = (u32)c->round;
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
@@ -1605,9 +1622,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
         d = f_d;
         th = f_th;
       } else {
-        v = a.ev[p].vq[i].x;
-        d = a.ev[p].d[i];
-        th = a.ev[p].xy[i].x;  // set by the second pass for every candidate
+        v = a.cand.vq[i].x;
+        d = a.cand.d[i];
+        th = a.cand.xy[i].x;
       }
       // everything that depends on v only, in one batch of loads
       const u64 gv = lda(&a.s.g[v]);
@@ -1686,7 +1703,7 @@ struct BatchDev {
   // per-team buffers (team t uses slot t)
   double2 *pbb, *ppp, *psk;  // [n_teams][nslot][cap]: pool 0, pool 1, selection, hop queues
   int2* pes;
-  int2* ev_vq;  // [n_teams][2][ecap]
+  int2* ev_vq;  // [n_teams][3][ecap]: events of parity 0 and 1, fan candidates
   double* ev_d;
   double2* ev_xy;
   int32_t* ae_e;  // [n_teams][acap]
@@ -1811,9 +1828,11 @@ __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, Round
   a.org_hist = nullptr;
   a.org_ofs = nullptr;
   for (int i = 0; i < 2; ++i) {
-    const int64_t o = ((int64_t)t * 2 + i) * B.ecap;
+    const int64_t o = ((int64_t)t * 3 + i) * B.ecap;
     a.ev[i] = DistEv{B.ev_vq + o, B.ev_d + o, B.ev_xy + o};
   }
+  const int64_t oc = ((int64_t)t * 3 + 2) * B.ecap;
+  a.cand = DistEv{B.ev_vq + oc, B.ev_d + oc, B.ev_xy + oc};
   const int64_t oa = (int64_t)t * B.acap;
   a.aev = AngEv{B.ae_e + oa, B.ae_D + oa, B.ae_X + oa};
   a.ctl = nullptr;
@@ -2281,6 +2300,7 @@ struct pch_mesh_s {
   int64_t sorted_cap = 0;
   u32 *org_hist = nullptr, *org_ofs = nullptr;
   DistEv ev[2] = {};
+  DistEv cand = {};
   AngEv aev = {};
   Ctl* ctl = nullptr;
   u32* hist = nullptr;
@@ -2331,6 +2351,10 @@ void free_work(pch_mesh_s* M) {
     (void)hipFree(M->ev[i].xy);
     M->ev[i] = DistEv{};
   }
+  (void)hipFree(M->cand.vq);
+  (void)hipFree(M->cand.d);
+  (void)hipFree(M->cand.xy);
+  M->cand = DistEv{};
   free_pool(M->sel);
   free_pool(M->hq[0]);
   free_pool(M->hq[1]);
@@ -2361,6 +2385,9 @@ pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
     HIP_TRY(dalloc(&M->ev[i].d, ecap));
     HIP_TRY(dalloc(&M->ev[i].xy, ecap));
   }
+  HIP_TRY(dalloc(&M->cand.vq, ecap));
+  HIP_TRY(dalloc(&M->cand.d, ecap));
+  HIP_TRY(dalloc(&M->cand.xy, ecap));
   HIP_TRY(alloc_pool(M->sel, cap));
   if (hop_queues) {
     HIP_TRY(alloc_pool(M->hq[0], cap));
@@ -2476,6 +2503,7 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.org_ofs = M->org_ofs;
   a.ev[0] = M->ev[0];
   a.ev[1] = M->ev[1];
+  a.cand = M->cand;
   a.aev = M->aev;
   a.ctl = M->ctl;
   a.hist = M->hist;
@@ -2923,7 +2951,7 @@ pch_status alloc_slots(pch_batch_s* b) {
   B.n_store = (int32_t)T;
   B.hops = b->o.hops;
   B.nslot = B.hops > 1 ? 5 : 3;
-  const int64_t np = T * B.nslot * B.cap, ne = T * 2 * B.ecap, na = T * B.acap;
+  const int64_t np = T * B.nslot * B.cap, ne = T * 3 * B.ecap, na = T * B.acap;
   HIP_TRY(dalloc(&B.pbb, np));
   HIP_TRY(dalloc(&B.ppp, np));
   HIP_TRY(dalloc(&B.psk, np));
