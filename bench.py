@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
     ap.add_argument("--hops", type=int, default=4, help="propagation hops per round")
+    ap.add_argument("--fuse-hops", type=int, default=1,
+                    help="1: all hops of a round in one propagation launch (hops <= 4); 0: one launch per hop")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-versus-plain measurement")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
@@ -227,7 +229,8 @@ def main():
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
     out = torch.empty(m.nv, dtype=torch.float64, device="cuda")
-    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0, hops=args.hops)
+    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0, hops=args.hops,
+                fuse_hops=args.fuse_hops)
 
     for i in range(args.warmup):
         pch.geodesic(mesh, [int(srcs[i])], out=out, **opts)
@@ -235,6 +238,7 @@ def main():
 
     keep = []
     tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0)
+    hop_launches = None
     t0 = time.perf_counter()
     for i in range(args.steps):
         # the statistics counters (windows created, events) stay off in the
@@ -242,6 +246,7 @@ def main():
         _, st = pch.geodesic(mesh, [int(srcs[args.warmup + i])], out=out, return_stats=True, counts=0, **opts)
         for kk in tot:
             tot[kk] += st[kk]
+        hop_launches = st["hop_launches"]
         if len(keep) < 8:
             keep.append(out.clone())
     torch.cuda.synchronize()
@@ -262,17 +267,18 @@ def main():
     kids = tot["created"] - tot["fan_windows"]
     prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
                   + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
-    # every round launches the propagation kernel once per hop; the HIP events
-    # bracket the launches of every n-th round
+    # every round launches the propagation kernel once (all hops fused) or
+    # once per hop; the HIP events bracket the launches of every n-th round
     timed = max(tot["propagate_launches"], 1)
     avg_launch_s = tot["ms_propagate"] / 1000.0 / timed
-    all_launches = max(tot["rounds"] * args.hops, 1)
+    all_launches = max(tot["rounds"] * hop_launches, 1)
     bytes_per_launch = prop_bytes / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = traffic_from_profile("icosphere7", f"select={args.select} k={args.k} hops={args.hops}")
+    traffic = traffic_from_profile("icosphere7", f"select={args.select} k={args.k} hops={args.hops} "
+                                                f"fuse_hops={args.fuse_hops}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_propagate", "avg_launch_us": round(avg_launch_s * 1e6, 3),
+                "kernel": "k_propagate_fused" if hop_launches == 1 and args.hops > 1 else "k_propagate", "avg_launch_us": round(avg_launch_s * 1e6, 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
                 "timed_launches": tot["propagate_launches"],
                 "propagate_share_of_wall": round(avg_launch_s * all_launches / wall, 4)}
@@ -314,7 +320,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, one seeded random "
                                "source per field", "faces": m.nf, "vertices": m.nv, "k": args.k,
-                   "select": ["kth", "adaptive-step"][args.select], "hops": args.hops},
+                   "select": ["kth", "adaptive-step"][args.select], "hops": args.hops,
+                   "propagation_launches_per_round": hop_launches},
         "windows_per_s": round(tot["processed"] / wall, 1),
         "fields_per_s": round(args.steps / wall, 3),
         "windows_per_field": round(tot["processed"] / args.steps, 1),

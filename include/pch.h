@@ -146,6 +146,12 @@ typedef struct {
                                  same-address atomics per launch); rounds,
                                  processed windows and timing are still
                                  filled. collect_stats implies 1. */
+  int32_t fuse_hops;          /* 1 = with hops <= 4, one launch propagates all
+                                 hops of a round: each workgroup takes the
+                                 hopping children of its own windows from
+                                 lists in LDS, depth first (default); 0 = one
+                                 launch per hop. Same windows, events and
+                                 results either way */
 } pch_options;
 
 /* Fill opts with the defaults above. */
@@ -158,6 +164,8 @@ typedef struct {
   double ms_propagate;       /* summed time of the timed propagation launches */
   int64_t propagate_launches; /* launches timed in ms_propagate (rounds with work) */
   double delta0;             /* first step used by PCH_SELECT_DELTA */
+  int64_t hop_launches;      /* propagation launches per round: 1 when the
+                                hops are fused, else hops */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).

@@ -1122,6 +1122,297 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
   ph_partition(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
+// Per-launch values of the propagation that every window reads.
+struct PropCtx {
+  Pool Q;    // the next round's pool
+  DistEv E;  // this round's distance events
+  int sh;    // selection test of a child: key bits >> sh <= T, or key <= cv
+  u64 T;
+  bool all, tab;
+  double cv;
+};
+
+// A lane's counts over the windows it propagated.
+struct PropAcc {
+  u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
+  u64 kmn = kAllOnes, kmx = 0;
+};
+
+// Algorithm 2 for one lane's window (have = false: the lane has none, but
+// still takes part in its wavefront's reservations, so every lane of the
+// wavefront calls this). Children that pass the round's selection test go
+// to HQ (capacity hq_cap) through the counter nq_ctr when to_hop is set,
+// the others to the next pool; events go to this round's buffers.
+__device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const PropCtx& x, bool have, double2 wbb,
+                                            double2 wpp, double2 wsk, int2 wes, bool to_hop, const Pool& HQ,
+                                            u64* nq_ctr, u64 hq_cap, PropAcc& acc) {
+  Ctl* c = a.ctl;
+  const DevMesh& m = a.m;
+  const u64* g = a.s.g;
+  // outputs of this lane, in fixed slots (no per-lane arrays, which would
+  // live in scratch memory): the left and right child, and the distance
+  // events at v0, v1 and v2
+  bool cl = false, cr = false;
+  double lb0 = 0, lb1 = 0, lpx = 0, lpy = 0, lkey = 0, rb0 = 0, rb1 = 0, rpx = 0, rpy = 0, rkey = 0;
+  int32_t le = 0, re = 0;
+  bool e0 = false, e1 = false, e2 = false;
+  int32_t ev0 = 0, ev1 = 0, ev2 = 0;
+  double ed0 = 0, ed1 = 0, ed2 = 0, epx = 0, epy = 0;
+  int32_t eq0 = -1, eq1 = -1, eq2 = -1;  // angle recipes (see DistEv)
+  bool has_aev = false;
+  double aD = 0, aX = 0;
+  double sg = 0;
+  int32_t src = 0, e = 0;
+  if (have) {
+    const double b0 = wbb.x, b1 = wbb.y, px = wpp.x, py = wpp.y;
+    epx = px;
+    epy = py;
+    sg = wsk.x;
+    e = wes.x;
+    src = wes.y;
+    // everything that depends on e only, in one batch of loads
+    const pch::HalfEdge h = m.hl[e].h;
+    const pch::HalfEdgeAng ha = m.hl[e].a;
+    const u64 ad_bits = lda(&a.s.as[e].D);
+    const u64 ax_bits = lda(&a.s.as[e].X);
+    const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
+    const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
+    const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
+    const double tol = kTau * L;
+    const double den = y2 - py;
+    const double t = (-py) / den;
+    const double X = px + (x2 - px) * t;
+    if (!isfinite(X)) acc.n_nonfin++;
+    const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
+    if (b0 <= tol) {
+      const double d = sg + sqrt(px * px + py * py);
+      if (d < g0 * kEv) {
+        e0 = true;
+        ev0 = v0;
+        ed0 = d;
+        eq0 = (h.pflags & 1) ? (e << 2) : -1;
+      }
+    }
+    if (b1 >= L - tol) {
+      const double dx = px - L;
+      const double d = sg + sqrt(dx * dx + py * py);
+      if (d < g1 * kEv) {
+        e1 = true;
+        ev1 = v1;
+        ed1 = d;
+        eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
+      }
+    }
+    bool doL = false, doR = false;
+    if (occ) {
+      const double dx = x2 - px, dy = y2 - py;
+      const double d2 = sg + sqrt(dx * dx + dy * dy);
+      if (d2 < g2 * kEv) {
+        e2 = true;
+        ev2 = v2;
+        ed2 = d2;
+        eq2 = (h.pflags & 4) ? ((e << 2) | 2) : -1;
+      }
+      if (!a.ch_on) {
+        doL = doR = true;
+      } else {
+        const double Ds = from_bits(ad_bits);
+        const double Xs = from_ordkey(ax_bits);
+        if (d2 < Ds) {
+          has_aev = true;
+          aD = d2;
+          aX = X;
+          doL = doR = true;
+        } else if (d2 <= Ds * kFm) {
+          doL = doR = true;  // a near-tie keeps both children
+        } else if (X < Xs - tol) {
+          doL = true;
+        } else if (X > Xs + tol) {
+          doR = true;
+        } else {
+          doL = doR = true;
+        }
+      }
+    } else if (X > b1) {
+      doL = true;
+    } else {
+      doR = true;
+    }
+    if (doL) {
+      if (h.tl < 0) {
+        acc.n_notwin++;
+      } else {
+        double s0, s1;
+        if (b0 == 0.0) {
+          s0 = 0.0;
+        } else {
+          const double dn0 = x2 * py + y2 * (b0 - px);
+          s0 = (py * b0) / dn0;
+        }
+        if (occ) {
+          s1 = 1.0;
+        } else {
+          const double dn1 = x2 * py + y2 * (b1 - px);
+          s1 = (py * b1) / dn1;
+        }
+        double c0 = s0 * l02, c1 = s1 * l02;
+        if (c0 < 0.0) c0 = 0.0;
+        if (c1 > l02) c1 = l02;
+        const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
+        const double cpx = ux * px + uy * py;
+        double cpy = ux * py - uy * px;
+        if (cpy > 0.0) cpy = 0.0;
+        const double rx = ux * c0 - L, ry = uy * c0;
+        const double rdist = sqrt(rx * rx + ry * ry);
+        const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
+        if (r == 1) {
+          acc.n_tiny++;
+        } else if (r == 2) {
+          acc.n_ich++;
+        } else {
+          cl = true;
+          lb0 = c0;
+          lb1 = c1;
+          lpx = cpx;
+          lpy = cpy;
+          lkey = window_key(c0, c1, cpx, cpy, sg);
+          le = h.tl;
+        }
+      }
+    }
+    if (doR) {
+      if (h.tr < 0) {
+        acc.n_notwin++;
+      } else {
+        const double ex = L - x2;
+        double r0, r1;
+        if (occ) {
+          r0 = 0.0;
+        } else {
+          const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
+          const double dn0 = y2 * (b0 - px) - ex * py;
+          r0 = nm0 / dn0;
+        }
+        if (b1 == L) {
+          r1 = 1.0;
+        } else {
+          const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
+          const double dn1 = y2 * (b1 - px) - ex * py;
+          r1 = nm1 / dn1;
+        }
+        double c0 = r0 * l12, c1 = r1 * l12;
+        if (c0 < 0.0) c0 = 0.0;
+        if (c1 > l12) c1 = l12;
+        const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
+        const double qx = px - x2, qy = py - y2;
+        const double cpx = ux * qx + uy * qy;
+        double cpy = ux * qy - uy * qx;
+        if (cpy > 0.0) cpy = 0.0;
+        const double rx = x2 + ux * c1, ry = y2 + uy * c1;
+        const double rdist = sqrt(rx * rx + ry * ry);
+        const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
+        if (r == 1) {
+          acc.n_tiny++;
+        } else if (r == 2) {
+          acc.n_ich++;
+        } else {
+          cr = true;
+          rb0 = c0;
+          rb1 = c1;
+          rpx = cpx;
+          rpy = cpy;
+          rkey = window_key(c0, c1, cpx, cpy, sg);
+          re = h.tr;
+        }
+      }
+    }
+  }
+  // children that pass the round's selection test go to the next hop
+  const bool ql = cl && to_hop && (x.tab ? (lkey <= x.cv) : (x.all || ((bits(lkey) >> x.sh) <= x.T)));
+  const bool qr = cr && to_hop && (x.tab ? (rkey <= x.cv) : (x.all || ((bits(rkey) >> x.sh) <= x.T)));
+  const int nk = (cl ? 1 : 0) + (cr ? 1 : 0);
+  const int nq = (ql ? 1 : 0) + (qr ? 1 : 0);
+  const int nd = (e0 ? 1 : 0) + (e1 ? 1 : 0) + (e2 ? 1 : 0);
+  // append children, distance events and angle events (one reservation per
+  // wavefront each)
+  u32 tk, td, ta, tq;
+  u64 jk, jd, ja, jq;
+  wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+                (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
+  auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
+    if (toq) {
+      const u64 j = jq++;
+      if (j < hq_cap)
+        store_window(HQ, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
+      else
+        flag_overflow(c);
+      return;
+    }
+    const u64 j = jk++;
+    if (j < (u64)a.cap) {
+      store_window(x.Q, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
+      const u64 kb = bits(ckey);
+      acc.kmn = kb < acc.kmn ? kb : acc.kmn;
+      acc.kmx = kb > acc.kmx ? kb : acc.kmx;
+    } else {
+      flag_overflow(c);
+    }
+  };
+  if (cl) put_child(ql, lb0, lb1, lpx, lpy, lkey, le);
+  if (cr) put_child(qr, rb0, rb1, rpx, rpy, rkey, re);
+  // the incoming angle of an event at a pseudo-source is evaluated later,
+  // only for the events that win their vertex (event_angle)
+  auto put_event = [&](int32_t v, double dv, int32_t q) {
+    const u64 j = jd++;
+    if (j < (u64)a.ecap) {
+      x.E.vq[j] = make_int2(v, q);
+      x.E.d[j] = dv;
+      x.E.xy[j] = q >= 0 ? make_double2(epx, epy) : make_double2(0.0, 0.0);
+    } else {
+      flag_overflow(c);
+    }
+  };
+  if (e0) put_event(ev0, ed0, eq0);
+  if (e1) put_event(ev1, ed1, eq1);
+  if (e2) put_event(ev2, ed2, eq2);
+  if (has_aev) {
+    if (ja < (u64)a.acap) {
+      a.aev.e[ja] = e;
+      a.aev.D[ja] = aD;
+      a.aev.X[ja] = aX;
+    } else {
+      flag_overflow(c);
+    }
+  }
+  // wavefront totals (the same on every lane), counted once by lane 0
+  if (lane_id() == 0) {
+    acc.n_kids += tk + tq;
+    acc.n_dev += td;
+    acc.n_aev += ta;
+  }
+}
+
+// End of a propagation launch: the workgroup's key range and counts.
+__device__ __forceinline__ void prop_finish(const RoundArgs& a, int p, PropAcc& acc) {
+  Ctl* c = a.ctl;
+  u64 kmn = acc.kmn, kmx = acc.kmx;
+  u32 tot[7] = {acc.n_tiny, acc.n_ich, acc.n_notwin, acc.n_nonfin, acc.n_kids, acc.n_dev, acc.n_aev};
+  block_totals(kmn, kmx, tot);
+  if (threadIdx.x == 0) {
+    if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
+    if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
+    if (tot[3]) atomicAdd(&c->nonfinite, (u64)tot[3]);
+    if (a.counts) {
+      if (tot[0]) atomicAdd(&c->cnt[C_TINY], (u64)tot[0]);
+      if (tot[1]) atomicAdd(&c->cnt[C_ICH], (u64)tot[1]);
+      if (tot[2]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[2]);
+      if (tot[4]) atomicAdd(&c->cnt[C_KIDS], (u64)tot[4]);
+      if (tot[5]) atomicAdd(&c->cnt[C_DEV], (u64)tot[5]);
+      if (tot[6]) atomicAdd(&c->cnt[C_AEV], (u64)tot[6]);
+    }
+  }
+}
+
 // Algorithm 2 for every selected window, against the round-start geod_dist
 // and angle_split (delayed update, Remark 3). Hop 1 takes the windows the
 // partition selected. With hops > 1 a child that passes the round's own
@@ -1156,279 +1447,27 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const bool all = c->sel_all;
   const bool tab = c->use_table;
   const double cv = c->cutval;
-  const DistEv E = a.ev[p];
-  const DevMesh& m = a.m;
-  const u64* g = a.s.g;
+  const PropCtx x{Q, a.ev[p], sh, T, all, tab, cv};
   if (t0 == 0 && active) {
     if (hop <= 1)
       c->cnt[C_SEL] = n_in;
     else
       c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
   }
-  u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
-  u64 kmn = kAllOnes, kmx = 0;
+  PropAcc acc;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
-    // outputs of this lane, in fixed slots (no per-lane arrays, which would
-    // live in scratch memory): the left and right child, and the distance
-    // events at v0, v1 and v2
-    bool cl = false, cr = false;
-    double lb0 = 0, lb1 = 0, lpx = 0, lpy = 0, lkey = 0, rb0 = 0, rb1 = 0, rpx = 0, rpy = 0, rkey = 0;
-    int32_t le = 0, re = 0;
-    bool e0 = false, e1 = false, e2 = false;
-    int32_t ev0 = 0, ev1 = 0, ev2 = 0;
-    double ed0 = 0, ed1 = 0, ed2 = 0, epx = 0, epy = 0;
-    int32_t eq0 = -1, eq1 = -1, eq2 = -1;  // angle recipes (see DistEv)
-    bool has_aev = false;
-    double aD = 0, aX = 0;
-    double sg = 0;
-    int32_t src = 0, e = 0;
-    if (i < N) {
-      const double2 wbb = i == t0 ? f_bb : S.bb[i];
-      const double2 wpp = i == t0 ? f_pp : S.pp[i];
-      const double2 wsk = i == t0 ? f_sk : S.sk[i];
-      const int2 wes = i == t0 ? f_es : S.es[i];
-      const double b0 = wbb.x, b1 = wbb.y, px = wpp.x, py = wpp.y;
-      epx = px;
-      epy = py;
-      sg = wsk.x;
-      e = wes.x;
-      src = wes.y;
-      // everything that depends on e only, in one batch of loads
-      const pch::HalfEdge h = m.hl[e].h;
-      const pch::HalfEdgeAng ha = m.hl[e].a;
-      const u64 ad_bits = lda(&a.s.as[e].D);
-      const u64 ax_bits = lda(&a.s.as[e].X);
-      const double L = h.L, x2 = h.x2, y2 = h.y2, l02 = h.l02, l12 = h.l12;
-      const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
-      const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
-      const double tol = kTau * L;
-      const double den = y2 - py;
-      const double t = (-py) / den;
-      const double X = px + (x2 - px) * t;
-      if (!isfinite(X)) n_nonfin++;
-      const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
-      if (b0 <= tol) {
-        const double d = sg + sqrt(px * px + py * py);
-        if (d < g0 * kEv) {
-          e0 = true;
-          ev0 = v0;
-          ed0 = d;
-          eq0 = (h.pflags & 1) ? (e << 2) : -1;
-        }
-      }
-      if (b1 >= L - tol) {
-        const double dx = px - L;
-        const double d = sg + sqrt(dx * dx + py * py);
-        if (d < g1 * kEv) {
-          e1 = true;
-          ev1 = v1;
-          ed1 = d;
-          eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
-        }
-      }
-      bool doL = false, doR = false;
-      if (occ) {
-        const double dx = x2 - px, dy = y2 - py;
-        const double d2 = sg + sqrt(dx * dx + dy * dy);
-        if (d2 < g2 * kEv) {
-          e2 = true;
-          ev2 = v2;
-          ed2 = d2;
-          eq2 = (h.pflags & 4) ? ((e << 2) | 2) : -1;
-        }
-        if (!a.ch_on) {
-          doL = doR = true;
-        } else {
-          const double Ds = from_bits(ad_bits);
-          const double Xs = from_ordkey(ax_bits);
-          if (d2 < Ds) {
-            has_aev = true;
-            aD = d2;
-            aX = X;
-            doL = doR = true;
-          } else if (d2 <= Ds * kFm) {
-            doL = doR = true;  // a near-tie keeps both children
-          } else if (X < Xs - tol) {
-            doL = true;
-          } else if (X > Xs + tol) {
-            doR = true;
-          } else {
-            doL = doR = true;
-          }
-        }
-      } else if (X > b1) {
-        doL = true;
-      } else {
-        doR = true;
-      }
-      if (doL) {
-        if (h.tl < 0) {
-          n_notwin++;
-        } else {
-          double s0, s1;
-          if (b0 == 0.0) {
-            s0 = 0.0;
-          } else {
-            const double dn0 = x2 * py + y2 * (b0 - px);
-            s0 = (py * b0) / dn0;
-          }
-          if (occ) {
-            s1 = 1.0;
-          } else {
-            const double dn1 = x2 * py + y2 * (b1 - px);
-            s1 = (py * b1) / dn1;
-          }
-          double c0 = s0 * l02, c1 = s1 * l02;
-          if (c0 < 0.0) c0 = 0.0;
-          if (c1 > l02) c1 = l02;
-          const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
-          const double cpx = ux * px + uy * py;
-          double cpy = ux * py - uy * px;
-          if (cpy > 0.0) cpy = 0.0;
-          const double rx = ux * c0 - L, ry = uy * c0;
-          const double rdist = sqrt(rx * rx + ry * ry);
-          const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
-          if (r == 1) {
-            n_tiny++;
-          } else if (r == 2) {
-            n_ich++;
-          } else {
-            cl = true;
-            lb0 = c0;
-            lb1 = c1;
-            lpx = cpx;
-            lpy = cpy;
-            lkey = window_key(c0, c1, cpx, cpy, sg);
-            le = h.tl;
-          }
-        }
-      }
-      if (doR) {
-        if (h.tr < 0) {
-          n_notwin++;
-        } else {
-          const double ex = L - x2;
-          double r0, r1;
-          if (occ) {
-            r0 = 0.0;
-          } else {
-            const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
-            const double dn0 = y2 * (b0 - px) - ex * py;
-            r0 = nm0 / dn0;
-          }
-          if (b1 == L) {
-            r1 = 1.0;
-          } else {
-            const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
-            const double dn1 = y2 * (b1 - px) - ex * py;
-            r1 = nm1 / dn1;
-          }
-          double c0 = r0 * l12, c1 = r1 * l12;
-          if (c0 < 0.0) c0 = 0.0;
-          if (c1 > l12) c1 = l12;
-          const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
-          const double qx = px - x2, qy = py - y2;
-          const double cpx = ux * qx + uy * qy;
-          double cpy = ux * qy - uy * qx;
-          if (cpy > 0.0) cpy = 0.0;
-          const double rx = x2 + ux * c1, ry = y2 + uy * c1;
-          const double rdist = sqrt(rx * rx + ry * ry);
-          const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
-          if (r == 1) {
-            n_tiny++;
-          } else if (r == 2) {
-            n_ich++;
-          } else {
-            cr = true;
-            rb0 = c0;
-            rb1 = c1;
-            rpx = cpx;
-            rpy = cpy;
-            rkey = window_key(c0, c1, cpx, cpy, sg);
-            re = h.tr;
-          }
-        }
-      }
+    const bool have = i < N;
+    double2 wbb = f_bb, wpp = f_pp, wsk = f_sk;
+    int2 wes = f_es;
+    if (have && i != t0) {
+      wbb = S.bb[i];
+      wpp = S.pp[i];
+      wsk = S.sk[i];
+      wes = S.es[i];
     }
-    // children that pass the round's selection test go to the next hop
-    const bool ql = cl && to_hop && (tab ? (lkey <= cv) : (all || ((bits(lkey) >> sh) <= T)));
-    const bool qr = cr && to_hop && (tab ? (rkey <= cv) : (all || ((bits(rkey) >> sh) <= T)));
-    const int nk = (cl ? 1 : 0) + (cr ? 1 : 0);
-    const int nq = (ql ? 1 : 0) + (qr ? 1 : 0);
-    const int nd = (e0 ? 1 : 0) + (e1 ? 1 : 0) + (e2 ? 1 : 0);
-    // append children, distance events and angle events (one reservation per
-    // wavefront each)
-    u32 tk, td, ta, tq;
-    u64 jk, jd, ja, jq;
-    wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
-                  (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
-    auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
-      if (toq) {
-        const u64 j = jq++;
-        if (j < (u64)a.cap)
-          store_window(HQ, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
-        else
-          flag_overflow(c);
-        return;
-      }
-      const u64 j = jk++;
-      if (j < (u64)a.cap) {
-        store_window(Q, j, cb0, cb1, cpx, cpy, sg, ckey, ce, src);
-        const u64 kb = bits(ckey);
-        kmn = kb < kmn ? kb : kmn;
-        kmx = kb > kmx ? kb : kmx;
-      } else {
-        flag_overflow(c);
-      }
-    };
-    if (cl) put_child(ql, lb0, lb1, lpx, lpy, lkey, le);
-    if (cr) put_child(qr, rb0, rb1, rpx, rpy, rkey, re);
-    // the incoming angle of an event at a pseudo-source is evaluated later,
-    // only for the events that win their vertex (event_angle)
-    auto put_event = [&](int32_t v, double dv, int32_t q) {
-      const u64 j = jd++;
-      if (j < (u64)a.ecap) {
-        E.vq[j] = make_int2(v, q);
-        E.d[j] = dv;
-        E.xy[j] = q >= 0 ? make_double2(epx, epy) : make_double2(0.0, 0.0);
-      } else {
-        flag_overflow(c);
-      }
-    };
-    if (e0) put_event(ev0, ed0, eq0);
-    if (e1) put_event(ev1, ed1, eq1);
-    if (e2) put_event(ev2, ed2, eq2);
-    if (has_aev) {
-      if (ja < (u64)a.acap) {
-        a.aev.e[ja] = e;
-        a.aev.D[ja] = aD;
-        a.aev.X[ja] = aX;
-      } else {
-        flag_overflow(c);
-      }
-    }
-    // wavefront totals (the same on every lane), counted once by lane 0
-    if (lane_id() == 0) {
-      n_kids += tk + tq;
-      n_dev += td;
-      n_aev += ta;
-    }
+    prop_window(a, p, x, have, wbb, wpp, wsk, wes, to_hop, HQ, nq_ctr, (u64)a.cap, acc);
   }
-  u32 tot[7] = {n_tiny, n_ich, n_notwin, n_nonfin, n_kids, n_dev, n_aev};
-  block_totals(kmn, kmx, tot);
-  if (threadIdx.x == 0) {
-    if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
-    if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
-    if (tot[3]) atomicAdd(&c->nonfinite, (u64)tot[3]);
-    if (a.counts) {
-      if (tot[0]) atomicAdd(&c->cnt[C_TINY], (u64)tot[0]);
-      if (tot[1]) atomicAdd(&c->cnt[C_ICH], (u64)tot[1]);
-      if (tot[2]) atomicAdd(&c->xcnt[X_NOTWIN], (u64)tot[2]);
-      if (tot[4]) atomicAdd(&c->cnt[C_KIDS], (u64)tot[4]);
-      if (tot[5]) atomicAdd(&c->cnt[C_DEV], (u64)tot[5]);
-      if (tot[6]) atomicAdd(&c->cnt[C_AEV], (u64)tot[6]);
-    }
-  }
+  prop_finish(a, p, acc);
 }
 
 // Organization by edge (Algorithm 3's reorganization, here as a one-pass
@@ -1482,6 +1521,100 @@ __global__ void __launch_bounds__(kBlock) k_org_scatter(RoundArgs a) {
 
 __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int hop) {
   ph_propagate(a, p, hop, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+}
+
+constexpr int kFuseHops = 4;          // hops that one fused launch carries
+constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
+
+// All hops of a round in one launch (hops <= kFuseHops). Each workgroup
+// propagates its share of the selected windows and, depth first, the
+// children that pass the round's selection test, from per-hop lists in LDS:
+// every step takes up to kBlock windows from the deepest non-empty list (its
+// next chunk of the selection when all lists are empty) and appends their
+// hopping children to the next hop's list. A list is filled only while every
+// deeper list is empty, from at most kBlock windows, so it never holds more
+// than 2 * kBlock. Every window propagates at the hop it would reach with one
+// launch per hop, against the same round-start values, so the round's
+// windows, events and counts are the same; three launches and their ramps
+// are saved per round.
+__global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) {
+  __shared__ double2 l_bb[kFuseHops - 1][kFuseCap], l_pp[kFuseHops - 1][kFuseCap], l_sk[kFuseHops - 1][kFuseCap];
+  __shared__ int2 l_es[kFuseHops - 1][kFuseCap];
+  __shared__ u64 l_n[kFuseHops + 1];  // l_n[h]: windows in the list of hop h (h >= 2)
+  Ctl* c = a.ctl;
+  const u64 t0 = blockIdx.x * (u64)kBlock + threadIdx.x, stride = (u64)gridDim.x * kBlock;
+  const Pool S = a.org_shift >= 0 ? a.sorted : a.sel;
+  // the lane's first window is loaded together with the round's counters
+  double2 f_bb = make_double2(0, 0), f_pp = f_bb, f_sk = f_bb;
+  int2 f_es = make_int2(0, 0);
+  if (t0 < (u64)a.cap) {
+    f_bb = S.bb[t0];
+    f_pp = S.pp[t0];
+    f_sk = S.sk[t0];
+    f_es = S.es[t0];
+  }
+  if (threadIdx.x <= (unsigned)kFuseHops) l_n[threadIdx.x] = 0;
+  const bool active = c->active != 0;
+  const u64 n_in = c->nsel;
+  const u64 N = active ? min(n_in, (u64)a.cap) : 0;
+  // a strided round has no key test, so its children wait for the next round
+  const bool hop_ok = c->smode == 0;
+  const int sh = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
+  const PropCtx x{a.pool[1 - p], a.ev[p], sh, T, all, tab, cv};
+  if (t0 == 0 && active) atomicAdd(&c->cnt[C_SEL], n_in);
+  __syncthreads();
+  PropAcc acc;
+  u64 base = blockIdx.x * (u64)kBlock;  // the workgroup's next chunk of the selection
+  u64 hopped = 0;                       // windows taken from the lists (thread 0)
+  int lvl = 1;                          // hop of the next step (the same in every thread)
+  for (;;) {
+    bool have;
+    double2 wbb = f_bb, wpp = f_pp, wsk = f_sk;
+    int2 wes = f_es;
+    if (lvl == 1) {
+      if (base >= N) break;
+      const u64 i = base + threadIdx.x;
+      have = i < N;
+      if (have && i != t0) {
+        wbb = S.bb[i];
+        wpp = S.pp[i];
+        wsk = S.sk[i];
+        wes = S.es[i];
+      }
+      base += stride;
+    } else {
+      const u64 n = l_n[lvl];
+      const u64 take = n < (u64)kBlock ? n : (u64)kBlock;
+      have = threadIdx.x < take;
+      if (have) {
+        const u64 j = n - take + threadIdx.x;
+        wbb = l_bb[lvl - 2][j];
+        wpp = l_pp[lvl - 2][j];
+        wsk = l_sk[lvl - 2][j];
+        wes = l_es[lvl - 2][j];
+      }
+      __syncthreads();  // every thread has its window before the list shrinks
+      if (threadIdx.x == 0) {
+        l_n[lvl] = n - take;
+        hopped += take;
+      }
+    }
+    const int nl = lvl < kFuseHops ? lvl + 1 : kFuseHops;
+    const Pool HQ{l_bb[nl - 2], l_pp[nl - 2], l_sk[nl - 2], l_es[nl - 2]};
+    prop_window(a, p, x, have, wbb, wpp, wsk, wes, hop_ok && lvl < a.hops, HQ, &l_n[nl], (u64)kFuseCap, acc);
+    __syncthreads();  // the next list and its length are visible
+    if (lvl < a.hops && l_n[lvl + 1] != 0) {
+      ++lvl;
+    } else {
+      while (lvl > 1 && l_n[lvl] == 0) --lvl;
+    }
+  }
+  if (threadIdx.x == 0 && hopped != 0) atomicAdd(&c->cnt[C_SEL], hopped);
+  prop_finish(a, p, acc);
 }
 
 // Algorithm 4, first pass: geod_dist and the angle_split distance take the
@@ -2536,11 +2669,11 @@ int grid_for(int64_t work, int max_blocks) {
 
 // Enqueue one round with input parity p (its set-up already ran: the initial
 // k_begin or the previous round's k_events3). ev0/ev1 (optional) bracket the
-// propagation launch.
+// propagation launches: one for all hops when fused, else one per hop.
 // Grids: the pool scan uses pool_blocks; propagation is sized for about twice
 // k windows; event passes and histograms use few blocks because their work is
 // small and the last-block ticket serializes one atomic per block.
-void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, int prop_blocks, bool kth,
+void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, int prop_blocks, bool kth, bool fused,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   if (kth)
     for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
@@ -2550,7 +2683,10 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
     k_org_scatter<<<prop_blocks, kBlock, 0, st>>>(a);
   }
   if (ev0) (void)hipEventRecord(ev0, st);
-  for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
+  if (fused)
+    k_propagate_fused<<<prop_blocks, kBlock, 0, st>>>(a, p);
+  else
+    for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
   if (ev1) (void)hipEventRecord(ev1, st);
   k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
@@ -2595,6 +2731,7 @@ void pch_options_default(pch_options* o) {
   o->n_cutoff = 0;
   o->hops = 1;
   o->counts = 1;
+  o->fuse_hops = 1;
 }
 
 pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len,
@@ -2784,6 +2921,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     // least 2k windows); its grid-stride loop covers any larger pool
     int pool_blocks = grid_for(std::max<int64_t>(2 * o.k, (int64_t)1 << 16), 1024);
     const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
+    const bool fused = o.fuse_hops != 0 && o.hops <= kFuseHops;
     const bool kth = o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_STRIDED;
     // the strided selection runs the pool scan on k threads (whole
     // workgroups): each selects the nearest of its windows
@@ -2798,9 +2936,9 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
       for (int r = 0; r < o.rounds_per_sync; ++r) {
         const bool timed = o.collect_timing && ((rounds_before + (u64)r) % (u64)o.collect_timing == 0);
         if (timed)
-          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, tev[2 * r], tev[2 * r + 1]);
+          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused, tev[2 * r], tev[2 * r + 1]);
         else
-          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth);
+          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused);
         p ^= 1;
       }
       HIP_TRY(hipGetLastError());
@@ -2813,7 +2951,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
           float ms = 0.f;
           HIP_TRY(hipEventElapsedTime(&ms, tev[2 * r], tev[2 * r + 1]));
           prop_ms += ms;
-          prop_n += o.hops;
+          prop_n += fused ? 1 : o.hops;
         }
       }
       rounds_before = host_ctl.round;
@@ -2864,6 +3002,7 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     stats->ms_propagate = prop_ms;
     stats->propagate_launches = prop_n;
+    stats->hop_launches = (o.fuse_hops != 0 && o.hops <= kFuseHops) ? 1 : o.hops;
     stats->delta0 = delta0;
   }
   return PCH_OK;

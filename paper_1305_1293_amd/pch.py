@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
                 ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("hops", ctypes.c_int32),
                 ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double),
-                ("organize", ctypes.c_int32), ("counts", ctypes.c_int32)]
+                ("organize", ctypes.c_int32), ("counts", ctypes.c_int32), ("fuse_hops", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ["rounds", "created", "processed", "stale", "tiny", "ich_dropped", "dist_events",
                  "angle_events", "fans", "fan_windows", "deferred", "peak_pool", "restarts"]] + \
                [("ms_total", ctypes.c_double), ("ms_propagate", ctypes.c_double),
-                ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double)]
+                ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double),
+                ("hop_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

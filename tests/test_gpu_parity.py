@@ -180,6 +180,33 @@ def test_counts_off_changes_no_result(pch):
         dm.close()
 
 
+@pytest.mark.parametrize("hops", [2, 3, 4])
+def test_fused_hops_equal_per_hop_launches(pch, hops):
+    """All hops of a round in one launch (hop lists in LDS, depth first) and
+    one launch per hop propagate the same windows at the same hops: per-round
+    records, statistics and distance bits are equal. k = 2^20 selects whole
+    pools, so the lists see their largest fills."""
+    import torch
+    for m, s, kw in [(G.config_mesh(1), 0, dict(k=1024)), (G.bumpy_icosphere(4, seed=9), 17, dict(k=1 << 20)),
+                     (G.bump_grid(48, seed=4), 100, dict(k=2048, select_mode=1, delta0=0.01)),
+                     (G.bumpy_icosphere(5, seed=3), 5, dict(k=16384, select_mode=1)),
+                     (G.bump_grid(64, seed=12), 0, dict(k=256, select_mode=4))]:
+        say(f"fused hops {hops} {m.name} source {s} {kw}")
+        d0, s0, log0 = gpu_field(pch, m, [s], collect_stats=1, hops=hops, fuse_hops=0, **kw)
+        d1, s1, log1 = gpu_field(pch, m, [s], collect_stats=1, hops=hops, fuse_hops=1, **kw)
+        torch.cuda.synchronize()
+        assert s0["hop_launches"] == hops and s1["hop_launches"] == 1
+        assert s0["restarts"] == 0 and s1["restarts"] == 0
+        if kw.get("select_mode") != 4:  # the strided selection depends on the pool's layout
+            assert np.array_equal(log0, log1)
+            assert np.array_equal(d0.view(np.uint64), d1.view(np.uint64))
+            for key in ("rounds", "processed", "created", "dist_events", "angle_events", "fans", "fan_windows"):
+                assert s0[key] == s1[key], key
+        else:
+            hbar = float(np.mean(np.linalg.norm(m.xyz[m.faces[:, 0]] - m.xyz[m.faces[:, 1]], axis=1)))
+            assert np.max(np.abs(d0 - d1) / np.maximum(d0, hbar)) <= 1e-9
+
+
 def test_grazing_boundary_regression(pch, oracle):
     m = G.bump_grid(96, seed=23)
     say("bump grid 96 seed 23 (grazing convex boundary)")
@@ -279,6 +306,12 @@ def test_full_size_bumpy_icosphere_all_vertices(pch, oracle):
     d, st, _ = gpu_field(pch, m, [s], k=16384)
     assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7")
     say(f"  rounds {st['rounds']} processed {st['processed']}")
+    # the launch configuration of the timed benchmark: adaptive step, 4 hops
+    # in one launch per round
+    d, st, _ = gpu_field(pch, m, [s], k=16384, select_mode=1, hops=4)
+    assert st["hop_launches"] == 1
+    assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7, adaptive step, 4 hops")
+    say(f"  adaptive step, 4 hops: rounds {st['rounds']} processed {st['processed']}")
 
 
 def test_full_size_bump_grid_samples_and_properties(pch, oracle):
