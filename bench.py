@@ -183,12 +183,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["field", "learned"], default="field")
-    ap.add_argument("--k", type=int, default=16384, help="windows selected per round")
+    ap.add_argument("--k", type=int, default=12288, help="windows selected per round")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
-    ap.add_argument("--hops", type=int, default=4, help="propagation hops per round")
+    ap.add_argument("--hops", type=int, default=5, help="propagation hops per round")
     ap.add_argument("--fuse-hops", type=int, default=1,
-                    help="1: all hops of a round in one propagation launch (hops <= 4); 0: one launch per hop")
+                    help="1: all hops of a round in one propagation launch (hops <= 6); 0: one launch per hop")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-versus-plain measurement")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")

@@ -146,7 +146,7 @@ typedef struct {
                                  same-address atomics per launch); rounds,
                                  processed windows and timing are still
                                  filled. collect_stats implies 1. */
-  int32_t fuse_hops;          /* 1 = with hops <= 4, one launch propagates all
+  int32_t fuse_hops;          /* 1 = with hops <= 6, one launch propagates all
                                  hops of a round: each workgroup takes the
                                  hopping children of its own windows from
                                  lists in LDS, depth first (default); 0 = one

@@ -282,6 +282,57 @@ __device__ __forceinline__ void wave_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, 
   s3 = shfl64(b3, kWave - 1) + (excl >> 24);
 }
 
+// The four reservations of wave_reserve4 for a whole workgroup: one atomic
+// per counter and workgroup instead of one per wavefront, so 4x fewer
+// same-address atomics meet at the counters. Every thread of the workgroup
+// must call it (it holds two barriers); a counter may be in LDS.
+__device__ __forceinline__ void block_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64* c3, u32 n3,
+                                               u64& s0, u64& s1, u64& s2, u64& s3, u32& t0, u32& t1, u32& t2,
+                                               u32& t3) {
+  constexpr int kW = kBlock / kWave;
+  __shared__ u32 s_w[kW][4];  // wavefront totals
+  __shared__ u64 s_b[kW][4];  // wavefront bases
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const u32 x = n0 | (n1 << 8) | (n2 << 16) | (n3 << 24);
+  u32 incl = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const u32 y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const u32 tot = __shfl(incl, kWave - 1, kWave);
+  const u32 excl = incl - x;
+  t0 = tot & 0xffu;
+  t1 = (tot >> 8) & 0xffu;
+  t2 = (tot >> 16) & 0xffu;
+  t3 = tot >> 24;
+  if (lane == kWave - 1) {
+    s_w[w][0] = t0;
+    s_w[w][1] = t1;
+    s_w[w][2] = t2;
+    s_w[w][3] = t3;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int j = threadIdx.x;
+    u64* cj = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
+    u32 sum = 0;
+#pragma unroll
+    for (int q = 0; q < kW; ++q) sum += s_w[q][j];
+    u64 base = sum ? atomicAdd(cj, (u64)sum) : 0;
+#pragma unroll
+    for (int q = 0; q < kW; ++q) {
+      s_b[q][j] = base;
+      base += s_w[q][j];
+    }
+  }
+  __syncthreads();
+  s0 = s_b[w][0] + (excl & 0xffu);
+  s1 = s_b[w][1] + ((excl >> 8) & 0xffu);
+  s2 = s_b[w][2] + ((excl >> 16) & 0xffu);
+  s3 = s_b[w][3] + (excl >> 24);
+}
+
 // Three reservations (per-lane counts at most 3), as wave_reserve4.
 __device__ __forceinline__ void wave_reserve3(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64& s0, u64& s1,
                                               u64& s2, u32& t0, u32& t1, u32& t2) {
@@ -1139,10 +1190,12 @@ struct PropAcc {
 };
 
 // Algorithm 2 for one lane's window (have = false: the lane has none, but
-// still takes part in its wavefront's reservations, so every lane of the
-// wavefront calls this). Children that pass the round's selection test go
-// to HQ (capacity hq_cap) through the counter nq_ctr when to_hop is set,
-// the others to the next pool; events go to this round's buffers.
+// still takes part in the reservations, so every lane of the wavefront, or
+// of the workgroup with kBlockRes, calls this). Children that pass the
+// round's selection test go to HQ (capacity hq_cap) through the counter
+// nq_ctr when to_hop is set, the others to the next pool; events go to this
+// round's buffers.
+template <bool kBlockRes>
 __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const PropCtx& x, bool have, double2 wbb,
                                             double2 wpp, double2 wsk, int2 wes, bool to_hop, const Pool& HQ,
                                             u64* nq_ctr, u64 hq_cap, PropAcc& acc) {
@@ -1337,8 +1390,12 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   // wavefront each)
   u32 tk, td, ta, tq;
   u64 jk, jd, ja, jq;
-  wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
-                (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
+  if constexpr (kBlockRes)
+    block_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+                   (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
+  else
+    wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+                  (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
   auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
     if (toq) {
       const u64 j = jq++;
@@ -1465,7 +1522,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       wsk = S.sk[i];
       wes = S.es[i];
     }
-    prop_window(a, p, x, have, wbb, wpp, wsk, wes, to_hop, HQ, nq_ctr, (u64)a.cap, acc);
+    prop_window<false>(a, p, x, have, wbb, wpp, wsk, wes, to_hop, HQ, nq_ctr, (u64)a.cap, acc);
   }
   prop_finish(a, p, acc);
 }
@@ -1523,7 +1580,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int ho
   ph_propagate(a, p, hop, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
-constexpr int kFuseHops = 4;          // hops that one fused launch carries
+constexpr int kFuseHops = 6;          // hops that one fused launch carries
 constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
 
 // All hops of a round in one launch (hops <= kFuseHops). Each workgroup
@@ -1605,7 +1662,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
     }
     const int nl = lvl < kFuseHops ? lvl + 1 : kFuseHops;
     const Pool HQ{l_bb[nl - 2], l_pp[nl - 2], l_sk[nl - 2], l_es[nl - 2]};
-    prop_window(a, p, x, have, wbb, wpp, wsk, wes, hop_ok && lvl < a.hops, HQ, &l_n[nl], (u64)kFuseCap, acc);
+    prop_window<true>(a, p, x, have, wbb, wpp, wsk, wes, hop_ok && lvl < a.hops, HQ, &l_n[nl], (u64)kFuseCap, acc);
     __syncthreads();  // the next list and its length are visible
     if (lvl < a.hops && l_n[lvl + 1] != 0) {
       ++lvl;
