@@ -55,10 +55,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload_tag: str, config_tag: str):
+def traffic_from_profile(kernel: str, workload_tag: str, config_tag: str):
     """HBM bytes per propagation launch from the committed counter summary, or
     None when the summary is missing or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", f"k_propagate_{workload_tag}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_tag}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -274,11 +274,12 @@ def main():
     all_launches = max(tot["rounds"] * hop_launches, 1)
     bytes_per_launch = prop_bytes / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = traffic_from_profile("icosphere7", f"select={args.select} k={args.k} hops={args.hops} "
-                                                f"fuse_hops={args.fuse_hops}")
+    kernel = "k_propagate_fused" if hop_launches == 1 else "k_propagate"
+    traffic = traffic_from_profile(kernel, "icosphere7", f"select={args.select} k={args.k} hops={args.hops} "
+                                                        f"fuse_hops={args.fuse_hops}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_propagate_fused" if hop_launches == 1 and args.hops > 1 else "k_propagate", "avg_launch_us": round(avg_launch_s * 1e6, 3),
+                "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
                 "timed_launches": tot["propagate_launches"],
                 "propagate_share_of_wall": round(avg_launch_s * all_launches / wall, 4)}
