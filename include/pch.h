@@ -281,6 +281,34 @@ pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_b
 pch_status pch_voronoi(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist, int32_t* label,
                        void* hip_stream, const pch_batch_options* opts);
 
+/* Iso-contours of a distance field (an application of the exact per-vertex
+ * distances, like the geodesic Voronoi diagram the paper's future work names).
+ * The contour of level c is that of the linear interpolant of the vertex
+ * distances over each face (marching triangles): a face whose three values
+ * are not all on the same side of c (side: d >= c) holds one segment between
+ * the two crossing points of its edges; a face with a non-finite vertex
+ * value holds none.
+ *  faces      device int32 [nf][3] (the mesh's faces; half-edge j of face f
+ *             is j = 3 f + k, from vertex faces[f][k] to faces[f][(k+1) % 3])
+ *  dist       device double [nv], e.g. the output of pch_geodesic
+ *  levels     host double [n_levels], finite, 1 <= n_levels <= PCH_ISO_MAX_LEVELS
+ *  seg_he     device int32 [cap][2]: the half-edges of the two endpoints
+ *  seg_t      device double [cap][2]: each endpoint's fraction along its
+ *             half-edge from the start vertex, (c - d_a) / (d_b - d_a)
+ *  seg_level  device int32 [cap]: the level index of the segment
+ *  cap        segments the outputs hold (0: count only; outputs may be NULL)
+ *  n_segments host: the number of segments (also when they exceed cap)
+ * Segments come in no particular order; each (face, level) pair gives at most
+ * one, so cap = nf * n_levels always suffices. Returns after the work on
+ * hip_stream is done; allocates 16 bytes of device memory per call.
+ * Errors: PCH_EINVAL (bad sizes or levels, a face index outside [0, nv)),
+ * PCH_EOVERFLOW (more than cap segments: the first cap found are written and
+ * n_segments holds the count), PCH_ENOMEM, PCH_EDEVICE. */
+#define PCH_ISO_MAX_LEVELS 64
+pch_status pch_isolines(const int32_t* faces, int64_t nf, int64_t nv, const double* dist, const double* levels,
+                        int32_t n_levels, int32_t* seg_he, double* seg_t, int32_t* seg_level, int64_t cap,
+                        int64_t* n_segments, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned distance predictor for PCH_SELECT_LEARNED: an MLP 7 -> 64 -> 64 -> 1
  * (ReLU) on features [(v - c) / R, (s - c) / R, |v - s| / R] of vertex v,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpch.so")
-SOURCES = ["pch_gpu.hip", "pch_mlp.hip", "pch_mesh.cpp"]
+SOURCES = ["pch_gpu.hip", "pch_mlp.hip", "pch_iso.hip", "pch_mesh.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -333,6 +333,48 @@ def voronoi(mesh: Mesh, sources, stream=None, **opts):
 
 
 # ---------------------------------------------------------------------------
+# iso-contours
+# ---------------------------------------------------------------------------
+
+ISO_MAX_LEVELS = 64
+EXPORTS += ["pch_isolines"]
+
+
+def isolines(faces, dist, levels, cap=None, stream=None):
+    """Iso-contour segments of the distance field ``dist`` (device float64
+    [nv]) over the mesh ``faces`` (device int32 [nf, 3]) at ``levels``, on the
+    linear interpolant of each face. Returns device tensors (he [n, 2] int32,
+    t [n, 2] float64, level [n] int32): segment i runs from the point at
+    fraction t[i, 0] along half-edge he[i, 0] (half-edge j = 3 f + k of face f
+    starts at faces[f, k] and ends at faces[f, (k + 1) % 3]) to the point at
+    t[i, 1] along he[i, 1]; level[i] indexes ``levels``."""
+    import torch
+    L = lib()
+    if not getattr(L, "_iso_ready", False):
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.pch_isolines.argtypes = [P, i64, i64, P, P, i32, P, P, P, i64, ctypes.POINTER(i64), P]
+        L._iso_ready = True
+    if faces.dtype != torch.int32 or not faces.is_cuda or not faces.is_contiguous() or faces.dim() != 2 \
+            or faces.shape[1] != 3:
+        raise ValueError("faces must be a contiguous int32 CUDA tensor [nf, 3]")
+    if dist.dtype != torch.float64 or not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous float64 CUDA tensor")
+    lv = np.ascontiguousarray(np.atleast_1d(np.asarray(levels, dtype=np.float64)))
+    nf = int(faces.shape[0])
+    if cap is None:
+        cap = nf * lv.size
+    he = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+    t = torch.empty((max(cap, 1), 2), dtype=torch.float64, device="cuda")
+    lev = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    n = ctypes.c_int64()
+    _check(L.pch_isolines(faces.data_ptr(), nf, int(dist.numel()), dist.data_ptr(), lv.ctypes.data, int(lv.size),
+                          he.data_ptr(), t.data_ptr(), lev.data_ptr(), int(cap), ctypes.byref(n),
+                          _stream_handle(stream)))
+    k = int(n.value)
+    return he[:k], t[:k], lev[:k]
+
+
+# ---------------------------------------------------------------------------
 # learned distance predictor
 # ---------------------------------------------------------------------------
 

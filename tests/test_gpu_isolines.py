@@ -1,0 +1,112 @@
+"""GPU iso-contours (pch_isolines) against the oracle's marching triangles:
+the same segments, half-edges and crossing fractions bit for bit, on the small
+configuration and on sampled faces of the full-size icosphere field."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import isolines as I
+from paper_1305_1293_amd import meshgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1305_1293_amd import pch as P
+    P.lib()
+    return P
+
+
+def as_records(he, t, lev):
+    he, t, lev = he.cpu().numpy(), t.cpu().numpy(), lev.cpu().numpy()
+    out = np.zeros(lev.size, dtype=[("face", np.int64), ("level", np.int64), ("j0", np.int64), ("t0", np.float64),
+                                    ("j1", np.int64), ("t1", np.float64)])
+    out["face"], out["level"] = he[:, 0] // 3, lev
+    out["j0"], out["t0"], out["j1"], out["t1"] = he[:, 0], t[:, 0], he[:, 1], t[:, 1]
+    return np.sort(out, order=["face", "level"])
+
+
+def assert_same(got, ref):
+    assert got.size == ref.size
+    for k in ("face", "level", "j0", "j1"):
+        assert np.array_equal(got[k], ref[k]), k
+    for k in ("t0", "t1"):
+        assert np.array_equal(got[k].view(np.uint64), ref[k].view(np.uint64)), k
+
+
+def test_isolines_match_oracle_small(pch):
+    import torch
+    m = G.config_mesh(1)
+    say(f"isolines {m.name}")
+    dm = pch.Mesh.from_generated(m)
+    d = pch.geodesic(dm, [0], k=1024)
+    dn = d.cpu().numpy()
+    # levels inside the field, one equal to a vertex value (a crossing at the vertex)
+    levels = list(np.quantile(dn, np.linspace(0.05, 0.95, 7))) + [float(dn[1234])]
+    faces = torch.from_numpy(m.faces.astype(np.int32)).cuda()
+    got = as_records(*pch.isolines(faces, d, levels))
+    ref = I.isolines(m.faces, dn, levels)
+    say(f"  {ref.size} segments")
+    assert ref.size > 1000
+    assert_same(got, ref)
+    # unreachable vertices: their faces hold no segment
+    d2 = d.clone()
+    d2[:200] = float("inf")
+    assert_same(as_records(*pch.isolines(faces, d2, levels)), I.isolines(m.faces, d2.cpu().numpy(), levels))
+    # too small an output: the count is reported with PCH_EOVERFLOW
+    with pytest.raises(pch.PchError) as e:
+        pch.isolines(faces, d, levels, cap=10)
+    assert e.value.code == -5 and str(ref.size) in str(e.value)
+    dm.close()
+
+
+def test_isolines_full_size_sampled_faces(pch):
+    """The bumpy icosphere field in the timed configuration; the oracle runs on
+    a sample of 3000 faces and the GPU's segments of those faces must equal it."""
+    import torch
+    m = G.config_mesh(2)
+    say(f"isolines {m.name}")
+    dm = pch.Mesh.from_generated(m)
+    d = pch.geodesic(dm, [int(m.meta["source"])], k=12288, select_mode=1, hops=5)
+    dn = d.cpu().numpy()
+    levels = list(np.linspace(0.1, 0.95, 16) * dn.max())
+    faces = torch.from_numpy(m.faces.astype(np.int32)).cuda()
+    got = as_records(*pch.isolines(faces, d, levels))
+    idx = np.sort(np.random.default_rng(5).choice(m.nf, 3000, replace=False))
+    ref = I.isolines(m.faces[idx], dn, levels)
+    # back to the full mesh's face and half-edge numbers
+    ref["face"] = idx[ref["face"]]
+    for k in ("j0", "j1"):
+        ref[k] = 3 * idx[ref[k] // 3] + ref[k] % 3
+    ref = np.sort(ref, order=["face", "level"])
+    assert_same(got[np.isin(got["face"], idx)], ref)
+    # every (face, level) pair gives at most one segment
+    key = got["face"] * len(levels) + got["level"]
+    assert np.unique(key).size == key.size
+    say(f"  {got.size} segments, {ref.size} on the sampled faces")
+    dm.close()
+
+
+def test_isolines_argument_errors(pch):
+    import torch
+    m = G.config_mesh(1)
+    faces = torch.from_numpy(m.faces.astype(np.int32)).cuda()
+    d = torch.zeros(m.nv, dtype=torch.float64, device="cuda")
+    for bad in ([np.nan], list(range(65))):
+        with pytest.raises(pch.PchError) as e:
+            pch.isolines(faces, d, bad)
+        assert e.value.code == -1
+    f2 = faces.clone()
+    f2[5, 1] = m.nv  # an index outside [0, nv): found by the kernel's bounds check, nothing read
+    with pytest.raises(pch.PchError) as e:
+        pch.isolines(f2, d, [0.5])
+    assert e.value.code == -1
