@@ -315,9 +315,16 @@ bool child_filter(double c0, double c1, double cpx, double cpy, double sg, doubl
 // Propagate one window (pseudo-source (px, py) in the frame of half-edge e)
 // across face(e) against the state (g, AD, AX). Children are appended to kids,
 // events to dev and aev; nothing in the state is written.
+// retest (stronger filtering, the paper's first item of future work): before
+// it crosses the face, the window takes the two endpoint tests of the ICH
+// filter (Figure 4(b)) again with the current g. Along the window's edge
+// |I x| - |v0 x| never increases toward v1 and |I x| - |v1 x| never increases
+// toward v0, whatever the pseudo-source I, so a window that fails a test at
+// the endpoint where that difference is smallest is beaten on its whole
+// interval by a path through v0 or v1; it is counted with the ICH drops.
 void propagate(const OMesh& M, double b0, double b1, double px, double py, double sg, int32_t e, int32_t src,
-               const double* g, const double* AD, const double* AX, bool ch_on, bool ich_on, double eps_tiny,
-               std::vector<Ev>& dev, std::vector<AEv>& aev, std::vector<Cand>& kids, Cnt& C) {
+               const double* g, const double* AD, const double* AX, bool ch_on, bool ich_on, bool retest,
+               double eps_tiny, std::vector<Ev>& dev, std::vector<AEv>& aev, std::vector<Cand>& kids, Cnt& C) {
   const int32_t en = nxt(e), ep = prv(e);
   const double L = M.L[e], x2 = M.ax[e], y2 = M.ay[e];
   const double l02 = M.L[ep], l12 = M.L[en];
@@ -325,6 +332,17 @@ void propagate(const OMesh& M, double b0, double b1, double px, double py, doubl
   const int32_t tl = M.twin[ep], tr = M.twin[en];
   const double g0 = g[v0], g1 = g[v1], g2 = g[v2];
   const double tol = kTau * L;
+  if (retest) {
+    // at b1 against v0 (distance along the edge b1), at b0 against v1
+    double dx1 = b1 - px;
+    double f1 = sg + std::sqrt(dx1 * dx1 + py * py);
+    double dx0 = b0 - px;
+    double f0 = sg + std::sqrt(dx0 * dx0 + py * py);
+    if (f1 > (g0 + b1) * kFm || f0 > (g1 + (L - b0)) * kFm) {
+      C.ich++;
+      return;
+    }
+  }
 
   const double den = y2 - py;
   const double t = (-py) / den;
@@ -679,7 +697,7 @@ int run_ich(const OMesh& M, const int32_t* src, int32_t m, double eps_tiny, int3
     dev.clear();
     aev.clear();
     std::vector<Cand> kids;
-    propagate(M, w.b0, w.b1, px, py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, eps_tiny, dev,
+    propagate(M, w.b0, w.b1, px, py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, false, eps_tiny, dev,
               aev, kids, C);
     for (const AEv& a : aev) {
       if (a.D < AD[a.e] || (a.D == AD[a.e] && a.X < AX[a.e])) {
@@ -770,6 +788,7 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, int32_
                 int32_t filters, int32_t mode, double delta0, const double* cut_table, int64_t n_cut, double* dist,
                 int64_t* stats, int64_t* rlog, int64_t max_log, int64_t* n_rounds, int64_t* vupd) {
   const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
+  const bool retest = (filters & 8) != 0;
   const int64_t nh = 3 * M.nf;
   std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
   std::vector<RWin> pool, nextp;
@@ -837,8 +856,8 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, int32_
         continue;
       }
       nsel++;
-      propagate(M, w.b0, w.b1, w.px, w.py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, eps_tiny,
-                dev, aev, kids, C);
+      propagate(M, w.b0, w.b1, w.px, w.py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, retest,
+                eps_tiny, dev, aev, kids, C);
     }
     // Further hops of the same round: children that pass the round's
     // selection test propagate at once, against the same snapshot, up to
@@ -852,7 +871,7 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, int32_
       if (hop_in.empty()) break;
       for (const Cand& c : hop_in) {
         nsel++;
-        propagate(M, c.b0, c.b1, c.px, c.py, c.sg, c.e, c.src, g.data(), AD.data(), AX.data(), ch_on, ich_on,
+        propagate(M, c.b0, c.b1, c.px, c.py, c.sg, c.e, c.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, retest,
                   eps_tiny, dev, aev, kids, C);
       }
     }

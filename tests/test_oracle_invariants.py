@@ -136,6 +136,26 @@ def test_filters_and_full_fan_do_not_change_distances(oracle, c1):
             assert st["created"] >= st0["created"]
 
 
+def test_propagation_retest_keeps_distances(oracle):
+    """Stronger filtering (filters bit 3): windows take the ICH endpoint tests
+    again when they propagate. Distances stay those of ICH on closed-form and
+    bumpy meshes in both selection rules, and the records change (the option
+    does act)."""
+    cases = [(G.config_mesh(1), 0, 1024, {}), (G.bumpy_icosphere(5, seed=3), 5, 4096, dict(mode=1, hops=4)),
+             (G.lshape(6), 5, 64, {}), (G.cube(6), 0, 64, dict(hops=3)), (G.cone_fan(7, 6), 5, 32, {})]
+    changed = 0
+    for m, s, k, kw in cases:
+        ref, _ = oracle.ich(m, [s])
+        hbar = float(oracle.lengths(m).mean())
+        if kw.get("mode") == 1:
+            kw = dict(kw, delta0=2 * hbar)
+        d3, _, log3 = oracle.replica(m, [s], k, filters=3, **kw)
+        d11, _, log11 = oracle.replica(m, [s], k, filters=11, **kw)
+        assert np.max(np.abs(d11 - ref) / np.maximum(ref, hbar)) <= 1e-9, m.name
+        changed += int(log3.shape != log11.shape or not np.array_equal(log3, log11))
+    assert changed >= 1
+
+
 def test_window_counts_close_to_ich(oracle, c1):
     """Soft check of Section 6: PCH creates only a little more windows than ICH
     when k is small relative to the wavefront."""
