@@ -108,7 +108,11 @@ enum {
 typedef struct {
   int32_t select_mode;        /* PCH_SELECT_* (default PCH_SELECT_KTH) */
   int32_t filters;            /* bit 0 CH one-angle-one-split, bit 1 ICH window
-                                 filter, bit 2 full fans (default 3) */
+                                 filter, bit 2 full fans, bit 3 stronger
+                                 filtering: a window takes the two endpoint
+                                 tests of the ICH filter again with the
+                                 round-start distances when it propagates
+                                 (its drops count as ICH drops) (default 3) */
   int64_t k;                  /* windows per round for PCH_SELECT_KTH (default 16384) */
   double eps_tiny;            /* drop children narrower than eps_tiny * edge
                                  length (Section 5.3 uses 1e-6; default 0) */

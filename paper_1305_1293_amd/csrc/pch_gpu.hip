@@ -201,7 +201,7 @@ struct RoundArgs {
   int64_t k;
   int32_t mode;
   double eps;
-  int32_t ch_on, ich_on, full_fan;
+  int32_t ch_on, ich_on, full_fan, retest;
   const double* table;  // device cutoff table or null
   int64_t n_table;
   const u32* cdf;       // learned cutoff: cumulative counts of predicted distances
@@ -1232,150 +1232,167 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
     const int v0 = h.v0, v1 = h.v1, v2 = h.v2;
     const double g0 = from_bits(lda(&g[v0])), g1 = from_bits(lda(&g[v1])), g2 = from_bits(lda(&g[v2]));
     const double tol = kTau * L;
-    const double den = y2 - py;
-    const double t = (-py) / den;
-    const double X = px + (x2 - px) * t;
-    if (!isfinite(X)) acc.n_nonfin++;
-    const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
-    if (b0 <= tol) {
-      const double d = sg + sqrt(px * px + py * py);
-      if (d < g0 * kEv) {
-        e0 = true;
-        ev0 = v0;
-        ed0 = d;
-        eq0 = (h.pflags & 1) ? (e << 2) : -1;
-      }
+    // stronger filtering (filters bit 3): the window takes the two endpoint
+    // tests of the ICH filter again, against the round-start distances, which
+    // may have dropped since it was made; both hold for any window on an edge
+    // (along the edge, |I x| - |v0 x| never increases toward v1 and
+    // |I x| - |v1 x| never increases toward v0), so a window that fails one is
+    // beaten on its whole interval
+    bool drop = false;
+    if (a.retest) {
+      const double dx1 = b1 - px;
+      const double f1 = sg + sqrt(dx1 * dx1 + py * py);
+      const double dx0 = b0 - px;
+      const double f0 = sg + sqrt(dx0 * dx0 + py * py);
+      drop = f1 > (g0 + b1) * kFm || f0 > (g1 + (L - b0)) * kFm;
     }
-    if (b1 >= L - tol) {
-      const double dx = px - L;
-      const double d = sg + sqrt(dx * dx + py * py);
-      if (d < g1 * kEv) {
-        e1 = true;
-        ev1 = v1;
-        ed1 = d;
-        eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
+    if (drop) acc.n_ich++;
+    if (!drop) {
+      const double den = y2 - py;
+      const double t = (-py) / den;
+      const double X = px + (x2 - px) * t;
+      if (!isfinite(X)) acc.n_nonfin++;
+      const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
+      if (b0 <= tol) {
+        const double d = sg + sqrt(px * px + py * py);
+        if (d < g0 * kEv) {
+          e0 = true;
+          ev0 = v0;
+          ed0 = d;
+          eq0 = (h.pflags & 1) ? (e << 2) : -1;
+        }
       }
-    }
-    bool doL = false, doR = false;
-    if (occ) {
-      const double dx = x2 - px, dy = y2 - py;
-      const double d2 = sg + sqrt(dx * dx + dy * dy);
-      if (d2 < g2 * kEv) {
-        e2 = true;
-        ev2 = v2;
-        ed2 = d2;
-        eq2 = (h.pflags & 4) ? ((e << 2) | 2) : -1;
+      if (b1 >= L - tol) {
+        const double dx = px - L;
+        const double d = sg + sqrt(dx * dx + py * py);
+        if (d < g1 * kEv) {
+          e1 = true;
+          ev1 = v1;
+          ed1 = d;
+          eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
+        }
       }
-      if (!a.ch_on) {
-        doL = doR = true;
-      } else {
-        const double Ds = from_bits(ad_bits);
-        const double Xs = from_ordkey(ax_bits);
-        if (d2 < Ds) {
-          has_aev = true;
-          aD = d2;
-          aX = X;
+      bool doL = false, doR = false;
+      if (occ) {
+        const double dx = x2 - px, dy = y2 - py;
+        const double d2 = sg + sqrt(dx * dx + dy * dy);
+        if (d2 < g2 * kEv) {
+          e2 = true;
+          ev2 = v2;
+          ed2 = d2;
+          eq2 = (h.pflags & 4) ? ((e << 2) | 2) : -1;
+        }
+        if (!a.ch_on) {
           doL = doR = true;
-        } else if (d2 <= Ds * kFm) {
-          doL = doR = true;  // a near-tie keeps both children
-        } else if (X < Xs - tol) {
-          doL = true;
-        } else if (X > Xs + tol) {
-          doR = true;
         } else {
-          doL = doR = true;
+          const double Ds = from_bits(ad_bits);
+          const double Xs = from_ordkey(ax_bits);
+          if (d2 < Ds) {
+            has_aev = true;
+            aD = d2;
+            aX = X;
+            doL = doR = true;
+          } else if (d2 <= Ds * kFm) {
+            doL = doR = true;  // a near-tie keeps both children
+          } else if (X < Xs - tol) {
+            doL = true;
+          } else if (X > Xs + tol) {
+            doR = true;
+          } else {
+            doL = doR = true;
+          }
+        }
+      } else if (X > b1) {
+        doL = true;
+      } else {
+        doR = true;
+      }
+      if (doL) {
+        if (h.tl < 0) {
+          acc.n_notwin++;
+        } else {
+          double s0, s1;
+          if (b0 == 0.0) {
+            s0 = 0.0;
+          } else {
+            const double dn0 = x2 * py + y2 * (b0 - px);
+            s0 = (py * b0) / dn0;
+          }
+          if (occ) {
+            s1 = 1.0;
+          } else {
+            const double dn1 = x2 * py + y2 * (b1 - px);
+            s1 = (py * b1) / dn1;
+          }
+          double c0 = s0 * l02, c1 = s1 * l02;
+          if (c0 < 0.0) c0 = 0.0;
+          if (c1 > l02) c1 = l02;
+          const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
+          const double cpx = ux * px + uy * py;
+          double cpy = ux * py - uy * px;
+          if (cpy > 0.0) cpy = 0.0;
+          const double rx = ux * c0 - L, ry = uy * c0;
+          const double rdist = sqrt(rx * rx + ry * ry);
+          const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
+          if (r == 1) {
+            acc.n_tiny++;
+          } else if (r == 2) {
+            acc.n_ich++;
+          } else {
+            cl = true;
+            lb0 = c0;
+            lb1 = c1;
+            lpx = cpx;
+            lpy = cpy;
+            lkey = window_key(c0, c1, cpx, cpy, sg);
+            le = h.tl;
+          }
         }
       }
-    } else if (X > b1) {
-      doL = true;
-    } else {
-      doR = true;
-    }
-    if (doL) {
-      if (h.tl < 0) {
-        acc.n_notwin++;
-      } else {
-        double s0, s1;
-        if (b0 == 0.0) {
-          s0 = 0.0;
+      if (doR) {
+        if (h.tr < 0) {
+          acc.n_notwin++;
         } else {
-          const double dn0 = x2 * py + y2 * (b0 - px);
-          s0 = (py * b0) / dn0;
-        }
-        if (occ) {
-          s1 = 1.0;
-        } else {
-          const double dn1 = x2 * py + y2 * (b1 - px);
-          s1 = (py * b1) / dn1;
-        }
-        double c0 = s0 * l02, c1 = s1 * l02;
-        if (c0 < 0.0) c0 = 0.0;
-        if (c1 > l02) c1 = l02;
-        const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
-        const double cpx = ux * px + uy * py;
-        double cpy = ux * py - uy * px;
-        if (cpy > 0.0) cpy = 0.0;
-        const double rx = ux * c0 - L, ry = uy * c0;
-        const double rdist = sqrt(rx * rx + ry * ry);
-        const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
-        if (r == 1) {
-          acc.n_tiny++;
-        } else if (r == 2) {
-          acc.n_ich++;
-        } else {
-          cl = true;
-          lb0 = c0;
-          lb1 = c1;
-          lpx = cpx;
-          lpy = cpy;
-          lkey = window_key(c0, c1, cpx, cpy, sg);
-          le = h.tl;
-        }
-      }
-    }
-    if (doR) {
-      if (h.tr < 0) {
-        acc.n_notwin++;
-      } else {
-        const double ex = L - x2;
-        double r0, r1;
-        if (occ) {
-          r0 = 0.0;
-        } else {
-          const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
-          const double dn0 = y2 * (b0 - px) - ex * py;
-          r0 = nm0 / dn0;
-        }
-        if (b1 == L) {
-          r1 = 1.0;
-        } else {
-          const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
-          const double dn1 = y2 * (b1 - px) - ex * py;
-          r1 = nm1 / dn1;
-        }
-        double c0 = r0 * l12, c1 = r1 * l12;
-        if (c0 < 0.0) c0 = 0.0;
-        if (c1 > l12) c1 = l12;
-        const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
-        const double qx = px - x2, qy = py - y2;
-        const double cpx = ux * qx + uy * qy;
-        double cpy = ux * qy - uy * qx;
-        if (cpy > 0.0) cpy = 0.0;
-        const double rx = x2 + ux * c1, ry = y2 + uy * c1;
-        const double rdist = sqrt(rx * rx + ry * ry);
-        const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
-        if (r == 1) {
-          acc.n_tiny++;
-        } else if (r == 2) {
-          acc.n_ich++;
-        } else {
-          cr = true;
-          rb0 = c0;
-          rb1 = c1;
-          rpx = cpx;
-          rpy = cpy;
-          rkey = window_key(c0, c1, cpx, cpy, sg);
-          re = h.tr;
+          const double ex = L - x2;
+          double r0, r1;
+          if (occ) {
+            r0 = 0.0;
+          } else {
+            const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
+            const double dn0 = y2 * (b0 - px) - ex * py;
+            r0 = nm0 / dn0;
+          }
+          if (b1 == L) {
+            r1 = 1.0;
+          } else {
+            const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
+            const double dn1 = y2 * (b1 - px) - ex * py;
+            r1 = nm1 / dn1;
+          }
+          double c0 = r0 * l12, c1 = r1 * l12;
+          if (c0 < 0.0) c0 = 0.0;
+          if (c1 > l12) c1 = l12;
+          const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
+          const double qx = px - x2, qy = py - y2;
+          const double cpx = ux * qx + uy * qy;
+          double cpy = ux * qy - uy * qx;
+          if (cpy > 0.0) cpy = 0.0;
+          const double rx = x2 + ux * c1, ry = y2 + uy * c1;
+          const double rdist = sqrt(rx * rx + ry * ry);
+          const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
+          if (r == 1) {
+            acc.n_tiny++;
+          } else if (r == 2) {
+            acc.n_ich++;
+          } else {
+            cr = true;
+            rb0 = c0;
+            rb1 = c1;
+            rpx = cpx;
+            rpy = cpy;
+            rkey = window_key(c0, c1, cpx, cpy, sg);
+            re = h.tr;
+          }
         }
       }
     }
@@ -1904,7 +1921,7 @@ struct BatchDev {
   int64_t cap, ecap, acap, max_nv, max_nh;
   int64_t k;
   double eps;
-  int32_t ch_on, ich_on, full_fan;
+  int32_t ch_on, ich_on, full_fan, retest;
   int32_t hops;      // propagation hops per round
   int32_t nslot;     // window buffers per team: pool 0, pool 1, selection (+ 2 hop queues)
   int32_t gang_max;  // workgroups per field (1: no helpers)
@@ -2038,6 +2055,7 @@ __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, Round
   a.ch_on = B.ch_on;
   a.ich_on = B.ich_on;
   a.full_fan = B.full_fan;
+  a.retest = B.retest;
   a.table = nullptr;
   a.n_table = 0;
   a.cdf = nullptr;
@@ -2708,6 +2726,7 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.ch_on = (o.filters & 1) != 0;
   a.ich_on = (o.filters & 2) != 0;
   a.full_fan = (o.filters & 4) != 0;
+  a.retest = (o.filters & 8) != 0;
   a.table = (o.select_mode == PCH_SELECT_TABLE) ? M->dtable : nullptr;
   a.n_table = (o.select_mode == PCH_SELECT_TABLE) ? o.n_cutoff : 0;
   a.cdf = M->dcdf;
@@ -3172,6 +3191,7 @@ pch_status alloc_slots(pch_batch_s* b) {
   B.ch_on = (b->o.filters & 1) != 0;
   B.ich_on = (b->o.filters & 2) != 0;
   B.full_fan = (b->o.filters & 4) != 0;
+  B.retest = (b->o.filters & 8) != 0;
   return PCH_OK;
 }
 

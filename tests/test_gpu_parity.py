@@ -207,6 +207,28 @@ def test_fused_hops_equal_per_hop_launches(pch, hops):
             assert np.max(np.abs(d0 - d1) / np.maximum(d0, hbar)) <= 1e-9
 
 
+@pytest.mark.parametrize("case", [("sinusoid64", 0, 1024, 1), ("sphere5", 5, 4096, 4), ("grid64", 0, 1024, 5),
+                                  ("sphere5", 5, 4096, 8)])
+def test_propagation_retest_matches_replica(pch, oracle, case):
+    """Stronger filtering (filters bit 3) on the GPU: the per-round records and
+    distance bits equal the replica with the same option, the distances ICH's."""
+    name, s, k, hops = case
+    m = {"sinusoid64": lambda: G.config_mesh(1), "sphere5": lambda: G.bumpy_icosphere(5, seed=3),
+         "grid64": lambda: G.bump_grid(64, seed=12)}[name]()
+    hbar = mean_edge(oracle, m)
+    kw = dict(mode=1, delta0=2 * hbar) if name != "sinusoid64" else {}
+    gkw = dict(select_mode=1, delta0=2 * hbar) if name != "sinusoid64" else {}
+    say(f"retest {name} source {s} k {k} hops {hops}")
+    dr, _, log_r = oracle.replica(m, [s], k, filters=11, hops=hops, **kw)
+    d, st, log = gpu_field(pch, m, [s], k=k, collect_stats=1, filters=11, hops=hops, **gkw)
+    assert log.shape == log_r.shape
+    bad = np.nonzero(np.any(log != log_r, axis=1))[0]
+    assert bad.size == 0, f"first differing round {bad[0]}: gpu {log[bad[0]].tolist()} replica {log_r[bad[0]].tolist()}"
+    assert np.array_equal(d.view(np.uint64), dr.view(np.uint64))
+    ref, _ = oracle.ich(m, [s])
+    assert_close(d, ref, hbar, what=name)
+
+
 def test_grazing_boundary_regression(pch, oracle):
     m = G.bump_grid(96, seed=23)
     say("bump grid 96 seed 23 (grazing convex boundary)")
