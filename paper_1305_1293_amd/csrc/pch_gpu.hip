@@ -2964,7 +2964,9 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   double prop_ms = 0.0;
   int64_t prop_n = 0;
   for (;;) {
-    pch_status s = ensure_work(M, cap, o.hops > 1);
+    // the hop queues in device memory serve only one launch per hop (fused
+    // hops keep their windows in LDS)
+    pch_status s = ensure_work(M, cap, o.hops > 1 && !(o.fuse_hops != 0 && o.hops <= kFuseHops));
     if (s != PCH_OK) return s;
     if (o.organize && M->sorted_cap < M->cap) {
       free_pool(M->sorted);
