@@ -110,3 +110,22 @@ def test_isolines_argument_errors(pch):
     with pytest.raises(pch.PchError) as e:
         pch.isolines(f2, d, [0.5])
     assert e.value.code == -1
+
+
+def test_isolines_edge_cases(pch):
+    """No faces; the largest number of levels; a constant field (no face
+    changes side); levels at the field's extremes."""
+    import torch
+    m = G.config_mesh(1)
+    faces = torch.from_numpy(m.faces.astype(np.int32)).cuda()
+    dm = pch.Mesh.from_generated(m)
+    d = pch.geodesic(dm, [0], k=1024)
+    he, t, lev = pch.isolines(torch.empty((0, 3), dtype=torch.int32, device="cuda"), d, [0.5])
+    assert he.shape[0] == 0 and t.shape[0] == 0 and lev.shape[0] == 0
+    dn = d.cpu().numpy()
+    levels = list(np.linspace(0.0, dn.max(), pch.ISO_MAX_LEVELS))
+    got = as_records(*pch.isolines(faces, d, levels))
+    assert_same(got, I.isolines(m.faces, dn, levels))
+    const = torch.full((m.nv,), 0.25, dtype=torch.float64, device="cuda")
+    assert pch.isolines(faces, const, [0.1, 0.25, 0.4])[0].shape[0] == 0
+    dm.close()
