@@ -1609,7 +1609,7 @@ constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
 // deeper list is empty, from at most kBlock windows, so it never holds more
 // than 2 * kBlock. Every window propagates at the hop it would reach with one
 // launch per hop, against the same round-start values, so the round's
-// windows, events and counts are the same; three launches and their ramps
+// windows, events and counts are the same; hops - 1 launches and their ramps
 // are saved per round.
 __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) {
   __shared__ double2 l_bb[kFuseHops - 1][kFuseCap], l_pp[kFuseHops - 1][kFuseCap], l_sk[kFuseHops - 1][kFuseCap];
