@@ -79,6 +79,16 @@ def _timed(torch, fn):
     return time.perf_counter() - t, r
 
 
+def batch_roofline(windows_per_s: float) -> dict:
+    """Lower bound of a batched launch's algorithmic HBM rate: per processed
+    window the propagation's reads and one window written (events, fans and
+    the pool scans are not counted)."""
+    per_window = PROP_READ_BYTES + WINDOW_BYTES
+    achieved = windows_per_s * per_window / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_window": per_window, "lower_bound": True}
+
+
 def measure_batched(pch, G, torch):
     """512 fields in one persistent launch against plain PCH field by field."""
     gens = G.batch_meshes(3)
@@ -114,7 +124,8 @@ def measure_batched(pch, G, torch):
             "plain_ms_est": round(plain_ms, 1),
             "plain": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on its first "
                      "source; 2 more sources per mesh timed and scaled to 32",
-            "speedup_vs_plain": round(plain_ms / batch_ms, 3), "max_rel_diff_vs_plain": worst}
+            "speedup_vs_plain": round(plain_ms / batch_ms, 3), "max_rel_diff_vs_plain": worst,
+            "roofline": batch_roofline(windows / dt)}
 
 
 def measure_concurrent(args, pch, m, mesh, srcs, keep, torch):
@@ -133,7 +144,7 @@ def measure_concurrent(args, pch, m, mesh, srcs, keep, torch):
     b.close()
     return {"fields": int(fs.size), "ms": round(1000.0 * dt, 2), "ms_per_field": round(1000.0 * dt / fs.size, 4),
             "windows_per_s": round(windows / dt, 1), "options": opts, "reruns": int(st["reruns"]),
-            "equal_to_single_field_runs": bool(same)}
+            "equal_to_single_field_runs": bool(same), "roofline": batch_roofline(windows / dt)}
 
 
 def measure_learned(args, pch, G, torch):
