@@ -123,7 +123,9 @@ pch_status pch_isolines(const int32_t* faces, int64_t nf, int64_t nv, const doub
                         int64_t* n_segments, void* hip_stream) {
   if (!n_segments) return iso_err(PCH_EINVAL, "n_segments is NULL");
   *n_segments = 0;
-  if (nf < 0 || nv < 1 || nf > (int64_t)1 << 30) return iso_err(PCH_EINVAL, "nf must be in [0, 2^30], nv >= 1");
+  // half-edge indices 3 f + k are int32
+  if (nf < 0 || nv < 1 || nf > (((int64_t)1 << 31) - 1) / 3)
+    return iso_err(PCH_EINVAL, "nf must be in [0, (2^31 - 1) / 3], nv >= 1");
   if (n_levels < 1 || n_levels > PCH_ISO_MAX_LEVELS)
     return iso_err(PCH_EINVAL, "n_levels must be in [1, " + std::to_string(PCH_ISO_MAX_LEVELS) + "]");
   if (!levels || (nf > 0 && (!faces || !dist))) return iso_err(PCH_EINVAL, "NULL input");
