@@ -102,6 +102,29 @@ def test_batch_gangs_equal_single_fields(pch, setup, gang, tpc, threads):
     b.close()
 
 
+@pytest.mark.parametrize("gang", [1, 8])
+def test_batch_stronger_filtering_equals_single_fields(pch, setup, gang):
+    """filters bit 3 (windows re-take the ICH endpoint tests when they
+    propagate) in the batched launch: every field equals its single-field run
+    with the same option bit for bit."""
+    import torch
+    gens, meshes, fm, fs = setup
+    k = 256
+    b = pch.Batch(meshes, fm, fs, k=k, teams_per_cu=1, hops=4, gang=gang, filters=11)
+    say(f"batch of {b.n_fields} fields, filters 11, gang {gang}")
+    out, st = b.run()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert st["reruns"] == 0
+    for f in range(b.n_fields):
+        d = pch.geodesic(meshes[fm[f]], [int(fs[f])], k=k, select_mode=1, hops=4, filters=11)
+        torch.cuda.synchronize()
+        ref = d.cpu().numpy()
+        gf = got[b.offsets[f]:b.offsets[f + 1]]
+        assert np.array_equal(gf.view(np.uint64), ref.view(np.uint64)), f"field {f}"
+    b.close()
+
+
 def test_batch_gangs_many_fields(pch):
     """More fields than workgroups (every XCD runs 32 or more teams): the last
     fields are shared by the teams that ran out of work."""
