@@ -1,8 +1,9 @@
 """Test infrastructure only: ctypes wrapper of the CPU oracle library.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
-this module. ``build()`` compiles ``pch_oracle.cpp`` with g++ (FP contraction
-off, no fast-math) into ``liboracle.so`` next to this file.
+this module. ``build()`` compiles ``mesh.cpp``, ``ich.cpp`` and
+``pch_oracle.cpp`` with g++ (FP contraction off, no fast-math) into
+``liboracle.so`` next to this file.
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "pch_oracle.cpp")
+SRCS = [os.path.join(HERE, f) for f in ("mesh.cpp", "ich.cpp", "pch_oracle.cpp")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 # per-round log columns written by orc_replica
@@ -29,7 +30,7 @@ _lib = None
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
-               "-o", LIB + ".tmp", SRC]
+               "-o", LIB + ".tmp", *SRCS]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
     return LIB

@@ -1,28 +1,29 @@
-// Test infrastructure only: a plain, slow CPU reference for exact geodesic
+// Test infrastructure only: plain, slow CPU references for exact geodesic
 // distance on triangle meshes (Ying, Xin, He: "Parallel Chen-Han (PCH)
 // Algorithm for Discrete Geodesics"). Only the test suite, the smoke check and
-// the benchmark's CPU-baseline leg load this library. The GPU library shares
-// no code with it.
+// the benchmark's CPU-baseline leg load this library (liboracle.so, built from
+// this file, ich.cpp and mesh.cpp). The GPU library shares no code with it.
 //
-// Three computations live here:
-//   * ich      - sequential Chen-Han with Xin-Wang's priority queue and window
-//                filter (ICH, Section 2 and the "Comparison to the ICH
-//                algorithm" paragraph of Section 6). Windows are kept in the
-//                paper's 6-tuple form (d, A, B, d0, d1, e) of Section 3
-//                (Figure 2); the pseudo-source is rebuilt from d0, d1 each time
-//                a window is propagated. Updates of geod_dist and angle_split
-//                are applied immediately.
-//   * replica  - the round-based PCH method (Algorithm 1) run sequentially:
-//                select all windows whose key is at or below a cutoff,
-//                propagate them against the round-start state (delayed update,
-//                Remark 3), then apply the distance and angle events by
+// The library holds:
+//   * ich      (ich.cpp) - sequential Chen-Han with Xin and Wang's priority
+//                queue and window filter, windows in the paper's (d, A, B, d0,
+//                d1, e) form, immediate updates: the distance oracle;
+//   * replica  (this file) - the round-based PCH method (Algorithm 1) run
+//                sequentially: select all windows whose key is at or below a
+//                cutoff, propagate them against the round-start state (delayed
+//                update, Remark 3), then apply the distance and angle events by
 //                minimum (Algorithm 4). Windows keep their pseudo-source as
-//                (px, py) in the edge frame. It logs per-round integer counts.
-//   * dijkstra - shortest paths along mesh edges (an upper bound).
+//                (px, py) in the edge frame. It logs per-round integer counts,
+//                the record the GPU's rounds are compared with;
+//   * mesh tables and Dijkstra along edges (mesh.cpp), used by both.
+// The two window codes share no function: each has its own propagation, fan,
+// filter and key.
 //
 // Floating point: built with -ffp-contract=off and no fast-math. sqrt and
-// division are IEEE correctly rounded; atan2, sin and cos used per window are
-// this file's own (stated below), so results do not depend on the libm build.
+// division are IEEE correctly rounded. The replica's atan2, sin and cos are
+// this file's own series (stated below), evaluated in the same order as the
+// GPU library's, so that the two take every floating-point decision alike and
+// their per-round records can be compared exactly.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -32,10 +33,13 @@
 #include <unordered_map>
 #include <vector>
 
+#include "mesh.h"
+
+using namespace orc;
+
 namespace {
 
 const double kPi = 3.14159265358979323846;
-const double kTwoPi = 2.0 * 3.14159265358979323846;
 const double kHalfPi = 0.5 * 3.14159265358979323846;
 const double kQuarterPi = 0.25 * 3.14159265358979323846;
 // Relative tolerance for "A = v0", "B = v1" and "w occupies v2" (Algorithm 2).
@@ -43,22 +47,11 @@ const double kTau = 1e-12;
 // A distance event is raised only when it lowers geod_dist by more than a
 // relative 1e-12 (d < g * kEv), so rounding noise cannot re-trigger a vertex.
 const double kEv = 1.0 - 1e-12;
-// Interior vertices with total angle above 2 pi + kSaddle are saddles.
-const double kSaddle = 1e-10;
 // Filters drop a window only when the dominating path is shorter by more than
 // a relative 1e-12: near-ties are left to rounding otherwise, and a window
 // grazing a nearly straight convex boundary vertex (the only one carrying rays
 // past it) can lose a tie it wins in exact arithmetic.
 const double kFm = 1.0 + 1e-12;
-
-thread_local std::string g_err;
-
-int fail(int code, const std::string& m) {
-  g_err = m;
-  return code;
-}
-
-enum { OK = 0, EINVAL_ = -1, EMESH = -2 };
 
 // --------------------------------------------------------------------------
 // own elementary functions (only + - * / sqrt, fixed order)
@@ -126,128 +119,7 @@ void orc_sincos(double t, double* s, double* c) {
 }
 
 // --------------------------------------------------------------------------
-// mesh (Section 4.1: he[3|F|], face of j = j/3, next = 3(j/3) + (j+1)%3)
-// --------------------------------------------------------------------------
-
-inline int32_t nxt(int32_t j) { return 3 * (j / 3) + (j + 1) % 3; }
-inline int32_t prv(int32_t j) { return 3 * (j / 3) + (j + 2) % 3; }
-
-struct OMesh {
-  int64_t nv = 0, nf = 0;
-  std::vector<int32_t> F;      // start vertex of half-edge j
-  std::vector<double> L;       // length of half-edge j
-  std::vector<int32_t> twin;   // opposite half-edge or -1
-  std::vector<double> ax, ay;  // opposite vertex in j's frame (start at 0, end at (L,0))
-  std::vector<double> alpha;   // corner angle at the start of j inside face(j)
-  std::vector<double> phi;     // angular position of j around its start vertex
-  std::vector<double> theta;   // total angle per vertex
-  std::vector<uint8_t> bnd, pseudo;
-  std::vector<int32_t> coff, corner;  // CCW list of outgoing half-edges per vertex
-};
-
-// Kahan's stable form of Heron's formula: 16 area^2 with sides a >= b >= c.
-double kahan16(double p, double q, double r) {
-  double a = p, b = q, c = r;
-  if (a < b) std::swap(a, b);
-  if (b < c) std::swap(b, c);
-  if (a < b) std::swap(a, b);
-  return (a + (b + c)) * (c - (a - b)) * (c + (a - b)) * (a + (b - c));
-}
-
-int build_mesh(const int32_t* faces, int64_t nf, int64_t nv, const double* len, OMesh& M) {
-  if (nf <= 0 || nv <= 0) return fail(EINVAL_, "empty mesh");
-  if (3 * nf > (int64_t)INT32_MAX) return fail(EINVAL_, "too many faces");
-  M.nv = nv;
-  M.nf = nf;
-  const int64_t nh = 3 * nf;
-  M.F.assign(faces, faces + nh);
-  M.L.assign(len, len + nh);
-  for (int64_t f = 0; f < nf; ++f) {
-    int32_t a = faces[3 * f], b = faces[3 * f + 1], c = faces[3 * f + 2];
-    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) return fail(EINVAL_, "face index out of range");
-    if (a == b || b == c || a == c) return fail(EMESH, "face with a repeated vertex");
-  }
-  for (int64_t j = 0; j < nh; ++j)
-    if (!(M.L[j] > 0.0) || !std::isfinite(M.L[j])) return fail(EINVAL_, "edge length not positive and finite");
-  // twins by (min, max) vertex pair
-  M.twin.assign(nh, -1);
-  std::unordered_map<uint64_t, int32_t> first;
-  first.reserve(nh * 2);
-  std::vector<uint8_t> paired(nh, 0);
-  for (int64_t j = 0; j < nh; ++j) {
-    uint32_t a = (uint32_t)M.F[j], b = (uint32_t)M.F[nxt((int32_t)j)];
-    uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
-    auto it = first.find(key);
-    if (it == first.end()) {
-      first.emplace(key, (int32_t)j);
-    } else {
-      int32_t o = it->second;
-      if (o < 0) return fail(EMESH, "non-manifold edge (more than two faces)");
-      if (M.F[o] == M.F[j]) return fail(EMESH, "inconsistent face orientation");
-      M.twin[j] = o;
-      M.twin[o] = (int32_t)j;
-      it->second = -1;
-    }
-  }
-  for (int64_t j = 0; j < nh; ++j) {
-    int32_t t = M.twin[j];
-    if (t >= 0 && std::fabs(M.L[j] - M.L[t]) > 1e-9 * M.L[j]) return fail(EINVAL_, "twin half-edges differ in length");
-  }
-  // apex coordinates and corner angles
-  M.ax.resize(nh);
-  M.ay.resize(nh);
-  M.alpha.resize(nh);
-  for (int64_t j = 0; j < nh; ++j) {
-    double Lj = M.L[j], lp = M.L[prv((int32_t)j)], ln = M.L[nxt((int32_t)j)];
-    double P = kahan16(Lj, lp, ln);
-    if (!(P > 0.0)) return fail(EMESH, "zero-area face (triangle inequality not strict)");
-    M.ax[j] = ((Lj * Lj + lp * lp) - ln * ln) / (2.0 * Lj);
-    M.ay[j] = std::sqrt(P) / (2.0 * Lj);
-    M.alpha[j] = std::atan2(M.ay[j], M.ax[j]);
-  }
-  // CCW order of outgoing half-edges around every vertex
-  std::vector<int32_t> cnt(nv, 0), bstart(nv, -1), mn(nv, INT32_MAX);
-  for (int64_t j = 0; j < nh; ++j) {
-    int32_t v = M.F[j];
-    cnt[v]++;
-    if (j < mn[v]) mn[v] = (int32_t)j;
-    if (M.twin[j] < 0) {
-      if (bstart[v] >= 0) return fail(EMESH, "non-manifold vertex (two boundary fans)");
-      bstart[v] = (int32_t)j;
-    }
-  }
-  M.coff.assign(nv + 1, 0);
-  for (int64_t v = 0; v < nv; ++v) M.coff[v + 1] = M.coff[v] + cnt[v];
-  M.corner.assign(nh, -1);
-  M.phi.assign(nh, 0.0);
-  M.theta.assign(nv, 0.0);
-  M.bnd.assign(nv, 0);
-  M.pseudo.assign(nv, 0);
-  for (int64_t v = 0; v < nv; ++v) {
-    if (cnt[v] == 0) continue;
-    int32_t h0 = bstart[v] >= 0 ? bstart[v] : mn[v];
-    M.bnd[v] = bstart[v] >= 0;
-    int32_t h = h0, k = 0;
-    double acc = 0.0;
-    while (true) {
-      if (k >= cnt[v]) return fail(EMESH, "non-manifold vertex");
-      M.corner[M.coff[v] + k] = h;
-      M.phi[h] = acc;
-      acc = acc + M.alpha[h];
-      ++k;
-      int32_t t = M.twin[prv(h)];
-      if (t < 0 || t == h0) break;
-      h = t;
-    }
-    if (k != cnt[v]) return fail(EMESH, "non-manifold vertex (several fans)");
-    M.theta[v] = acc;
-    M.pseudo[v] = M.bnd[v] || (acc > kTwoPi + kSaddle);
-  }
-  return OK;
-}
-
-// --------------------------------------------------------------------------
-// window geometry shared by the two loops (Section 3, Algorithm 2)
+// window geometry of the replica (Section 3, Algorithm 2)
 // --------------------------------------------------------------------------
 
 struct Ev {
@@ -602,124 +474,6 @@ void fan(const OMesh& M, int32_t v, double d, double th, bool full, const double
 }
 
 // --------------------------------------------------------------------------
-// ICH: priority queue, immediate updates, paper's (d0, d1) window form
-// --------------------------------------------------------------------------
-
-struct IWin {
-  double key;
-  int64_t seq;
-  double sg, b0, b1, d0, d1;
-  int32_t e, src;
-};
-struct IWinCmp {
-  bool operator()(const IWin& a, const IWin& b) const {
-    if (a.key != b.key) return a.key > b.key;
-    return a.seq > b.seq;
-  }
-};
-
-// Pseudo-source in the edge frame from the distances to the edge endpoints
-// (Figure 2(b)); it lies on the side away from face(e).
-void rebuild(double L, double d0, double d1, double* px, double* py) {
-  double x = ((L * L + d0 * d0) - d1 * d1) / (2.0 * L);
-  double t = d0 * d0 - x * x;
-  *px = x;
-  *py = -std::sqrt(t > 0.0 ? t : 0.0);
-}
-
-int run_ich(const OMesh& M, const int32_t* src, int32_t m, double eps_tiny, int32_t filters, double* dist,
-            int64_t* stats) {
-  const bool ch_on = filters & 1, ich_on = filters & 2, full_fan = filters & 4;
-  const int64_t nh = 3 * M.nf;
-  std::vector<double> g(M.nv, INFINITY), AD(nh, INFINITY), AX(nh, 0.0);
-  std::priority_queue<IWin, std::vector<IWin>, IWinCmp> pq;
-  int64_t seq = 0, created = 0, processed = 0, stale = 0, peak = 0, updates = 0, ang_updates = 0;
-  Cnt C;
-  std::vector<Cand> wins;
-  std::vector<Ev> stack, dev;
-  std::vector<AEv> aev;
-
-  auto push_all = [&](std::vector<Cand>& ws) {
-    for (const Cand& k : ws) {
-      double px, py;
-      double Lk = M.L[k.e];
-      rebuild(Lk, k.d0, k.d1, &px, &py);
-      IWin w;
-      w.key = key_of(k.b0, k.b1, px, py, k.sg);
-      w.seq = seq++;
-      w.sg = k.sg;
-      w.b0 = k.b0;
-      w.b1 = k.b1;
-      w.d0 = k.d0;
-      w.d1 = k.d1;
-      w.e = k.e;
-      w.src = k.src;
-      pq.push(w);
-      created++;
-    }
-    ws.clear();
-    if ((int64_t)pq.size() > peak) peak = (int64_t)pq.size();
-  };
-  // apply distance updates immediately, expanding fans at pseudo-sources
-  auto drain = [&]() {
-    while (!stack.empty()) {
-      Ev ev = stack.back();
-      stack.pop_back();
-      if (!(ev.d < g[ev.v] * kEv)) continue;
-      g[ev.v] = ev.d;
-      updates++;
-      if (M.pseudo[ev.v]) {
-        std::vector<Ev> dfr;
-        fan(M, ev.v, ev.d, ev.th, full_fan, g.data(), eps_tiny, ich_on, wins, dfr, C);
-        for (const Ev& x : dfr) stack.push_back(x);
-      }
-    }
-    push_all(wins);
-  };
-
-  for (int32_t i = 0; i < m; ++i) g[src[i]] = 0.0;
-  for (int32_t i = 0; i < m; ++i) {
-    std::vector<Ev> dfr;
-    fan(M, src[i], 0.0, 0.0, true, g.data(), eps_tiny, ich_on, wins, dfr, C);
-    for (const Ev& x : dfr) stack.push_back(x);
-  }
-  drain();
-  while (!pq.empty()) {
-    IWin w = pq.top();
-    pq.pop();
-    if (w.sg > g[w.src]) {
-      stale++;
-      continue;
-    }
-    processed++;
-    double px, py;
-    rebuild(M.L[w.e], w.d0, w.d1, &px, &py);
-    dev.clear();
-    aev.clear();
-    std::vector<Cand> kids;
-    propagate(M, w.b0, w.b1, px, py, w.sg, w.e, w.src, g.data(), AD.data(), AX.data(), ch_on, ich_on, false, eps_tiny, dev,
-              aev, kids, C);
-    for (const AEv& a : aev) {
-      if (a.D < AD[a.e] || (a.D == AD[a.e] && a.X < AX[a.e])) {
-        AD[a.e] = a.D;
-        AX[a.e] = a.X;
-        ang_updates++;
-      }
-    }
-    for (const Ev& x : dev) stack.push_back(x);
-    drain();
-    push_all(kids);
-  }
-  for (int64_t v = 0; v < M.nv; ++v) dist[v] = g[v];
-  if (stats) {
-    int64_t s[16] = {created, processed, stale, C.tiny, C.ich, updates, ang_updates, C.fans, C.fan_kept, 0, peak,
-                     C.notwin, C.deferred, 0, 0, 0};
-    std::memcpy(stats, s, sizeof(s));
-  }
-  return OK;
-}
-
-// --------------------------------------------------------------------------
 // replica: round-based PCH with delayed updates
 // --------------------------------------------------------------------------
 
@@ -966,66 +720,6 @@ int run_replica(const OMesh& M, const int32_t* src, int32_t m, int64_t k, int32_
 // --------------------------------------------------------------------------
 extern "C" {
 
-const char* orc_last_error(void) { return g_err.c_str(); }
-
-// Half-edge lengths from coordinates: sqrt((dx*dx + dy*dy) + dz*dz), with
-// d = xyz[end] - xyz[start].
-int orc_lengths(const double* xyz, int64_t nv, const int32_t* faces, int64_t nf, double* he_len) {
-  for (int64_t f = 0; f < nf; ++f) {
-    for (int i = 0; i < 3; ++i) {
-      int32_t a = faces[3 * f + i], b = faces[3 * f + (i + 1) % 3];
-      if (a < 0 || b < 0 || a >= nv || b >= nv) return fail(EINVAL_, "face index out of range");
-      double dx = xyz[3 * b] - xyz[3 * a];
-      double dy = xyz[3 * b + 1] - xyz[3 * a + 1];
-      double dz = xyz[3 * b + 2] - xyz[3 * a + 2];
-      he_len[3 * f + i] = std::sqrt((dx * dx + dy * dy) + dz * dz);
-    }
-  }
-  return OK;
-}
-
-// Mesh tables for tests: twin[3nf], ax/ay/alpha/phi[3nf], theta[nv], flags[nv]
-// (bit 0 boundary, bit 1 pseudo-source).
-int orc_mesh_info(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, int32_t* twin, double* ax,
-                  double* ay, double* alpha, double* phi, double* theta, uint8_t* flags) {
-  OMesh M;
-  int rc = build_mesh(faces, nf, nv, he_len, M);
-  if (rc) return rc;
-  const int64_t nh = 3 * nf;
-  for (int64_t j = 0; j < nh; ++j) {
-    twin[j] = M.twin[j];
-    ax[j] = M.ax[j];
-    ay[j] = M.ay[j];
-    alpha[j] = M.alpha[j];
-    phi[j] = M.phi[j];
-  }
-  for (int64_t v = 0; v < nv; ++v) {
-    theta[v] = M.theta[v];
-    flags[v] = (uint8_t)(M.bnd[v] | (M.pseudo[v] << 1));
-  }
-  return OK;
-}
-
-static int check_sources(const int32_t* src, int32_t m, int64_t nv) {
-  if (m <= 0) return fail(EINVAL_, "no source vertex");
-  for (int32_t i = 0; i < m; ++i)
-    if (src[i] < 0 || src[i] >= nv) return fail(EINVAL_, "source vertex out of range");
-  return OK;
-}
-
-int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
-            double eps_tiny, int32_t filters, double* dist, int64_t* stats) {
-  OMesh M;
-  int rc = build_mesh(faces, nf, nv, he_len, M);
-  if (rc) return rc;
-  rc = check_sources(src, m, nv);
-  if (rc) return rc;
-  std::vector<int32_t> s(src, src + m);
-  std::sort(s.begin(), s.end());
-  s.erase(std::unique(s.begin(), s.end()), s.end());
-  return run_ich(M, s.data(), (int32_t)s.size(), eps_tiny, filters, dist, stats);
-}
-
 int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
                 int64_t k, int32_t hops, double eps_tiny, int32_t filters, int32_t mode, double delta0,
                 const double* cut_table,
@@ -1034,50 +728,15 @@ int orc_replica(const int32_t* faces, int64_t nf, int64_t nv, const double* he_l
   OMesh M;
   int rc = build_mesh(faces, nf, nv, he_len, M);
   if (rc) return rc;
-  rc = check_sources(src, m, nv);
+  std::vector<int32_t> s;
+  rc = sorted_sources(src, m, nv, s);
   if (rc) return rc;
   if (k < 1) return fail(EINVAL_, "k must be >= 1");
   if (hops < 1) return fail(EINVAL_, "hops must be >= 1");
   if (mode != 0 && mode != 1) return fail(EINVAL_, "unknown selection mode");
   if (mode == 1 && !(delta0 > 0.0)) return fail(EINVAL_, "delta0 must be > 0");
-  std::vector<int32_t> s(src, src + m);
-  std::sort(s.begin(), s.end());
-  s.erase(std::unique(s.begin(), s.end()), s.end());
   return run_replica(M, s.data(), (int32_t)s.size(), k, hops, eps_tiny, filters, mode, delta0, cut_table, n_cut,
                      dist, stats, rlog, max_log, n_rounds, vupd);
-}
-
-// Dijkstra along mesh edges (length of the best edge path).
-int orc_dijkstra(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
-                 double* dist) {
-  int rc = check_sources(src, m, nv);
-  if (rc) return rc;
-  std::vector<std::vector<std::pair<int32_t, double>>> adj(nv);
-  for (int64_t j = 0; j < 3 * nf; ++j) {
-    int32_t a = faces[j], b = faces[nxt((int32_t)j)];
-    adj[a].push_back({b, he_len[j]});
-    adj[b].push_back({a, he_len[j]});
-  }
-  for (int64_t v = 0; v < nv; ++v) dist[v] = INFINITY;
-  typedef std::pair<double, int32_t> QE;
-  std::priority_queue<QE, std::vector<QE>, std::greater<QE>> q;
-  for (int32_t i = 0; i < m; ++i) {
-    dist[src[i]] = 0.0;
-    q.push({0.0, src[i]});
-  }
-  while (!q.empty()) {
-    QE t = q.top();
-    q.pop();
-    if (t.first > dist[t.second]) continue;
-    for (auto& e : adj[t.second]) {
-      double nd = t.first + e.second;
-      if (nd < dist[e.first]) {
-        dist[e.first] = nd;
-        q.push({nd, e.first});
-      }
-    }
-  }
-  return OK;
 }
 
 // Own elementary functions, exported so tests can check them against libm.

@@ -177,3 +177,22 @@ def test_grazing_convex_boundary_regression(oracle):
     assert rel(d, ref) < 1e-12
     dr, _, _ = oracle.replica(m, [0], 2048)
     assert rel(dr, ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["ico4", "grid48", "c1", "lshape12", "cone7"])
+def test_ich_and_replica_agree(oracle, case):
+    """The two window codes share no arithmetic: ICH carries the paper's
+    (d0, d1) windows, unfolds children by ray hits in the parent's frame and
+    fans by the law of sines; the replica carries (px, py) pseudo-sources
+    rotated into each child's frame. On meshes of thousands of faces (well
+    past what brute force enumerates) they agree to rounding, so a derivation
+    error in either would show here."""
+    m, s = {"ico4": (G.bumpy_icosphere(4, seed=9), 17), "grid48": (G.bump_grid(48, seed=4), 100),
+            "c1": (G.config_mesh(1), 0), "lshape12": (G.lshape(12), 0), "cone7": (G.cone_fan(7, 8), 5)}[case]
+    hbar = float(oracle.lengths(m).mean())
+    d, _ = oracle.ich(m, [s])
+    for kw in (dict(k=1 << 30), dict(k=512, hops=3), dict(k=256, mode=1, delta0=2 * hbar, hops=4)):
+        dr, _, _ = oracle.replica(m, [s], **kw)
+        fin = np.isfinite(d)
+        assert np.array_equal(fin, np.isfinite(dr)), kw
+        assert np.max(np.abs(d[fin] - dr[fin]) / np.maximum(d[fin], hbar)) < 1e-12, kw
