@@ -330,11 +330,14 @@ struct Ich {
     }
   }
 
-  void run(const std::vector<int32_t>& src) {
+  // max_processed > 0 stops after that many propagated windows (a bounded
+  // sample of the run, for timing only: the distances are then incomplete)
+  void run(const std::vector<int32_t>& src, int64_t max_processed = 0) {
     for (int32_t s : src) g[s] = 0.0;
     for (int32_t s : src) fan(s, 0.0, 0.0, true);
     settle();
     while (!pq.empty()) {
+      if (max_processed > 0 && processed >= max_processed) break;
       const Win w = pq.top().w;
       pq.pop();
       if (w.d > g[w.src]) {
@@ -356,8 +359,9 @@ extern "C" {
 // (int64 [16], nullable): created, processed, stale, tiny, filtered, vertex
 // updates, corner updates, fans, fan windows, 0, peak queue, boundary drops,
 // edge-path arrivals from fans, 0, 0, 0.
-int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
-            double eps_tiny, int32_t filters, double* dist_out, int64_t* stats) {
+int orc_ich_bounded(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src,
+                    int32_t m, double eps_tiny, int32_t filters, int64_t max_processed, double* dist_out,
+                    int64_t* stats) {
   OMesh M;
   int rc = orc::build_mesh(faces, nf, nv, he_len, M);
   if (rc) return rc;
@@ -365,7 +369,7 @@ int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, 
   rc = orc::sorted_sources(src, m, nv, s);
   if (rc) return rc;
   Ich run(M, eps_tiny, filters);
-  run.run(s);
+  run.run(s, max_processed);
   for (int64_t v = 0; v < nv; ++v) dist_out[v] = run.g[v];
   if (stats) {
     int64_t st[16] = {run.created, run.processed, run.stale, run.tiny, run.filtered, run.updates,
@@ -374,6 +378,11 @@ int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, 
     std::memcpy(stats, st, sizeof(st));
   }
   return orc::OK;
+}
+
+int orc_ich(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len, const int32_t* src, int32_t m,
+            double eps_tiny, int32_t filters, double* dist_out, int64_t* stats) {
+  return orc_ich_bounded(faces, nf, nv, he_len, src, m, eps_tiny, filters, 0, dist_out, stats);
 }
 
 }  // extern "C"

@@ -50,6 +50,7 @@ def lib():
         L.orc_lengths.argtypes = [P, i64, P, i64, P]
         L.orc_mesh_info.argtypes = [P, i64, i64, P, P, P, P, P, P, P, P]
         L.orc_ich.argtypes = [P, i64, i64, P, P, i32, d, i32, P, P]
+        L.orc_ich_bounded.argtypes = [P, i64, i64, P, P, i32, d, i32, i64, P, P]
         L.orc_replica.argtypes = [P, i64, i64, P, P, i32, i64, i32, d, i32, i32, d, P, i64, P, P, P, i64, P, P]
         L.orc_dijkstra.argtypes = [P, i64, i64, P, P, i32, P]
         L.orc_fn_atan2.argtypes = [d, d]
@@ -101,18 +102,20 @@ def _sources(sources) -> np.ndarray:
     return np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
 
 
-def ich(mesh, sources, eps_tiny: float = 0.0, filters: int = 3):
+def ich(mesh, sources, eps_tiny: float = 0.0, filters: int = 3, max_processed: int = 0):
     """Exact distance field by sequential ICH.
 
     filters: bit 0 the CH one-angle-one-split rule, bit 1 the ICH window
     filter, bit 2 full fans (every direction at a pseudo-source).
+    max_processed > 0 stops after that many propagated windows: a bounded
+    sample of the run for timing, whose distances are incomplete.
     """
     s = _sources(sources)
     he = lengths(mesh)
     dist = np.empty(mesh.nv, np.float64)
     stats = np.zeros(16, np.int64)
-    _check(lib().orc_ich(_ptr(mesh.faces), mesh.nf, mesh.nv, _ptr(he), _ptr(s), s.size, eps_tiny, filters,
-                         _ptr(dist), _ptr(stats)))
+    _check(lib().orc_ich_bounded(_ptr(mesh.faces), mesh.nf, mesh.nv, _ptr(he), _ptr(s), s.size, eps_tiny, filters,
+                                 int(max_processed), _ptr(dist), _ptr(stats)))
     return dist, dict(zip(STAT_FIELDS, stats.tolist()))
 
 
