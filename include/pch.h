@@ -122,9 +122,9 @@ typedef struct {
   int32_t rounds_per_sync;    /* rounds enqueued between host polls (default 16) */
   const double* cutoff_table; /* host, n_cutoff values, PCH_SELECT_TABLE */
   int64_t n_cutoff;
-  int32_t collect_timing;     /* n > 0: time the propagation launch of every
-                                 n-th round with HIP events on hip_stream
-                                 (pch_stats.ms_propagate) */
+  int32_t collect_timing;     /* n > 0: time the phases of every n-th round
+                                 with HIP events on hip_stream
+                                 (pch_stats.ms_phase, ms_propagate) */
   int32_t hops;               /* propagation hops per round, 1..16 (default 1:
                                  every selected window crosses one face, as in
                                  Algorithm 1). With h > 1, children that pass
@@ -156,6 +156,19 @@ typedef struct {
                                  lists in LDS, depth first (default); 0 = one
                                  launch per hop. Same windows, events and
                                  results either way */
+  int32_t fuse_scan;          /* 1 = with fused hops, the pool scan of the
+                                 selection runs in the same launch: each
+                                 workgroup propagates the windows it selects
+                                 at once, with no selection buffer (default;
+                                 not with PCH_SELECT_STRIDED or organize);
+                                 0 = a partition launch first. Same windows,
+                                 events and results either way */
+  int32_t round_graph;        /* 1 = enqueue each rounds_per_sync rounds as one
+                                 captured HIP graph (kept in the mesh handle
+                                 and replayed while the launch arguments stay
+                                 the same; not with collect_timing or an odd
+                                 rounds_per_sync); 0 = launch by launch
+                                 (default) */
 } pch_options;
 
 /* Fill opts with the defaults above. */
@@ -170,6 +183,14 @@ typedef struct {
   double delta0;             /* first step used by PCH_SELECT_DELTA */
   int64_t hop_launches;      /* propagation launches per round: 1 when the
                                 hops are fused, else hops */
+  double ms_phase[4];        /* with collect_timing: GPU time of the timed
+                                rounds' phases, from HIP events between them
+                                on hip_stream: [0] selection (histogram passes
+                                and partition), [1] propagation (=
+                                ms_propagate), [2] organization by edge,
+                                [3] events (Algorithm 4 and the next round's
+                                set-up) */
+  int64_t timed_rounds;      /* rounds timed in ms_phase */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).
@@ -180,7 +201,10 @@ typedef struct {
  * If the window pool outgrows its capacity the run restarts with twice the
  * capacity (stats->restarts counts them); PCH_EOVERFLOW if that would pass
  * opts->pool_limit. Errors: PCH_EINVAL (source out of range, m < 1, bad
- * option), PCH_ENOMEM, PCH_EDEVICE, PCH_ENUMERIC. */
+ * option), PCH_ENOMEM, PCH_EDEVICE (a HIP error, or a window or event whose
+ * half-edge or vertex index lies outside the mesh: every such index is
+ * range-checked before it is gathered and none is dereferenced),
+ * PCH_ENUMERIC (a window's apex crossing was not finite). */
 pch_status pch_geodesic(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist,
                         void* hip_stream, const pch_options* opts, pch_stats* stats);
 
@@ -200,8 +224,10 @@ pch_status pch_round_log(pch_mesh mesh, int64_t* out, int64_t max_rounds, int64_
  * device queue (most expected time first: 24 windows per half-edge before
  * the first run, then the workgroup time each field took in the previous
  * run) and runs
- * its rounds with the adaptive-step selection (PCH_SELECT_DELTA); results
- * equal pch_geodesic with the same k and delta0 bit for bit. With gang > 1 a
+ * its rounds with the adaptive-step selection (PCH_SELECT_DELTA) or the
+ * learned cutoff (PCH_SELECT_LEARNED, each field with its own predictions);
+ * results equal pch_geodesic with the same rule, k, hops and (for LEARNED)
+ * predictions bit for bit. With gang > 1 a
  * workgroup may instead join a running field of its own XCD when that field's
  * expected time left per workgroup exceeds the next queued field's; the field's
  * rounds are then split over its workgroups from the next round on. Fields
@@ -228,6 +254,14 @@ typedef struct {
                             other, in ticks of the device's 100 MHz wall clock
                             (0 = 2 s); when a wait runs out the field is rerun
                             with pch_geodesic */
+  int32_t select_mode;   /* PCH_SELECT_DELTA (default) or PCH_SELECT_LEARNED */
+  const float* predicted; /* PCH_SELECT_LEARNED: device float [offsets[n_fields]],
+                            the predicted distances of field f at
+                            predicted[offsets[f] .. offsets[f + 1]) (the layout
+                            of the output, see pch_batch_offsets); read at
+                            every pch_batch_run, so the caller keeps it alive
+                            and may change its values between runs */
+  double w0;             /* as pch_options.w0 (default 4) */
 } pch_batch_options;
 
 typedef struct {
@@ -253,10 +287,28 @@ pch_status pch_batch_offsets(pch_batch batch, int64_t* offsets);
 /* dist: device double [offsets[n_fields]] (caller-owned). */
 pch_status pch_batch_run(pch_batch batch, double* dist, void* hip_stream, pch_batch_stats* stats);
 
-/* Per-field record of the last run, host int64 [n_fields][10]: status (0
- * ok; rerun with pch_geodesic after 1 pool overflow, 2 the round limit, 3 a
- * shared field whose workgroups stopped waiting for each other, 4 a field no
- * workgroup finished), rounds, windows processed, windows created, fans,
+/* Status of a batched field (first column of pch_batch_field_stats). Every
+ * field whose status is not PCH_FIELD_OK is rerun with pch_geodesic and the
+ * same rule: a pool overflow, the round limit, an abandoned gang or a field
+ * no workgroup finished then complete normally, while non-finite window
+ * geometry makes pch_batch_run return PCH_ENUMERIC and an index outside the
+ * mesh PCH_EDEVICE (the single-field checks). */
+enum {
+  PCH_FIELD_OK = 0,
+  PCH_FIELD_OVERFLOW = 1,   /* the workgroup's window pool overflowed */
+  PCH_FIELD_MAX_ROUNDS = 2, /* no termination within the round limit */
+  PCH_FIELD_ABANDONED = 3,  /* a shared field whose workgroups stopped waiting */
+  PCH_FIELD_NOT_RUN = 4,    /* no workgroup finished the field */
+  PCH_FIELD_NONFINITE = 5,  /* a window's apex crossing was not finite */
+  PCH_FIELD_BAD_INDEX = 6   /* a window or event named a half-edge or vertex
+                               outside the mesh (an internal error: such an
+                               index is never dereferenced) */
+};
+const char* pch_field_status_string(int64_t status);
+
+/* Per-field record of the last run, host int64 [n_fields][10]: status
+ * (PCH_FIELD_*, after any rerun the status of the batched attempt), rounds,
+ * windows processed, windows created, fans,
  * peak pool, stale windows, the time from the start of the field to its end
  * in ticks of the device's constant-rate wall clock (100 MHz on MI355X; 0
  * after a rerun), the helper workgroups that joined it, and the ticks they

@@ -31,6 +31,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,8 @@ constexpr int kHistBins = 4096;
 constexpr int kSmallGrid = 128;
 constexpr u64 kAllOnes = ~0ull;
 constexpr int64_t kMaxRounds = 1 << 24;
+// sources kept in a stack array before they are sorted
+constexpr int kNoallocMaxSources = 1024;
 
 // constants of the window arithmetic (same values as the method description)
 constexpr double kTau = 1e-12;             // endpoint / occupancy tolerance, relative to L
@@ -89,7 +92,7 @@ enum {
 enum { X_NOTWIN = 0, X_NUM = 4 };
 
 struct Ctl {
-  u64 npool[2];
+  u64 npool[2];     // slots used in pool buffer 0 and 1 (live windows and tombstones)
   u64 ndev[2];
   u64 nsel;
   u64 naev;
@@ -117,8 +120,22 @@ struct Ctl {
   u64 peak;
   u64 smode;        // current round uses the strided selection
   u64 ncand;        // fan candidates of the current round
-  u64 pad[6];
+  u64 badidx;       // a window or event named a half-edge or vertex outside the mesh
+  // The pool: the round's windows are the live slots [0, nscan) of buffer
+  // pin. The partition either leaves the windows it keeps in place (selected
+  // and stale ones become tombstones) and the round appends its new windows
+  // to the same buffer after slot s0 = nscan, or it compacts the kept windows
+  // into the other buffer (s0 = 0); pout is the buffer that receives them.
+  // The next round's live windows are keptin (kept in place) plus the slots
+  // appended after s0.
+  u64 pin, pout, nscan, s0, keptin;
+  u64 pad[5];
 };
+
+// key of a tombstone: a pool slot whose window was selected or dropped (no
+// finite non-negative key has this bit pattern, and no histogram prefix of
+// one matches it)
+constexpr u64 kDead = ~0ull;
 
 // A pool of windows (Section 3, Figure 2): the interval [b0, b1] of
 // half-edge e, the pseudo-source (px, py) in e's frame, its distance sg from
@@ -173,6 +190,7 @@ struct DevMesh {
   const int32_t* coff;
   const int32_t* corner;
   const pch::Corner* crec;
+  int32_t nv, nh;  // vertices and half-edges: every gathered index is checked against them
 };
 
 struct DevState {
@@ -470,7 +488,34 @@ __device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, do
   P.es[i] = make_int2(e, src);
 }
 
+// A list of hop windows in LDS: like a pool without the key, which the
+// propagation of a window does not read (48 bytes per window).
+struct HopList {
+  double2* bb;
+  double2* pp;
+  double* sg;
+  int2* es;
+};
+
+__device__ __forceinline__ void store_window(const HopList& P, u64 i, double b0, double b1, double px, double py,
+                                             double sg, double, int32_t e, int32_t src) {
+  P.bb[i] = make_double2(b0, b1);
+  P.pp[i] = make_double2(px, py);
+  P.sg[i] = sg;
+  P.es[i] = make_int2(e, src);
+}
+
 __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, 1ull); }
+
+// Range guard of a gathered index (a window's half-edge or pseudo-source, an
+// event's vertex or corner): an index outside [0, n) is never dereferenced; it
+// sets the control block's badidx flag, and the host reports an error for the
+// field instead of reading outside the mesh's tables.
+__device__ __forceinline__ bool idx_ok(Ctl* c, int32_t i, int32_t n) {
+  if ((u32)i < (u32)n) return true;
+  atomicOr(&c->badidx, 1ull);
+  return false;
+}
 
 // Incoming angle of a propagation event (q = 4 e + k, pseudo-source (px, py)
 // in e's frame): the angular position around vertex k of half-edge e of the
@@ -622,12 +667,14 @@ __device__ __forceinline__ double shfl_d(double x, int src) {
 // v at distance d). The wavefront's (fan, corner) pairs are spread over its
 // lanes: an exclusive prefix sum of the fan degrees numbers the pairs and each
 // lane finds the owner of its pair by binary search over the lanes. Windows
-// and events are reserved once per wavefront and step; windows go to pool qi,
-// events to event buffer qi. Every lane of the wavefront must call it.
+// and events are reserved once per wavefront and step; windows go to pool
+// buffer po, events to event buffer qi. Every lane of the wavefront must call
+// it.
 // The lane's corners are q0 .. q0 + deg - 1 of the CCW corner list (deg = 0
 // when it has no fan).
 __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, double d, double th, bool full,
-                          int qi, u64& kmn, u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer, u32& notwin) {
+                          int po, int qi, u64& kmn, u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer,
+                          u32& notwin) {
   Ctl* c = a.ctl;
   const int lane = lane_id();
   if (!has) deg = 0;
@@ -639,7 +686,7 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
   }
   const int total = __shfl(incl, kWave - 1, kWave);
   const int base = incl - deg;
-  const Pool& P = a.pool[qi];
+  const Pool P = po ? a.pool[1] : a.pool[0];
   const DistEv& E = a.ev[qi];
   for (int t0 = 0; t0 < total; t0 += kWave) {
     const int t = t0 + lane;
@@ -664,7 +711,7 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
     const u32 nev = (o.ea ? 1u : 0u) + (o.eb ? 1u : 0u);
     u64 jw, je, jz;
     u32 tw, te, tz;
-    wave_reserve3(&c->npool[qi], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, jw, je, jz, tw, te, tz);
+    wave_reserve3(&c->npool[po], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, jw, je, jz, tw, te, tz);
     if (o.win) {
       if (jw < (u64)a.cap) {
         store_window(P, jw, o.b0, o.b1, o.px, o.py, od, o.key, o.e, ov);
@@ -744,10 +791,12 @@ __device__ __forceinline__ u64 ld(const u64* p) {
 // smallest key.
 __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, double* m_out) {
   Ctl* c = a.ctl;
-  const u64 done = ld(&c->done), active = ld(&c->active), overflow = ld(&c->overflow);
+  const u64 done = ld(&c->done), active = ld(&c->active), overflow = ld(&c->overflow) | ld(&c->badidx);
   const u64 round = ld(&c->round), peak = ld(&c->peak);
   const u64 dmode = ld(&c->dmode), lmode = ld(&c->lmode);
-  const u64 N = ld(&c->npool[p]), nd = ld(&c->ndev[p]);
+  const u64 pout = ld(&c->pout), s0 = ld(&c->s0), keptin = ld(&c->keptin);
+  const u64 slots = ld(&c->npool[pout & 1]), nd = ld(&c->ndev[p]);
+  const u64 N = keptin + (slots - s0);  // live windows
   const u64 mn = ld(&c->kmin[p]), mx = ld(&c->kmax[p]);
   u64 rec[C_NUM], tot[C_NUM];
 #pragma unroll
@@ -793,7 +842,19 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
 #pragma unroll
   for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
   c->cnt[C_N] = N;
-  c->npool[1 - p] = 0;
+  // the pool: keep the windows in place while at most half of the slots are
+  // tombstones and half of the buffer is used, else compact them into the
+  // other buffer
+  c->pin = pout;
+  c->nscan = slots;
+  c->keptin = 0;
+  if (slots - N > N || slots > (u64)a.cap / 2) {
+    c->pout = pout ^ 1;
+    c->npool[(pout ^ 1) & 1] = 0;
+    c->s0 = 0;
+  } else {
+    c->s0 = slots;
+  }
   c->ndev[1 - p] = 0;
   c->nsel = 0;
   c->naev = 0;
@@ -936,7 +997,7 @@ __global__ void __launch_bounds__(kBlock) k_init_fans(RoundArgs a, const int32_t
     const int v = has ? src[i] : 0;
     const int q0 = has ? a.m.coff[v] : 0;
     const int deg = has ? a.m.coff[v + 1] - q0 : 0;
-    wave_fans(a, has, v, q0, deg, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
+    wave_fans(a, has, v, q0, deg, 0.0, 0.0, true, 0, 0, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
   kmn = wave_min64(kmn);
   kmx = wave_max64(kmx);
@@ -948,48 +1009,98 @@ __global__ void __launch_bounds__(kBlock) k_init_fans(RoundArgs a, const int32_t
 
 __global__ void k_begin(RoundArgs a, int p) { round_begin(a, p); }
 
-// Predicted-distance CDF for the learned cutoff: maximum, histogram, scan.
-__global__ void k_pred_max(const float* pred, int64_t n, u32* mx) {
-  u32 m = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float x = pred[i];
-    const u32 b = (x > 0.f && x < INFINITY) ? __float_as_uint(x) : 0u;  // non-negative floats order as u32
-    m = b > m ? b : m;
-  }
-  atomicMax(mx, m);
+// Predicted-distance CDFs for the learned cutoff (maximum, histogram, scan)
+// of nf fields: field f has n_f predictions at pred + off_f and its table at
+// cdf + f (kCdfBins + 1), the bits of the largest positive finite prediction
+// in the last word; its bin width goes to pbin[f]. With off == nullptr there
+// is one field of n1 predictions at offset 0. blockIdx.y strides over the
+// fields. A field's table does not depend on how many fields are built
+// together.
+struct PredFields {
+  const float* pred;
+  const int64_t* off;  // [nf] offsets, or null
+  const int64_t* n;    // [nf] counts, or null
+  int64_t n1;
+  int32_t nf;
+  u32* cdf;
+  double* pbin;  // [nf] or null
+};
+
+__device__ __forceinline__ void pred_field(const PredFields& P, int f, const float*& x, int64_t& n, u32*& cdf) {
+  x = P.pred + (P.off ? P.off[f] : 0);
+  n = P.off ? P.n[f] : P.n1;
+  cdf = P.cdf + (int64_t)f * (kCdfBins + 1);
 }
-__global__ void k_pred_hist(const float* pred, int64_t n, const u32* mx, u32* hist) {
-  const double bw = (double)__uint_as_float(*mx) * 1.000001 / (double)kCdfBins;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float x = pred[i];
-    int b = (x > 0.f && bw > 0.0) ? (int)((double)x / bw) : 0;
-    if (!(x < INFINITY)) b = kCdfBins - 1;
-    b = b < 0 ? 0 : (b >= kCdfBins ? kCdfBins - 1 : b);
-    atomicAdd(&hist[b], 1u);
+
+__device__ __forceinline__ double pred_bin_width(u32 mx) { return (double)__uint_as_float(mx) * 1.000001 / (double)kCdfBins; }
+
+__global__ void k_pred_max(PredFields P) {
+  for (int f = blockIdx.y; f < P.nf; f += gridDim.y) {
+    const float* x;
+    int64_t n;
+    u32* cdf;
+    pred_field(P, f, x, n, cdf);
+    u32 m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const float v = x[i];
+      const u32 b = (v > 0.f && v < INFINITY) ? __float_as_uint(v) : 0u;  // non-negative floats order as u32
+      m = b > m ? b : m;
+    }
+    atomicMax(&cdf[kCdfBins], m);
   }
 }
-__global__ void __launch_bounds__(1024) k_pred_scan(u32* hist) {
+__global__ void k_pred_hist(PredFields P) {
+  for (int f = blockIdx.y; f < P.nf; f += gridDim.y) {
+    const float* x;
+    int64_t n;
+    u32* cdf;
+    pred_field(P, f, x, n, cdf);
+    const double bw = pred_bin_width(cdf[kCdfBins]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const float v = x[i];
+      int b = (v > 0.f && bw > 0.0) ? (int)((double)v / bw) : 0;
+      if (!(v < INFINITY)) b = kCdfBins - 1;
+      b = b < 0 ? 0 : (b >= kCdfBins ? kCdfBins - 1 : b);
+      atomicAdd(&cdf[b], 1u);
+    }
+  }
+}
+__global__ void __launch_bounds__(1024) k_pred_scan(PredFields P) {
   __shared__ u32 part[1024];
   constexpr int per = kCdfBins / 1024;
-  u32 loc[per];
-  u32 sum = 0;
-  for (int i = 0; i < per; ++i) {
-    loc[i] = hist[threadIdx.x * per + i];
-    sum += loc[i];
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+  for (int f = blockIdx.x; f < P.nf; f += gridDim.x) {
+    u32* hist = P.cdf + (int64_t)f * (kCdfBins + 1);
+    u32 loc[per];
+    u32 sum = 0;
+    for (int i = 0; i < per; ++i) {
+      loc[i] = hist[threadIdx.x * per + i];
+      sum += loc[i];
+    }
+    part[threadIdx.x] = sum;
     __syncthreads();
-    part[threadIdx.x] += y;
+    for (int o = 1; o < 1024; o <<= 1) {
+      const u32 y = threadIdx.x >= (u32)o ? part[threadIdx.x - o] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += y;
+      __syncthreads();
+    }
+    u32 run = part[threadIdx.x] - sum;
+    for (int i = 0; i < per; ++i) {
+      run += loc[i];
+      hist[threadIdx.x * per + i] = run;
+    }
+    if (threadIdx.x == 0 && P.pbin) P.pbin[f] = pred_bin_width(hist[kCdfBins]);
     __syncthreads();
   }
-  u32 run = part[threadIdx.x] - sum;
-  for (int i = 0; i < per; ++i) {
-    run += loc[i];
-    hist[threadIdx.x * per + i] = run;
-  }
+}
+
+// Enqueues the tables of P (zeroed first).
+void enqueue_pred_cdf(const PredFields& P, hipStream_t st) {
+  k_fill_u32<<<256, kBlock, 0, st>>>(P.cdf, (int64_t)P.nf * (kCdfBins + 1), 0u);
+  const unsigned fy = (unsigned)std::min(P.nf, 65535);
+  k_pred_max<<<dim3(P.off ? 16 : 256, fy), kBlock, 0, st>>>(P);
+  k_pred_hist<<<dim3(P.off ? 64 : 1024, fy), kBlock, 0, st>>>(P);
+  k_pred_scan<<<std::min(P.nf, 65535), 1024, 0, st>>>(P);
 }
 
 // One 12-bit radix-select pass over the truncated keys t = key_bits >> shift:
@@ -1006,11 +1117,12 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   if (!c->active || c->use_table || c->sel_all || c->rank == 0) return;
   for (int i = threadIdx.x; i < kHistBins; i += kBlock) h[i] = 0;
   __syncthreads();
-  const u64 N = min(c->npool[p], (u64)a.cap);
+  const u64 N = min(c->nscan, (u64)a.cap);
   const int s = (int)c->shift;
   const int lo = 24 - 12 * pass;
   const u64 want = c->want;
-  const double2* sk = a.pool[p].sk;
+  // tombstones (key kDead) never match a prefix of a finite key
+  const double2* sk = c->pin ? a.pool[1].sk : a.pool[0].sk;
   for (u64 i = blockIdx.x * (u64)kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
     const u64 t = bits(sk[i].y) >> s;
     if ((t >> (lo + 12)) == want) atomicAdd(&h[(t >> lo) & (kHistBins - 1)], 1u);
@@ -1069,40 +1181,41 @@ __global__ void __launch_bounds__(kBlock) k_hist(RoundArgs a, int p, int pass) {
   }
 }
 
-// Split the pool: stale windows (sigma > geod_dist of their pseudo-source) are
-// dropped, selected windows go to the selection buffer, the rest to the other
-// pool buffer. Appends are reserved per wavefront.
+// Split the pool (selection, Section 4.2 step 1): stale windows (sigma >
+// geod_dist of their pseudo-source) are dropped, selected windows go to the
+// selection buffer, the rest stay in the pool. In a round that keeps the pool
+// in place, a kept window is not moved: only the selected and stale ones are
+// touched (copied out and marked as tombstones), so the scan reads the key,
+// distance and pseudo-source of each slot and nothing else. A compacting round
+// moves the kept windows into the other buffer instead. Appends are reserved
+// per wavefront.
 __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
-  const Pool P = a.pool[p];
-  const Pool Q = a.pool[1 - p];
-  const Pool S = a.sel;
-  // the lane's first window is loaded together with the round's counters
-  double2 f_bb = make_double2(0, 0), f_pp = f_bb, f_sk = f_bb;
-  int2 f_es = make_int2(0, 0);
-  if (t0 < (u64)a.cap) {
-    f_bb = P.bb[t0];
-    f_pp = P.pp[t0];
-    f_sk = P.sk[t0];
-    f_es = P.es[t0];
-  }
   const bool active = c->active != 0;
-  const u64 N = active ? min(c->npool[p], (u64)a.cap) : 0;
+  const u64 pin = c->pin, pout = c->pout;
+  const u64 N = active ? min(c->nscan, (u64)a.cap) : 0;
   const int s = (int)c->shift;
   const u64 T = c->want;
   const bool all = c->sel_all;
   const bool tab = c->use_table;
   const double cv = c->cutval;
-  // Strided selection (Section 6, the approximate k-selection): the thread
-  // owns windows t0, t0 + stride, t0 + 2 stride, ... and selects the nearest
-  // of those that are not stale (the first one on equal keys).
   const bool strided = c->smode != 0;
+  const bool inplace = pin == pout;
+  const Pool P = pin ? a.pool[1] : a.pool[0];
+  const Pool Q = pout ? a.pool[1] : a.pool[0];
+  u64* qctr = &c->npool[pout & 1];
+  const Pool S = a.sel;
+  // Strided selection (Section 6, the approximate k-selection): the thread
+  // owns slots t0, t0 + stride, t0 + 2 stride, ... and selects the nearest
+  // of its live windows that are not stale (the first one on equal keys).
   u64 imin = kAllOnes;
   if (strided) {
     double kbest = 0.0;
     for (u64 i = t0; i < N; i += stride) {
-      const double2 wsk = i == t0 ? f_sk : P.sk[i];
-      const int32_t src = i == t0 ? f_es.y : P.es[i].y;
+      const double2 wsk = P.sk[i];
+      if (bits(wsk.y) == kDead) continue;
+      const int32_t src = P.es[i].y;
+      if (!idx_ok(c, src, a.m.nv)) continue;
       if (wsk.x > from_bits(lda(&a.s.g[src]))) continue;  // stale
       if (imin == kAllOnes || wsk.y < kbest) {
         kbest = wsk.y;
@@ -1110,62 +1223,65 @@ __device__ __forceinline__ void ph_partition(const RoundArgs& a, int p, u64 t0, 
       }
     }
   }
-  u32 stale_n = 0;
+  u32 stale_n = 0, kept_in = 0;
   u64 kmn = kAllOnes, kmx = 0;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
-    const bool valid = i < N;
-    bool sel = false, keep = false;
-    double b0 = 0, b1 = 0, px = 0, py = 0, sg = 0, key = 0;
-    int32_t e = 0, src = 0;
-    if (valid) {
-      const double2 wbb = i == t0 ? f_bb : P.bb[i];
-      const double2 wpp = i == t0 ? f_pp : P.pp[i];
-      const double2 wsk = i == t0 ? f_sk : P.sk[i];
-      const int2 wes = i == t0 ? f_es : P.es[i];
-      b0 = wbb.x;
-      b1 = wbb.y;
-      px = wpp.x;
-      py = wpp.y;
-      sg = wsk.x;
-      key = wsk.y;
-      e = wes.x;
-      src = wes.y;
-      const bool stale = sg > from_bits(lda(&a.s.g[src]));
-      if (stale) {
-        stale_n++;
-      } else {
-        sel = strided ? (all || i == imin) : (tab ? (key <= cv) : (all || ((bits(key) >> s) <= T)));
-        keep = !sel;
+    bool sel = false, keep = false, gone = false;
+    double2 wsk = make_double2(0.0, 0.0);
+    int2 wes = make_int2(0, 0);
+    if (i < N) {
+      wsk = P.sk[i];
+      if (bits(wsk.y) != kDead) {
+        wes = P.es[i];
+        const bool stale = !idx_ok(c, wes.y, a.m.nv) || wsk.x > from_bits(lda(&a.s.g[wes.y]));
+        if (stale) {
+          stale_n++;
+          gone = true;
+        } else {
+          sel = strided ? (all || i == imin) : (tab ? (wsk.y <= cv) : (all || ((bits(wsk.y) >> s) <= T)));
+          keep = !sel;
+        }
       }
+    }
+    const bool move = sel || (keep && !inplace);
+    double2 wbb = make_double2(0.0, 0.0), wpp = wbb;
+    if (move) {
+      wbb = P.bb[i];
+      wpp = P.pp[i];
     }
     u64 js, jk, jz;
     u32 ts, tk, tz;
-    wave_reserve3(&c->nsel, sel ? 1u : 0u, &c->npool[1 - p], keep ? 1u : 0u, &c->nsel, 0u, js, jk, jz, ts, tk, tz);
+    wave_reserve3(&c->nsel, sel ? 1u : 0u, qctr, (keep && !inplace) ? 1u : 0u, &c->nsel, 0u, js, jk, jz, ts, tk,
+                  tz);
     if (sel) {
       if (js < (u64)a.cap) {
-        store_window(S, js, b0, b1, px, py, sg, key, e, src);
-        if (a.org_shift >= 0) atomicAdd(&a.org_hist[e >> a.org_shift], 1u);
+        store_window(S, js, wbb.x, wbb.y, wpp.x, wpp.y, wsk.x, wsk.y, wes.x, wes.y);
+        if (a.org_shift >= 0) atomicAdd(&a.org_hist[wes.x >> a.org_shift], 1u);
       } else {
         flag_overflow(c);
       }
     }
+    if (inplace && (sel || gone)) reinterpret_cast<double*>(P.sk)[2 * i + 1] = from_bits(kDead);
     if (keep) {
-      if (jk < (u64)a.cap) {
-        store_window(Q, jk, b0, b1, px, py, sg, key, e, src);
-        const u64 kb = bits(key);
-        kmn = kb < kmn ? kb : kmn;
-        kmx = kb > kmx ? kb : kmx;
+      if (inplace) {
+        kept_in++;
+      } else if (jk < (u64)a.cap) {
+        store_window(Q, jk, wbb.x, wbb.y, wpp.x, wpp.y, wsk.x, wsk.y, wes.x, wes.y);
       } else {
         flag_overflow(c);
       }
+      const u64 kb = bits(wsk.y);
+      kmn = kb < kmn ? kb : kmn;
+      kmx = kb > kmx ? kb : kmx;
     }
   }
-  u32 tot[1] = {stale_n};
+  u32 tot[2] = {stale_n, kept_in};
   block_totals(kmn, kmx, tot);
   if (threadIdx.x == 0) {
     if (kmn != kAllOnes) atomicMin(&c->kmin[1 - p], kmn);
     if (kmx != 0) atomicMax(&c->kmax[1 - p], kmx);
     if (tot[0] && a.counts) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
+    if (tot[1]) atomicAdd(&c->keptin, (u64)tot[1]);
   }
 }
 
@@ -1176,6 +1292,7 @@ __global__ void __launch_bounds__(kBlock) k_partition(RoundArgs a, int p) {
 // Per-launch values of the propagation that every window reads.
 struct PropCtx {
   Pool Q;    // the next round's pool
+  u64* qctr; // its slot counter
   DistEv E;  // this round's distance events
   int sh;    // selection test of a child: key bits >> sh <= T, or key <= cv
   u64 T;
@@ -1195,9 +1312,9 @@ struct PropAcc {
 // round's selection test go to HQ (capacity hq_cap) through the counter
 // nq_ctr when to_hop is set, the others to the next pool; events go to this
 // round's buffers.
-template <bool kBlockRes>
+template <bool kBlockRes, class HopQ>
 __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const PropCtx& x, bool have, double2 wbb,
-                                            double2 wpp, double2 wsk, int2 wes, bool to_hop, const Pool& HQ,
+                                            double2 wpp, double2 wsk, int2 wes, bool to_hop, const HopQ& HQ,
                                             u64* nq_ctr, u64 hq_cap, PropAcc& acc) {
   Ctl* c = a.ctl;
   const DevMesh& m = a.m;
@@ -1216,7 +1333,7 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   double aD = 0, aX = 0;
   double sg = 0;
   int32_t src = 0, e = 0;
-  if (have) {
+  if (have && idx_ok(c, wes.x, m.nh) && idx_ok(c, wes.y, m.nv)) {
     const double b0 = wbb.x, b1 = wbb.y, px = wpp.x, py = wpp.y;
     epx = px;
     epy = py;
@@ -1408,10 +1525,10 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   u32 tk, td, ta, tq;
   u64 jk, jd, ja, jq;
   if constexpr (kBlockRes)
-    block_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+    block_reserve4(x.qctr, (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
                    (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
   else
-    wave_reserve4(&c->npool[1 - p], (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+    wave_reserve4(x.qctr, (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
                   (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
   auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
     if (toq) {
@@ -1510,7 +1627,8 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const bool active = c->active != 0;
   const u64 n_in = hop <= 1 ? c->nsel : c->nhop[hop - 1];
   const u64 N = active ? min(n_in, (u64)a.cap) : 0;
-  const Pool Q = a.pool[1 - p];
+  const u64 pout = c->pout;
+  const Pool Q = pout ? a.pool[1] : a.pool[0];
   // children hop on when they pass the round's selection test; a strided
   // round has no key test, so its children wait for the next round
   const bool to_hop = hop < a.hops && c->smode == 0;
@@ -1521,7 +1639,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const bool all = c->sel_all;
   const bool tab = c->use_table;
   const double cv = c->cutval;
-  const PropCtx x{Q, a.ev[p], sh, T, all, tab, cv};
+  const PropCtx x{Q, &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
   if (t0 == 0 && active) {
     if (hop <= 1)
       c->cnt[C_SEL] = n_in;
@@ -1539,7 +1657,7 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
       wsk = S.sk[i];
       wes = S.es[i];
     }
-    prop_window<false>(a, p, x, have, wbb, wpp, wsk, wes, to_hop, HQ, nq_ctr, (u64)a.cap, acc);
+    prop_window<false, Pool>(a, p, x, have, wbb, wpp, wsk, wes, to_hop, HQ, nq_ctr, (u64)a.cap, acc);
   }
   prop_finish(a, p, acc);
 }
@@ -1600,21 +1718,25 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int ho
 constexpr int kFuseHops = 6;          // hops that one fused launch carries
 constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
 
-// All hops of a round in one launch (hops <= kFuseHops). Each workgroup
-// propagates its share of the selected windows and, depth first, the
-// children that pass the round's selection test, from per-hop lists in LDS:
-// every step takes up to kBlock windows from the deepest non-empty list (its
-// next chunk of the selection when all lists are empty) and appends their
-// hopping children to the next hop's list. A list is filled only while every
-// deeper list is empty, from at most kBlock windows, so it never holds more
-// than 2 * kBlock. Every window propagates at the hop it would reach with one
-// launch per hop, against the same round-start values, so the round's
-// windows, events and counts are the same; hops - 1 launches and their ramps
-// are saved per round.
+// All hops of a round in one launch (hops <= NL + 1 <= kFuseHops). Each
+// workgroup propagates its share of the selected windows and, depth first,
+// the children that pass the round's selection test, from NL per-hop lists in
+// LDS: every step takes up to kBlock windows from the deepest non-empty list
+// (its next chunk of the selection when all lists are empty) and appends
+// their hopping children to the next hop's list. A list is filled only while
+// every deeper list is empty, from at most kBlock windows, so it never holds
+// more than 2 * kBlock. Every window propagates at the hop it would reach
+// with one launch per hop, against the same round-start values, so the
+// round's windows, events and counts are the same; hops - 1 launches and
+// their ramps are saved per round. The lists take NL * 24 KiB of LDS, so
+// fewer hops leave room for more workgroups per compute unit.
+template <int NL>
 __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) {
-  __shared__ double2 l_bb[kFuseHops - 1][kFuseCap], l_pp[kFuseHops - 1][kFuseCap], l_sk[kFuseHops - 1][kFuseCap];
-  __shared__ int2 l_es[kFuseHops - 1][kFuseCap];
-  __shared__ u64 l_n[kFuseHops + 1];  // l_n[h]: windows in the list of hop h (h >= 2)
+  __shared__ double2 l_bb[NL][kFuseCap], l_pp[NL][kFuseCap];
+  __shared__ double l_sg[NL][kFuseCap];
+  __shared__ int2 l_es[NL][kFuseCap];
+  __shared__ u64 l_n[NL + 2];  // l_n[h]: windows in the list of hop h (h >= 2)
+  constexpr int kTop = NL + 1;  // the deepest hop
   Ctl* c = a.ctl;
   const u64 t0 = blockIdx.x * (u64)kBlock + threadIdx.x, stride = (u64)gridDim.x * kBlock;
   const Pool S = a.org_shift >= 0 ? a.sorted : a.sel;
@@ -1627,7 +1749,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
     f_sk = S.sk[t0];
     f_es = S.es[t0];
   }
-  if (threadIdx.x <= (unsigned)kFuseHops) l_n[threadIdx.x] = 0;
+  if (threadIdx.x <= (unsigned)kTop) l_n[threadIdx.x] = 0;
   const bool active = c->active != 0;
   const u64 n_in = c->nsel;
   const u64 N = active ? min(n_in, (u64)a.cap) : 0;
@@ -1638,7 +1760,9 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
   const bool all = c->sel_all;
   const bool tab = c->use_table;
   const double cv = c->cutval;
-  const PropCtx x{a.pool[1 - p], a.ev[p], sh, T, all, tab, cv};
+  const u64 pout = c->pout;
+  const PropCtx x{pout ? a.pool[1] : a.pool[0], &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
+  const int hops = a.hops < kTop ? a.hops : kTop;
   if (t0 == 0 && active) atomicAdd(&c->cnt[C_SEL], n_in);
   __syncthreads();
   PropAcc acc;
@@ -1668,7 +1792,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
         const u64 j = n - take + threadIdx.x;
         wbb = l_bb[lvl - 2][j];
         wpp = l_pp[lvl - 2][j];
-        wsk = l_sk[lvl - 2][j];
+        wsk = make_double2(l_sg[lvl - 2][j], 0.0);
         wes = l_es[lvl - 2][j];
       }
       __syncthreads();  // every thread has its window before the list shrinks
@@ -1677,17 +1801,139 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
         hopped += take;
       }
     }
-    const int nl = lvl < kFuseHops ? lvl + 1 : kFuseHops;
-    const Pool HQ{l_bb[nl - 2], l_pp[nl - 2], l_sk[nl - 2], l_es[nl - 2]};
-    prop_window<true>(a, p, x, have, wbb, wpp, wsk, wes, hop_ok && lvl < a.hops, HQ, &l_n[nl], (u64)kFuseCap, acc);
+    const int nl = lvl < kTop ? lvl + 1 : kTop;
+    const HopList HQ{l_bb[nl - 2], l_pp[nl - 2], l_sg[nl - 2], l_es[nl - 2]};
+    prop_window<true, HopList>(a, p, x, have, wbb, wpp, wsk, wes, hop_ok && lvl < hops, HQ, &l_n[nl],
+                               (u64)kFuseCap, acc);
     __syncthreads();  // the next list and its length are visible
-    if (lvl < a.hops && l_n[lvl + 1] != 0) {
+    if (lvl < hops && l_n[lvl + 1] != 0) {
       ++lvl;
     } else {
       while (lvl > 1 && l_n[lvl] == 0) --lvl;
     }
   }
   if (threadIdx.x == 0 && hopped != 0) atomicAdd(&c->cnt[C_SEL], hopped);
+  prop_finish(a, p, acc);
+}
+
+// Selection and propagation in one launch (hops <= NL + 1): the workgroups
+// scan the pool as the partition does (stale windows dropped, the kept ones
+// left in place or compacted into the other buffer) and propagate each
+// selected window in the same step, without a selection buffer; the hopping
+// children then go depth first through the LDS lists as in
+// k_propagate_fused. The selected windows, their order aside, and every
+// count are those of the partition followed by the propagation, against the
+// same round-start values.
+template <int NL>
+__global__ void __launch_bounds__(kBlock) k_select_propagate(RoundArgs a, int p) {
+  __shared__ double2 l_bb[NL][kFuseCap], l_pp[NL][kFuseCap];
+  __shared__ double l_sg[NL][kFuseCap];
+  __shared__ int2 l_es[NL][kFuseCap];
+  __shared__ u64 l_n[NL + 2];  // l_n[h]: windows in the list of hop h (h >= 2)
+  constexpr int kTop = NL + 1;  // the deepest hop
+  Ctl* c = a.ctl;
+  if (threadIdx.x <= (unsigned)kTop) l_n[threadIdx.x] = 0;
+  const bool active = c->active != 0;
+  const u64 pin = c->pin, pout = c->pout;
+  const u64 N = active ? min(c->nscan, (u64)a.cap) : 0;
+  const int sh = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
+  const bool inplace = pin == pout;
+  const Pool P = pin ? a.pool[1] : a.pool[0];
+  const PropCtx x{pout ? a.pool[1] : a.pool[0], &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
+  const int hops = a.hops < kTop ? a.hops : kTop;
+  __syncthreads();
+  PropAcc acc;
+  u32 stale_n = 0, kept_in = 0, n_sel = 0;
+  const u64 stride = (u64)gridDim.x * kBlock;
+  u64 base = blockIdx.x * (u64)kBlock;  // the workgroup's next chunk of the pool
+  u64 hopped = 0;                       // windows taken from the lists (thread 0)
+  int lvl = 1;                          // hop of the next step (the same in every thread)
+  for (;;) {
+    bool have = false;
+    double2 wbb = make_double2(0.0, 0.0), wpp = wbb, wsk = wbb;
+    int2 wes = make_int2(0, 0);
+    if (lvl == 1) {
+      if (base >= N) break;
+      const u64 i = base + threadIdx.x;
+      base += stride;
+      bool keep = false, gone = false;
+      if (i < N) {
+        // the whole slot in one batch of loads (a tombstone's other fields
+        // are read but not used)
+        wsk = P.sk[i];
+        wes = P.es[i];
+        wbb = P.bb[i];
+        wpp = P.pp[i];
+        if (bits(wsk.y) != kDead) {
+          const bool stale = !idx_ok(c, wes.y, a.m.nv) || wsk.x > from_bits(lda(&a.s.g[wes.y]));
+          if (stale) {
+            stale_n++;
+            gone = true;
+          } else {
+            have = tab ? (wsk.y <= cv) : (all || ((bits(wsk.y) >> sh) <= T));
+            keep = !have;
+          }
+        }
+      }
+      if (have) n_sel++;
+      if (inplace) {
+        if (have || gone) reinterpret_cast<double*>(P.sk)[2 * i + 1] = from_bits(kDead);
+        if (keep) kept_in++;
+      } else {
+        u64 jk, j1, j2;
+        u32 tk, t1, t2;
+        wave_reserve3(x.qctr, keep ? 1u : 0u, x.qctr, 0u, x.qctr, 0u, jk, j1, j2, tk, t1, t2);
+        if (keep) {
+          if (jk < (u64)a.cap)
+            store_window(x.Q, jk, wbb.x, wbb.y, wpp.x, wpp.y, wsk.x, wsk.y, wes.x, wes.y);
+          else
+            flag_overflow(c);
+        }
+      }
+      if (keep) {
+        const u64 kb = bits(wsk.y);
+        acc.kmn = kb < acc.kmn ? kb : acc.kmn;
+        acc.kmx = kb > acc.kmx ? kb : acc.kmx;
+      }
+    } else {
+      const u64 n = l_n[lvl];
+      const u64 take = n < (u64)kBlock ? n : (u64)kBlock;
+      have = threadIdx.x < take;
+      if (have) {
+        const u64 j = n - take + threadIdx.x;
+        wbb = l_bb[lvl - 2][j];
+        wpp = l_pp[lvl - 2][j];
+        wsk = make_double2(l_sg[lvl - 2][j], 0.0);
+        wes = l_es[lvl - 2][j];
+      }
+      __syncthreads();  // every thread has its window before the list shrinks
+      if (threadIdx.x == 0) {
+        l_n[lvl] = n - take;
+        hopped += take;
+      }
+    }
+    const int nl = lvl < kTop ? lvl + 1 : kTop;
+    const HopList HQ{l_bb[nl - 2], l_pp[nl - 2], l_sg[nl - 2], l_es[nl - 2]};
+    prop_window<true, HopList>(a, p, x, have, wbb, wpp, wsk, wes, lvl < hops, HQ, &l_n[nl], (u64)kFuseCap, acc);
+    __syncthreads();  // the next list and its length are visible
+    if (lvl < hops && l_n[lvl + 1] != 0) {
+      ++lvl;
+    } else {
+      while (lvl > 1 && l_n[lvl] == 0) --lvl;
+    }
+  }
+  u32 tot[3] = {stale_n, kept_in, n_sel};
+  u64 z0 = kAllOnes, z1 = 0;
+  block_totals(z0, z1, tot);
+  if (threadIdx.x == 0) {
+    if (tot[0] && a.counts) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
+    if (tot[1]) atomicAdd(&c->keptin, (u64)tot[1]);
+    if (tot[2] + hopped) atomicAdd(&c->cnt[C_SEL], (u64)tot[2] + hopped);
+  }
   prop_finish(a, p, acc);
 }
 
@@ -1727,11 +1973,12 @@ __device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u6
   for (u64 i = t0; i < nd; i += stride) {
     const int32_t v = i == t0 ? f.vq.x : a.ev[p].vq[i].x;
     const double d = i == t0 ? f.d : a.ev[p].d[i];
-    atomicMin(&a.s.g[v], bits(d));
+    if (idx_ok(c, v, a.m.nv)) atomicMin(&a.s.g[v], bits(d));
   }
   for (u64 i = t0; i < na; i += stride) {
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
+    if (!idx_ok(c, e, a.m.nh)) continue;
     // a corner whose apex distance improves forgets its old crossing (the
     // crossings are only compared in the next pass)
     if (atomicMin(&a.s.as[e].D, bits(D)) > bits(D)) a.s.as[e].X = kAllOnes;
@@ -1757,14 +2004,14 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
     const double X = i == t0 ? f.X : a.aev.X[i];
-    if (bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
+    if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
   }
   for (u64 i = t0; i < nd; i += stride) {
     const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
     const double d = i == t0 ? f.d : a.ev[p].d[i];
     const double2 xy = i == t0 ? f.xy : a.ev[p].xy[i];
     const int32_t v = vq.x;
-    const bool win = bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO);
+    const bool win = idx_ok(c, v, a.m.nv) && bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO);
     double th = 0.0;
     if (win) {
       // the incoming angle of an event that wins a pseudo-source vertex
@@ -1816,6 +2063,7 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ncand, (u64)a.ecap) : 0;
   const u32 stamp = (u32)c->round;
+  const int po = (int)(c->pout & 1);
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
@@ -1833,19 +2081,22 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
         d = a.cand.d[i];
         th = a.cand.xy[i].x;
       }
+      const bool okv = idx_ok(c, v, a.m.nv);
+      if (!okv) v = 0;
       // everything that depends on v only, in one batch of loads
       const u64 gv = lda(&a.s.g[v]);
       const u64 fv = lda(&a.s.fanth[v]);
       const uint8_t fl = a.m.flags[v];
       q0 = a.m.coff[v];
       q1 = a.m.coff[v + 1];
-      if (bits(d) == gv && (fl & pch::VF_PSEUDO) && ordkey(th) == fv && atomicMax(&a.s.claim[v], stamp) < stamp) {
+      if (okv && bits(d) == gv && (fl & pch::VF_PSEUDO) && ordkey(th) == fv &&
+          atomicMax(&a.s.claim[v], stamp) < stamp) {
         a.s.fanth[v] = kAllOnes;
         has = true;
         fans++;
       }
     }
-    wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
+    wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, po, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
   }
   u32 tot[5] = {kept, tiny, ich, fans, notwin};
   block_totals(kmn, kmx, tot);
@@ -1928,6 +2179,10 @@ struct BatchDev {
   int32_t n_store;   // workgroups with buffers of their own; the others only help
   u64 wait;          // longest wait of a gang member, wall-clock ticks
   int64_t max_rounds;
+  int32_t mode;       // PCH_SELECT_DELTA or PCH_SELECT_LEARNED
+  const u32* cdf;     // LEARNED: [n_fields][kCdfBins + 1] predicted-distance tables
+  const double* pbin; // LEARNED: [n_fields] bin widths
+  double w0;
 };
 
 // status, rounds, processed, created, fans, peak pool, stale, leader time,
@@ -1940,8 +2195,21 @@ constexpr int kMaxGang = 32;   // workgroups on one field
 // 100 MHz wall clock (2 s): far above any round, so it only ends a wait that
 // cannot end.
 constexpr u64 kGangWait = 200000000ull;
-// field status before a workgroup finishes it (the host reruns such fields)
-constexpr int64_t kFieldNotRun = 4;
+// Status of a batched field (the first field_stats column). The host reruns
+// every field whose status is not PCH_FIELD_OK through pch_geodesic with the
+// same rule, which either finishes it (a larger pool, no gang) or returns the
+// error (non-finite geometry, an index outside the mesh).
+__host__ __device__ __forceinline__ int64_t field_status(bool ok, bool overflow, bool over_rounds, bool nonfinite,
+                                                         bool badidx) {
+  if (badidx) return PCH_FIELD_BAD_INDEX;
+  if (nonfinite) return PCH_FIELD_NONFINITE;
+  if (!ok) return PCH_FIELD_ABANDONED;
+  if (overflow) return PCH_FIELD_OVERFLOW;
+  if (over_rounds) return PCH_FIELD_MAX_ROUNDS;
+  return PCH_FIELD_OK;
+}
+// field status before a workgroup finishes it
+constexpr int64_t kFieldNotRun = PCH_FIELD_NOT_RUN;
 
 // The workgroups that share one field: the leader (the workgroup that took
 // the field, whose buffers hold it) and the helpers of the same XCD that
@@ -2050,7 +2318,7 @@ __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, Round
   a.ecap = B.ecap;
   a.acap = B.acap;
   a.k = B.k;
-  a.mode = PCH_SELECT_DELTA;
+  a.mode = B.mode;
   a.eps = B.eps;
   a.ch_on = B.ch_on;
   a.ich_on = B.ich_on;
@@ -2058,9 +2326,10 @@ __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, Round
   a.retest = B.retest;
   a.table = nullptr;
   a.n_table = 0;
-  a.cdf = nullptr;
-  a.pbin = 0.0;
-  a.w0 = 4.0;
+  const bool learned = B.mode == PCH_SELECT_LEARNED;
+  a.cdf = learned ? B.cdf + (int64_t)f * (kCdfBins + 1) : nullptr;
+  a.pbin = learned ? B.pbin[f] : 0.0;
+  a.w0 = B.w0;
   a.counts = 1;
 }
 
@@ -2078,8 +2347,8 @@ __device__ __forceinline__ void init_fan(const RoundArgs& a, int v, Ctl* ctl) {
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0;
   const int q0 = a.m.coff[v];
-  wave_fans(a, lane_id() == 0, v, q0, a.m.coff[v + 1] - q0, 0.0, 0.0, true, 0, kmn, kmx, kept, tiny, ich, defer,
-            notwin);
+  wave_fans(a, lane_id() == 0, v, q0, a.m.coff[v + 1] - q0, 0.0, 0.0, true, 0, 0, kmn, kmx, kept, tiny, ich,
+            defer, notwin);
   kmn = wave_min64(kmn);
   kmx = wave_max64(kmx);
   if (lane_id() == 0) {
@@ -2314,6 +2583,7 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
       for (size_t w = 0; w < sizeof(Ctl) / sizeof(u64); ++w) cw[w] = 0;
       lctl.kmin[0] = lctl.kmin[1] = kAllOnes;
       lctl.delta = B.mesh_delta0[mi];
+      lctl.lfac = 1.0;
       s_slot = -1;
       s_stop = 0;
       if (R) {
@@ -2416,7 +2686,8 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     if (threadIdx.x == 0) {
       int64_t* st = B.fstat + (int64_t)f * kFieldStat;
       const u64 rounds = ld(&c->round);
-      st[0] = !ok ? 3 : (ld(&c->overflow) ? 1 : ((int64_t)rounds > B.max_rounds ? 2 : 0));
+      st[0] = field_status(ok, ld(&c->overflow) != 0, (int64_t)rounds > B.max_rounds, ld(&c->nonfinite) != 0,
+                           ld(&c->badidx) != 0);
       st[1] = (int64_t)rounds;
       st[2] = (int64_t)ld(&c->tot[C_SEL]);
       st[3] = (int64_t)(ld(&c->tot[C_KIDS]) + ld(&c->tot[C_FANWIN]));
@@ -2485,6 +2756,27 @@ int pch::set_error(int s, const std::string& msg) {
 // host side
 // ---------------------------------------------------------------------------
 
+// The work buffers of one field: window pools, selection, hop queues, events,
+// and the per-call tables (sources, cutoff table, predicted-distance table,
+// round log). pch_geodesic keeps them in the mesh handle and grows them on
+// demand; carve_work lays them out in a fixed device arena instead.
+struct WorkBufs {
+  int64_t cap = 0, ecap = 0, acap = 0;
+  Pool pool[2] = {};
+  Pool sel = {};
+  Pool hq[2] = {};
+  Pool sorted = {};
+  u32 *org_hist = nullptr, *org_ofs = nullptr;
+  DistEv ev[2] = {};
+  DistEv cand = {};
+  AngEv aev = {};
+  int32_t* dsrc = nullptr;
+  double* dtable = nullptr;
+  u32* dcdf = nullptr;  // [kCdfBins + 4]: histogram / cdf, the maximum, a pad word, the bin width
+  int64_t* dlog = nullptr;
+  int64_t dlog_cap = 0;
+};
+
 struct pch_mesh_s {
   pch::HostMesh host;
   int device = 0;
@@ -2498,27 +2790,17 @@ struct pch_mesh_s {
   u64 *g = nullptr, *fanth = nullptr;
   Split* as = nullptr;
   u32* claim = nullptr;
-  // work buffers (grow on demand)
-  int64_t cap = 0, ecap = 0, acap = 0;
-  Pool pool[2] = {};
-  Pool sel = {};
-  Pool hq[2] = {};
-  int64_t hq_cap = 0;
-  Pool sorted = {};
-  int64_t sorted_cap = 0;
-  u32 *org_hist = nullptr, *org_ofs = nullptr;
-  DistEv ev[2] = {};
-  DistEv cand = {};
-  AngEv aev = {};
   Ctl* ctl = nullptr;
   u32* hist = nullptr;
-  int32_t* dsrc = nullptr;
-  int64_t dsrc_cap = 0;
-  double* dtable = nullptr;
-  int64_t dtable_cap = 0;
-  u32* dcdf = nullptr;  // [kCdfBins + 1]: histogram / cdf, then the maximum
-  int64_t* dlog = nullptr;
-  int64_t dlog_cap = 0;
+  // a captured graph of rounds_per_sync rounds, replayed while its launch
+  // arguments stay the same
+  hipGraphExec_t rg_exec = nullptr;
+  hipStream_t rg_stream = nullptr;
+  RoundArgs rg_args{};
+  int rg_key[6] = {};
+  // work buffers (grow on demand)
+  WorkBufs w;
+  int64_t hq_cap = 0, sorted_cap = 0, dsrc_cap = 0, dtable_cap = 0;
   std::vector<int64_t> last_log;
   int64_t last_rounds = 0;
 };
@@ -2553,62 +2835,127 @@ hipError_t alloc_pool(Pool& P, int64_t n) {
 
 void free_work(pch_mesh_s* M) {
   for (int i = 0; i < 2; ++i) {
-    free_pool(M->pool[i]);
-    (void)hipFree(M->ev[i].vq);
-    (void)hipFree(M->ev[i].d);
-    (void)hipFree(M->ev[i].xy);
-    M->ev[i] = DistEv{};
+    free_pool(M->w.pool[i]);
+    (void)hipFree(M->w.ev[i].vq);
+    (void)hipFree(M->w.ev[i].d);
+    (void)hipFree(M->w.ev[i].xy);
+    M->w.ev[i] = DistEv{};
   }
-  (void)hipFree(M->cand.vq);
-  (void)hipFree(M->cand.d);
-  (void)hipFree(M->cand.xy);
-  M->cand = DistEv{};
-  free_pool(M->sel);
-  free_pool(M->hq[0]);
-  free_pool(M->hq[1]);
+  (void)hipFree(M->w.cand.vq);
+  (void)hipFree(M->w.cand.d);
+  (void)hipFree(M->w.cand.xy);
+  M->w.cand = DistEv{};
+  free_pool(M->w.sel);
+  free_pool(M->w.hq[0]);
+  free_pool(M->w.hq[1]);
   M->hq_cap = 0;
-  free_pool(M->sorted);
+  free_pool(M->w.sorted);
   M->sorted_cap = 0;
-  (void)hipFree(M->aev.e);
-  (void)hipFree(M->aev.D);
-  (void)hipFree(M->aev.X);
-  M->aev = AngEv{};
-  M->cap = M->ecap = M->acap = 0;
+  (void)hipFree(M->w.aev.e);
+  (void)hipFree(M->w.aev.D);
+  (void)hipFree(M->w.aev.X);
+  M->w.aev = AngEv{};
+  M->w.cap = M->w.ecap = M->w.acap = 0;
 }
 
 pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
-  if (cap <= M->cap && (!hop_queues || M->hq_cap >= M->cap)) return PCH_OK;
-  if (cap <= M->cap) {
+  if (cap <= M->w.cap && (!hop_queues || M->hq_cap >= M->w.cap)) return PCH_OK;
+  if (cap <= M->w.cap) {
     // the hop queues are allocated on first use
-    HIP_TRY(alloc_pool(M->hq[0], M->cap));
-    HIP_TRY(alloc_pool(M->hq[1], M->cap));
-    M->hq_cap = M->cap;
+    HIP_TRY(alloc_pool(M->w.hq[0], M->w.cap));
+    HIP_TRY(alloc_pool(M->w.hq[1], M->w.cap));
+    M->hq_cap = M->w.cap;
     return PCH_OK;
   }
   free_work(M);
   const int64_t ecap = 4 * cap, acap = cap;
   for (int i = 0; i < 2; ++i) {
-    HIP_TRY(alloc_pool(M->pool[i], cap));
-    HIP_TRY(dalloc(&M->ev[i].vq, ecap));
-    HIP_TRY(dalloc(&M->ev[i].d, ecap));
-    HIP_TRY(dalloc(&M->ev[i].xy, ecap));
+    HIP_TRY(alloc_pool(M->w.pool[i], cap));
+    HIP_TRY(dalloc(&M->w.ev[i].vq, ecap));
+    HIP_TRY(dalloc(&M->w.ev[i].d, ecap));
+    HIP_TRY(dalloc(&M->w.ev[i].xy, ecap));
   }
-  HIP_TRY(dalloc(&M->cand.vq, ecap));
-  HIP_TRY(dalloc(&M->cand.d, ecap));
-  HIP_TRY(dalloc(&M->cand.xy, ecap));
-  HIP_TRY(alloc_pool(M->sel, cap));
+  HIP_TRY(dalloc(&M->w.cand.vq, ecap));
+  HIP_TRY(dalloc(&M->w.cand.d, ecap));
+  HIP_TRY(dalloc(&M->w.cand.xy, ecap));
+  HIP_TRY(alloc_pool(M->w.sel, cap));
   if (hop_queues) {
-    HIP_TRY(alloc_pool(M->hq[0], cap));
-    HIP_TRY(alloc_pool(M->hq[1], cap));
+    HIP_TRY(alloc_pool(M->w.hq[0], cap));
+    HIP_TRY(alloc_pool(M->w.hq[1], cap));
     M->hq_cap = cap;
   }
-  HIP_TRY(dalloc(&M->aev.e, acap));
-  HIP_TRY(dalloc(&M->aev.D, acap));
-  HIP_TRY(dalloc(&M->aev.X, acap));
-  M->cap = cap;
-  M->ecap = ecap;
-  M->acap = acap;
+  HIP_TRY(dalloc(&M->w.aev.e, acap));
+  HIP_TRY(dalloc(&M->w.aev.D, acap));
+  HIP_TRY(dalloc(&M->w.aev.X, acap));
+  M->w.cap = cap;
+  M->w.ecap = ecap;
+  M->w.acap = acap;
   return PCH_OK;
+}
+
+// Device memory that a field's work buffers can be carved from.
+struct ScratchArena {
+  char* base;
+  size_t bytes;
+};
+
+// Lays out the work buffers of one field with pool capacity cap (and the
+// same event capacities as pch_geodesic) from base, each array 256-byte
+// aligned; returns the bytes they take. Assigns w only when they fit in avail.
+// The sources, cutoff table and predicted-distance table come first, so a
+// larger cap leaves them where they are.
+size_t carve_work(WorkBufs& w, char* base, size_t avail, int64_t cap, int64_t nsrc, int64_t ntable, bool cdf) {
+  const int64_t ecap = 4 * cap, acap = cap;
+  size_t at = 0;
+  auto take = [&](size_t n) {
+    const size_t o = at;
+    at += (n + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_src = take(sizeof(int32_t) * (size_t)kNoallocMaxSources);
+  const size_t o_tab = ntable > 0 ? take(sizeof(double) * ntable) : 0;
+  const size_t o_cdf = cdf ? take(sizeof(u32) * (kCdfBins + 4)) : 0;
+  (void)nsrc;
+  size_t o_pool[3][4], o_ev[3][3], o_ae[3];
+  for (auto& q : o_pool) {
+    q[0] = take(sizeof(double2) * cap);
+    q[1] = take(sizeof(double2) * cap);
+    q[2] = take(sizeof(double2) * cap);
+    q[3] = take(sizeof(int2) * cap);
+  }
+  for (auto& q : o_ev) {
+    q[0] = take(sizeof(int2) * ecap);
+    q[1] = take(sizeof(double) * ecap);
+    q[2] = take(sizeof(double2) * ecap);
+  }
+  o_ae[0] = take(sizeof(int32_t) * acap);
+  o_ae[1] = take(sizeof(double) * acap);
+  o_ae[2] = take(sizeof(double) * acap);
+  if (at > avail) return at;
+  auto pool_at = [&](const size_t* q) {
+    return Pool{reinterpret_cast<double2*>(base + q[0]), reinterpret_cast<double2*>(base + q[1]),
+                reinterpret_cast<double2*>(base + q[2]), reinterpret_cast<int2*>(base + q[3])};
+  };
+  auto ev_at = [&](const size_t* q) {
+    return DistEv{reinterpret_cast<int2*>(base + q[0]), reinterpret_cast<double*>(base + q[1]),
+                  reinterpret_cast<double2*>(base + q[2])};
+  };
+  w = WorkBufs{};
+  w.cap = cap;
+  w.ecap = ecap;
+  w.acap = acap;
+  w.pool[0] = pool_at(o_pool[0]);
+  w.pool[1] = pool_at(o_pool[1]);
+  w.sel = pool_at(o_pool[2]);
+  w.ev[0] = ev_at(o_ev[0]);
+  w.ev[1] = ev_at(o_ev[1]);
+  w.cand = ev_at(o_ev[2]);
+  w.aev = AngEv{reinterpret_cast<int32_t*>(base + o_ae[0]), reinterpret_cast<double*>(base + o_ae[1]),
+                reinterpret_cast<double*>(base + o_ae[2])};
+  w.dsrc = reinterpret_cast<int32_t*>(base + o_src);
+  w.dtable = ntable > 0 ? reinterpret_cast<double*>(base + o_tab) : nullptr;
+  w.dcdf = cdf ? reinterpret_cast<u32*>(base + o_cdf) : nullptr;
+  return at;
 }
 
 pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
@@ -2652,6 +2999,8 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
 }
 
 void free_mesh(pch_mesh_s* M) {
+  if (M->rg_exec) (void)hipGraphExecDestroy(M->rg_exec);
+  if (M->rg_stream) (void)hipStreamDestroy(M->rg_stream);
   free_work(M);
   (void)hipFree(M->hl);
   (void)hipFree(M->phi);
@@ -2669,12 +3018,12 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->claim);
   (void)hipFree(M->ctl);
   (void)hipFree(M->hist);
-  (void)hipFree(M->dsrc);
-  (void)hipFree(M->dtable);
-  (void)hipFree(M->dcdf);
-  (void)hipFree(M->dlog);
-  (void)hipFree(M->org_hist);
-  (void)hipFree(M->org_ofs);
+  (void)hipFree(M->w.dsrc);
+  (void)hipFree(M->w.dtable);
+  (void)hipFree(M->w.dcdf);
+  (void)hipFree(M->w.dlog);
+  (void)hipFree(M->w.org_hist);
+  (void)hipFree(M->w.org_ofs);
 }
 
 pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
@@ -2690,15 +3039,16 @@ pch_status finish_create(pch_mesh_s* M, void* stream, pch_mesh* out) {
   return PCH_OK;
 }
 
-RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
-  RoundArgs a;
-  a.m = DevMesh{M->hl, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+RoundArgs make_args(pch_mesh_s* M, const WorkBufs& w, const pch_options& o) {
+  RoundArgs a{};  // zeroed padding: captured round graphs compare arguments bytewise
+  a.m = DevMesh{M->hl,    M->phi,    M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff,
+                 M->corner, M->crec, (int32_t)M->host.nv, (int32_t)M->host.nh};
   a.s = DevState{M->g, M->as, M->fanth, M->claim};
-  a.pool[0] = M->pool[0];
-  a.pool[1] = M->pool[1];
-  a.sel = M->sel;
-  a.hq[0] = M->hq[0];
-  a.hq[1] = M->hq[1];
+  a.pool[0] = w.pool[0];
+  a.pool[1] = w.pool[1];
+  a.sel = w.sel;
+  a.hq[0] = w.hq[0];
+  a.hq[1] = w.hq[1];
   a.hops = o.hops;
   a.org_shift = -1;
   if (o.organize) {
@@ -2706,20 +3056,20 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
     while (((M->host.nh - 1) >> bitlen) > 0) ++bitlen;
     a.org_shift = bitlen > 12 ? bitlen - 12 : 0;  // (nh - 1) >> org_shift < kOrgBuckets
   }
-  a.sorted = M->sorted;
-  a.org_hist = M->org_hist;
-  a.org_ofs = M->org_ofs;
-  a.ev[0] = M->ev[0];
-  a.ev[1] = M->ev[1];
-  a.cand = M->cand;
-  a.aev = M->aev;
+  a.sorted = w.sorted;
+  a.org_hist = w.org_hist;
+  a.org_ofs = w.org_ofs;
+  a.ev[0] = w.ev[0];
+  a.ev[1] = w.ev[1];
+  a.cand = w.cand;
+  a.aev = w.aev;
   a.ctl = M->ctl;
   a.hist = M->hist;
-  a.log = o.collect_stats ? M->dlog : nullptr;
-  a.max_log = o.collect_stats ? M->dlog_cap : 0;
-  a.cap = M->cap;
-  a.ecap = M->ecap;
-  a.acap = M->acap;
+  a.log = o.collect_stats ? w.dlog : nullptr;
+  a.max_log = o.collect_stats ? w.dlog_cap : 0;
+  a.cap = w.cap;
+  a.ecap = w.ecap;
+  a.acap = w.acap;
   a.k = o.k;
   a.mode = o.select_mode;
   a.eps = o.eps_tiny;
@@ -2727,14 +3077,16 @@ RoundArgs make_args(pch_mesh_s* M, const pch_options& o) {
   a.ich_on = (o.filters & 2) != 0;
   a.full_fan = (o.filters & 4) != 0;
   a.retest = (o.filters & 8) != 0;
-  a.table = (o.select_mode == PCH_SELECT_TABLE) ? M->dtable : nullptr;
+  a.table = (o.select_mode == PCH_SELECT_TABLE) ? w.dtable : nullptr;
   a.n_table = (o.select_mode == PCH_SELECT_TABLE) ? o.n_cutoff : 0;
-  a.cdf = M->dcdf;
+  a.cdf = w.dcdf;
   a.pbin = 0.0;
   a.w0 = o.w0 > 0.0 ? o.w0 : 4.0;
   a.counts = (o.counts != 0 || o.collect_stats != 0) ? 1 : 0;
   return a;
 }
+
+constexpr int kRoundEvents = 5;  // timing events of one timed round
 
 int grid_for(int64_t work, int max_blocks) {
   int64_t b = (work + kBlock - 1) / kBlock;
@@ -2749,24 +3101,66 @@ int grid_for(int64_t work, int max_blocks) {
 // Grids: the pool scan uses pool_blocks; propagation is sized for about twice
 // k windows; event passes and histograms use few blocks because their work is
 // small and the last-block ticket serializes one atomic per block.
+// One fused propagation launch with the hop lists that a.hops needs.
+void launch_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) {
+  switch (a.hops <= 2 ? 1 : a.hops - 1) {
+    case 1: k_propagate_fused<1><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 2: k_propagate_fused<2><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 3: k_propagate_fused<3><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 4: k_propagate_fused<4><<<blocks, kBlock, 0, st>>>(a, p); break;
+    default: k_propagate_fused<5><<<blocks, kBlock, 0, st>>>(a, p); break;
+  }
+}
+
+// The pool scan and the propagation of all hops in one launch.
+void launch_select_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) {
+  switch (a.hops <= 2 ? 1 : a.hops - 1) {
+    case 1: k_select_propagate<1><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 2: k_select_propagate<2><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 3: k_select_propagate<3><<<blocks, kBlock, 0, st>>>(a, p); break;
+    case 4: k_select_propagate<4><<<blocks, kBlock, 0, st>>>(a, p); break;
+    default: k_select_propagate<5><<<blocks, kBlock, 0, st>>>(a, p); break;
+  }
+}
+
+// Round launch plan: kSplit = partition, then propagation (fused hops or one
+// launch per hop); kScanFused = the pool scan inside the fused propagation.
+enum RoundPlan { kSplit = 0, kScanFused = 1 };
+
 void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, int prop_blocks, bool kth, bool fused,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                   const hipEvent_t* ev = nullptr, RoundPlan plan = kSplit) {
+  // ev (optional): kRoundEvents events bracketing the phases: selection,
+  // organization, propagation, events
+  if (ev) (void)hipEventRecord(ev[0], st);
   if (kth)
     for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
+  if (plan == kScanFused) {
+    if (ev) (void)hipEventRecord(ev[1], st);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    launch_select_fused(a, p, st, pool_blocks);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+    k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+    k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+    if (ev) (void)hipEventRecord(ev[4], st);
+    return;
+  }
   k_partition<<<pool_blocks, kBlock, 0, st>>>(a, p);
+  if (ev) (void)hipEventRecord(ev[1], st);
   if (a.org_shift >= 0) {
     k_org_scan<<<1, 1024, 0, st>>>(a);
     k_org_scatter<<<prop_blocks, kBlock, 0, st>>>(a);
   }
-  if (ev0) (void)hipEventRecord(ev0, st);
+  if (ev) (void)hipEventRecord(ev[2], st);
   if (fused)
-    k_propagate_fused<<<prop_blocks, kBlock, 0, st>>>(a, p);
+    launch_fused(a, p, st, prop_blocks);
   else
     for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
-  if (ev1) (void)hipEventRecord(ev1, st);
+  if (ev) (void)hipEventRecord(ev[3], st);
   k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
+  if (ev) (void)hipEventRecord(ev[4], st);
 }
 
 }  // namespace
@@ -2778,6 +3172,19 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
 extern "C" {
 
 const char* pch_last_error(void) { return t_err.c_str(); }
+
+const char* pch_field_status_string(int64_t s) {
+  switch (s) {
+    case PCH_FIELD_OK: return "ok";
+    case PCH_FIELD_OVERFLOW: return "pool overflow (rerun)";
+    case PCH_FIELD_MAX_ROUNDS: return "round limit (rerun)";
+    case PCH_FIELD_ABANDONED: return "gang stopped waiting (rerun)";
+    case PCH_FIELD_NOT_RUN: return "not finished (rerun)";
+    case PCH_FIELD_NONFINITE: return "non-finite window geometry";
+    case PCH_FIELD_BAD_INDEX: return "index outside the mesh";
+  }
+  return "unknown field status";
+}
 
 const char* pch_status_string(pch_status s) {
   switch (s) {
@@ -2808,6 +3215,8 @@ void pch_options_default(pch_options* o) {
   o->hops = 1;
   o->counts = 1;
   o->fuse_hops = 1;
+  o->fuse_scan = 1;
+  o->round_graph = 0;
 }
 
 pch_status pch_mesh_create_from_lengths(const int32_t* faces, int64_t nf, int64_t nv, const double* he_len,
@@ -2868,8 +3277,11 @@ pch_status pch_round_log(pch_mesh M, int64_t* out, int64_t max_rounds, int64_t* 
   return PCH_OK;
 }
 
-pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
-                        const pch_options* opts, pch_stats* stats) {
+// Algorithm 1 on one mesh. sc == nullptr: the work buffers live in the mesh
+// handle and grow on demand (pch_geodesic); otherwise they are carved from
+// the arena and nothing is allocated.
+static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
+                                const pch_options* opts, pch_stats* stats, const ScratchArena* sc) {
   auto t_start = std::chrono::steady_clock::now();
   if (!M || !sources || !dist) return set_err(PCH_EINVAL, "null pointer argument");
   if (m < 1) return set_err(PCH_EINVAL, "need at least one source vertex");
@@ -2890,32 +3302,61 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   if (o.rounds_per_sync < 1) o.rounds_per_sync = 16;
   if (o.hops == 0) o.hops = 1;
   if (o.hops < 1 || o.hops > kMaxHops) return set_err(PCH_EINVAL, "hops must be in [1, 16]");
+  const bool fused_hops = o.fuse_hops != 0 && o.hops <= kFuseHops;
+  if (sc) {
+    if (m > kNoallocMaxSources) return set_err(PCH_EINVAL, "an arena run takes at most 1024 sources");
+    if (o.collect_timing || o.collect_stats || o.organize || (o.hops > 1 && !fused_hops))
+      return set_err(PCH_EINVAL,
+                     "an arena run does not take collect_timing, collect_stats, organize or unfused hops");
+  }
   const pch::HostMesh& H = M->host;
-  std::vector<int32_t> src(sources, sources + m);
-  for (int32_t s : src)
-    if (s < 0 || s >= H.nv) return set_err(PCH_EINVAL, "source vertex out of range");
-  std::sort(src.begin(), src.end());
-  src.erase(std::unique(src.begin(), src.end()), src.end());
+  // the sources, sorted and without duplicates (a stack array for up to
+  // kNoallocMaxSources of them)
+  int32_t src_small[kNoallocMaxSources];
+  std::vector<int32_t> src_big;
+  int32_t* src = src_small;
+  if (m > kNoallocMaxSources) {
+    src_big.assign(sources, sources + m);
+    src = src_big.data();
+  } else {
+    std::memcpy(src_small, sources, sizeof(int32_t) * (size_t)m);
+  }
+  for (int32_t i = 0; i < m; ++i)
+    if (src[i] < 0 || src[i] >= H.nv) return set_err(PCH_EINVAL, "source vertex out of range");
+  std::sort(src, src + m);
+  const int nsrc = (int)(std::unique(src, src + m) - src);
   hipStream_t st = (hipStream_t)hip_stream;
   int cur_dev = 0;
   HIP_TRY(hipGetDevice(&cur_dev));
   if (cur_dev != M->device) return set_err(PCH_EINVAL, "mesh was created on another device");
-
-  if ((int64_t)src.size() > M->dsrc_cap) {
-    (void)hipFree(M->dsrc);
-    M->dsrc = nullptr;
-    HIP_TRY(dalloc(&M->dsrc, (int64_t)src.size()));
-    M->dsrc_cap = (int64_t)src.size();
+  const bool use_table = o.select_mode == PCH_SELECT_TABLE && o.n_cutoff > 0;
+  int64_t cap = o.pool_capacity > 0 ? o.pool_capacity : std::max<int64_t>(1 << 18, 2 * H.nh);
+  if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
+  // the work buffers: the mesh's own, or carved from the arena
+  WorkBufs wl;
+  WorkBufs& w = sc ? wl : M->w;
+  if (sc) {
+    const size_t need = carve_work(wl, sc->base, sc->bytes, cap, nsrc, use_table ? o.n_cutoff : 0,
+                                   o.select_mode == PCH_SELECT_LEARNED);
+    if (need > sc->bytes)
+      return set_err(PCH_EOVERFLOW, "the field needs " + std::to_string(need >> 20) +
+                                        " MiB of work buffers, more than the arena of " +
+                                        std::to_string(sc->bytes >> 20) + " MiB");
+  } else if ((int64_t)nsrc > M->dsrc_cap) {
+    (void)hipFree(M->w.dsrc);
+    M->w.dsrc = nullptr;
+    HIP_TRY(dalloc(&M->w.dsrc, (int64_t)nsrc));
+    M->dsrc_cap = (int64_t)nsrc;
   }
-  HIP_TRY(hipMemcpyAsync(M->dsrc, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice, st));
-  if (o.select_mode == PCH_SELECT_TABLE && o.n_cutoff > 0) {
-    if (o.n_cutoff > M->dtable_cap) {
-      (void)hipFree(M->dtable);
-      M->dtable = nullptr;
-      HIP_TRY(dalloc(&M->dtable, o.n_cutoff));
+  HIP_TRY(hipMemcpyAsync(w.dsrc, src, sizeof(int32_t) * (size_t)nsrc, hipMemcpyHostToDevice, st));
+  if (use_table) {
+    if (!sc && o.n_cutoff > M->dtable_cap) {
+      (void)hipFree(M->w.dtable);
+      M->w.dtable = nullptr;
+      HIP_TRY(dalloc(&M->w.dtable, o.n_cutoff));
       M->dtable_cap = o.n_cutoff;
     }
-    HIP_TRY(hipMemcpyAsync(M->dtable, o.cutoff_table, sizeof(double) * o.n_cutoff, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.dtable, o.cutoff_table, sizeof(double) * o.n_cutoff, hipMemcpyHostToDevice, st));
   }
   double delta0 = o.delta0;
   if (delta0 == 0.0) {
@@ -2925,34 +3366,27 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   }
   double pbin = 0.0;
   if (o.select_mode == PCH_SELECT_LEARNED) {
-    if (!M->dcdf) HIP_TRY(dalloc(&M->dcdf, kCdfBins + 1));
-    k_fill_u32<<<64, kBlock, 0, st>>>(M->dcdf, kCdfBins + 1, 0u);
-    k_pred_max<<<256, kBlock, 0, st>>>(o.predicted, H.nv, M->dcdf + kCdfBins);
-    k_pred_hist<<<1024, kBlock, 0, st>>>(o.predicted, H.nv, M->dcdf + kCdfBins, M->dcdf);
-    k_pred_scan<<<1, 1024, 0, st>>>(M->dcdf);
-    u32 mxb = 0;
-    HIP_TRY(hipMemcpyAsync(&mxb, M->dcdf + kCdfBins, sizeof(u32), hipMemcpyDeviceToHost, st));
+    // the table (kCdfBins + 1 words), a pad word, then the bin width (8-byte aligned)
+    if (!w.dcdf) HIP_TRY(dalloc(&M->w.dcdf, kCdfBins + 4));
+    double* dpbin = reinterpret_cast<double*>(w.dcdf + kCdfBins + 2);
+    enqueue_pred_cdf(PredFields{o.predicted, nullptr, nullptr, H.nv, 1, w.dcdf, dpbin}, st);
+    HIP_TRY(hipMemcpyAsync(&pbin, dpbin, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    float mx;
-    std::memcpy(&mx, &mxb, sizeof(mx));
-    pbin = (double)mx * 1.000001 / (double)kCdfBins;
     if (!(pbin > 0.0)) return set_err(PCH_EINVAL, "predicted distances must be positive");
   }
-  int64_t cap = o.pool_capacity > 0 ? o.pool_capacity : std::max<int64_t>(1 << 18, 2 * H.nh);
-  if (o.pool_limit > 0 && cap > o.pool_limit) cap = o.pool_limit;
   const int64_t log_rounds = 1 << 18;
-  if (o.collect_stats && M->dlog_cap < log_rounds) {
-    (void)hipFree(M->dlog);
-    M->dlog = nullptr;
-    HIP_TRY(dalloc(&M->dlog, log_rounds * C_NUM));
-    M->dlog_cap = log_rounds;
+  if (o.collect_stats && M->w.dlog_cap < log_rounds) {
+    (void)hipFree(M->w.dlog);
+    M->w.dlog = nullptr;
+    HIP_TRY(dalloc(&M->w.dlog, log_rounds * C_NUM));
+    M->w.dlog_cap = log_rounds;
   }
   int64_t restarts = 0;
   Ctl host_ctl, ctl_init;
   // optional per-launch timing of the propagation kernel
   std::vector<hipEvent_t> tev;
-  if (o.collect_timing) {
-    tev.resize(2 * (size_t)o.rounds_per_sync);
+  if (o.collect_timing) {  // never with the arena (rejected above)
+    tev.resize(kRoundEvents * (size_t)o.rounds_per_sync);
     for (auto& e : tev) HIP_TRY(hipEventCreate(&e));
   }
   struct EvGuard {
@@ -2961,24 +3395,31 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
       for (auto e : v) (void)hipEventDestroy(e);
     }
   } ev_guard{tev};
-  double prop_ms = 0.0;
-  int64_t prop_n = 0;
+  int64_t prop_n = 0, timed_rounds = 0;
+  double phase_ms[4] = {0.0, 0.0, 0.0, 0.0};
   for (;;) {
     // the hop queues in device memory serve only one launch per hop (fused
     // hops keep their windows in LDS)
-    pch_status s = ensure_work(M, cap, o.hops > 1 && !(o.fuse_hops != 0 && o.hops <= kFuseHops));
-    if (s != PCH_OK) return s;
-    if (o.organize && M->sorted_cap < M->cap) {
-      free_pool(M->sorted);
-      HIP_TRY(alloc_pool(M->sorted, M->cap));
-      M->sorted_cap = M->cap;
-      if (!M->org_hist) {
-        HIP_TRY(dalloc(&M->org_hist, kOrgBuckets));
-        HIP_TRY(dalloc(&M->org_ofs, kOrgBuckets));
-        HIP_TRY(hipMemsetAsync(M->org_hist, 0, sizeof(u32) * kOrgBuckets, st));
+    if (sc) {
+      // a restart with a larger pool stays inside the arena or fails
+      const size_t need = carve_work(wl, sc->base, sc->bytes, cap, nsrc, use_table ? o.n_cutoff : 0,
+                                     o.select_mode == PCH_SELECT_LEARNED);
+      if (need > sc->bytes) return set_err(PCH_EOVERFLOW, "window pool outgrew the arena");
+    } else {
+      pch_status s = ensure_work(M, cap, o.hops > 1 && !fused_hops);
+      if (s != PCH_OK) return s;
+    }
+    if (!sc && o.organize && M->sorted_cap < M->w.cap) {
+      free_pool(M->w.sorted);
+      HIP_TRY(alloc_pool(M->w.sorted, M->w.cap));
+      M->sorted_cap = M->w.cap;
+      if (!M->w.org_hist) {
+        HIP_TRY(dalloc(&M->w.org_hist, kOrgBuckets));
+        HIP_TRY(dalloc(&M->w.org_ofs, kOrgBuckets));
+        HIP_TRY(hipMemsetAsync(M->w.org_hist, 0, sizeof(u32) * kOrgBuckets, st));
       }
     }
-    RoundArgs a = make_args(M, o);
+    RoundArgs a = make_args(M, w, o);
     a.pbin = pbin;
     const int fill_blocks = 1024;
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->g, H.nv, bits_host(INFINITY));
@@ -2990,34 +3431,65 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     ctl_init.delta = delta0;
     ctl_init.lfac = 1.0;
     HIP_TRY(hipMemcpyAsync(M->ctl, &ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    const int nsrc = (int)src.size();
-    k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->dsrc, nsrc);
-    k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, M->dsrc, nsrc);
+    k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, w.dsrc, nsrc);
+    k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, w.dsrc, nsrc);
     k_begin<<<1, kWave, 0, st>>>(a, 0);
     HIP_TRY(hipGetLastError());
     // the pool scan is sized from the largest pool seen so far (twice it, at
     // least 2k windows); its grid-stride loop covers any larger pool
     int pool_blocks = grid_for(std::max<int64_t>(2 * o.k, (int64_t)1 << 16), 1024);
     const int prop_blocks = grid_for(std::max<int64_t>(2 * o.k, 1), 2048);
-    const bool fused = o.fuse_hops != 0 && o.hops <= kFuseHops;
-    const bool kth = o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_STRIDED;
+    const bool fused = fused_hops;
+    // the histogram passes serve the k-th-key rule (and a cutoff table's
+    // rounds after the table); the other rules set their cutoff in the set-up
+    const bool kth = o.select_mode == PCH_SELECT_KTH || o.select_mode == PCH_SELECT_TABLE;
     // the strided selection runs the pool scan on k threads (whole
     // workgroups): each selects the nearest of its windows
     const bool strided = o.select_mode == PCH_SELECT_STRIDED;
     if (strided) pool_blocks = grid_for(o.k, 1 << 30);
+    // the pool scan runs inside the fused propagation unless the round needs
+    // the whole selection first (strided selection, grouping by edge)
+    const RoundPlan plan = (fused && o.fuse_scan != 0 && !strided && !o.organize) ? kScanFused : kSplit;
     int p = 0;
     bool overflow = false;
-    prop_ms = 0.0;
+    for (double& x : phase_ms) x = 0.0;
     prop_n = 0;
+    timed_rounds = 0;
     u64 rounds_before = 0;
+    // rounds_per_sync rounds from a captured graph: only without timing
+    // events, with an even chunk (every chunk starts at parity 0), and not in
+    // an arena run (instantiating a graph allocates)
+    const bool graph = o.round_graph != 0 && !o.collect_timing && o.rounds_per_sync % 2 == 0 && !sc;
     for (;;) {
-      for (int r = 0; r < o.rounds_per_sync; ++r) {
-        const bool timed = o.collect_timing && ((rounds_before + (u64)r) % (u64)o.collect_timing == 0);
-        if (timed)
-          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused, tev[2 * r], tev[2 * r + 1]);
-        else
-          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused);
-        p ^= 1;
+      if (graph) {
+        const int key[6] = {pool_blocks, prop_blocks, kth ? 1 : 0, fused ? 1 : 0, (int)plan, o.rounds_per_sync};
+        if (!M->rg_exec || std::memcmp(key, M->rg_key, sizeof key) != 0 ||
+            std::memcmp(&a, &M->rg_args, sizeof a) != 0) {
+          if (M->rg_exec) (void)hipGraphExecDestroy(M->rg_exec);
+          M->rg_exec = nullptr;
+          if (!M->rg_stream) HIP_TRY(hipStreamCreateWithFlags(&M->rg_stream, hipStreamNonBlocking));
+          hipGraph_t gr;
+          HIP_TRY(hipStreamBeginCapture(M->rg_stream, hipStreamCaptureModeThreadLocal));
+          for (int r = 0; r < o.rounds_per_sync; ++r)
+            enqueue_round(a, r & 1, M->rg_stream, pool_blocks, prop_blocks, kth, fused, nullptr, plan);
+          HIP_TRY(hipStreamEndCapture(M->rg_stream, &gr));
+          const hipError_t e = hipGraphInstantiate(&M->rg_exec, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (e != hipSuccess) {
+            M->rg_exec = nullptr;
+            return set_err(PCH_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+          }
+          std::memcpy(M->rg_key, key, sizeof key);
+          std::memcpy(&M->rg_args, &a, sizeof a);
+        }
+        HIP_TRY(hipGraphLaunch(M->rg_exec, st));
+      } else {
+        for (int r = 0; r < o.rounds_per_sync; ++r) {
+          const bool timed = o.collect_timing && ((rounds_before + (u64)r) % (u64)o.collect_timing == 0);
+          enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused,
+                        timed ? &tev[kRoundEvents * (size_t)r] : nullptr, plan);
+          p ^= 1;
+        }
       }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(&host_ctl, M->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -3026,14 +3498,23 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
         const u64 ran = host_ctl.round - rounds_before;
         for (u64 r = 0; r < ran && r < (u64)o.rounds_per_sync; ++r) {
           if ((rounds_before + r) % (u64)o.collect_timing != 0) continue;
-          float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, tev[2 * r], tev[2 * r + 1]));
-          prop_ms += ms;
+          const hipEvent_t* ev = &tev[kRoundEvents * (size_t)r];
+          // phases in pch_stats.ms_phase order: selection, propagation,
+          // organization, events
+          const int from[4] = {0, 2, 1, 3}, to[4] = {1, 3, 2, 4};
+          for (int q = 0; q < 4; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[from[q]], ev[to[q]]));
+            phase_ms[q] += ms;
+          }
+          timed_rounds++;
           prop_n += fused ? 1 : o.hops;
         }
       }
       rounds_before = host_ctl.round;
       if (!strided) pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
+      if (host_ctl.badidx)
+        return set_err(PCH_EDEVICE, "a window or event named a half-edge or vertex outside the mesh");
       if (host_ctl.overflow) {
         overflow = true;
         break;
@@ -3054,9 +3535,9 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   HIP_TRY(hipMemcpyAsync(dist, M->g, sizeof(double) * H.nv, hipMemcpyDeviceToDevice, st));
   M->last_rounds = (int64_t)host_ctl.round;
   if (o.collect_stats) {
-    const int64_t n = std::min<int64_t>(M->last_rounds, M->dlog_cap);
+    const int64_t n = std::min<int64_t>(M->last_rounds, M->w.dlog_cap);
     M->last_log.assign((size_t)n * C_NUM, 0);
-    if (n) HIP_TRY(hipMemcpyAsync(M->last_log.data(), M->dlog, sizeof(int64_t) * n * C_NUM, hipMemcpyDeviceToHost, st));
+    if (n) HIP_TRY(hipMemcpyAsync(M->last_log.data(), M->w.dlog, sizeof(int64_t) * n * C_NUM, hipMemcpyDeviceToHost, st));
   } else {
     M->last_log.clear();
   }
@@ -3078,13 +3559,21 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
     stats->restarts = restarts;
     stats->ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    stats->ms_propagate = prop_ms;
+    stats->ms_propagate = phase_ms[1];
+    for (int q = 0; q < 4; ++q) stats->ms_phase[q] = phase_ms[q];
+    stats->timed_rounds = timed_rounds;
     stats->propagate_launches = prop_n;
     stats->hop_launches = (o.fuse_hops != 0 && o.hops <= kFuseHops) ? 1 : o.hops;
     stats->delta0 = delta0;
   }
   return PCH_OK;
 }
+
+pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
+                        const pch_options* opts, pch_stats* stats) {
+  return geodesic_core(M, sources, m, dist, hip_stream, opts, stats, nullptr);
+}
+
 
 }  // extern "C"
 
@@ -3113,6 +3602,9 @@ struct pch_batch_s {
   int32_t *d_fmesh = nullptr, *d_fsrc = nullptr, *d_order = nullptr;
   u64 *d_cost = nullptr, *d_wins = nullptr;
   u64* d_queue = nullptr;
+  int64_t* d_fn = nullptr;  // vertices per field (learned cutoff tables)
+  u32* d_cdf = nullptr;     // LEARNED: [n_fields][kCdfBins + 1]
+  double* d_pbin = nullptr; // LEARNED: [n_fields]
   GangRec* d_gang = nullptr;
   u32* d_board = nullptr;
   bool slots = false;
@@ -3219,6 +3711,16 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
   HIP_TRY(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_cost, b->cost.data(), sizeof(u64) * nf, hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_wins, b->wins.data(), sizeof(u64) * nf, hipMemcpyHostToDevice, b->stream));
+  if (b->o.select_mode == PCH_SELECT_LEARNED) {
+    // every field's predicted-distance table, from the predictions as they
+    // are now (outside the graph)
+    enqueue_pred_cdf(PredFields{b->o.predicted, b->d_off, b->d_fn, 0, nf, b->d_cdf, b->d_pbin}, b->stream);
+    std::vector<double> pb(nf);
+    HIP_TRY(hipMemcpyAsync(pb.data(), b->d_pbin, sizeof(double) * nf, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int f = 0; f < nf; ++f)
+      if (!(pb[f] > 0.0)) return set_err(PCH_EINVAL, "predicted distances must be positive");
+  }
   if (b->o.use_graph) {
     if (!b->gexec || b->g_out != out) {
       drop_graph(b);
@@ -3246,7 +3748,11 @@ pch_status batch_run(pch_batch_s* b, double* out, hipStream_t user, pch_batch_st
     if (fs[0] == 0) continue;
     pch_options o;
     pch_options_default(&o);
-    o.select_mode = PCH_SELECT_DELTA;
+    o.select_mode = b->o.select_mode;
+    if (o.select_mode == PCH_SELECT_LEARNED) {
+      o.predicted = b->o.predicted + b->off[f];
+      o.w0 = b->o.w0;
+    }
     o.k = b->o.k;
     o.delta0 = b->delta0[b->fmesh[f]];
     o.filters = b->o.filters;
@@ -3321,6 +3827,9 @@ void pch_batch_options_default(pch_batch_options* o) {
   o->team_threads = 256;
   o->hops = 1;
   o->gang = 1;
+  o->select_mode = PCH_SELECT_DELTA;
+  o->predicted = nullptr;
+  o->w0 = 4.0;
 }
 
 void pch_batch_destroy(pch_batch b) {
@@ -3329,7 +3838,8 @@ void pch_batch_destroy(pch_batch b) {
   free_slots(b);
   for (void* p : {(void*)b->d_meshes, (void*)b->d_nv, (void*)b->d_nh, (void*)b->d_off, (void*)b->d_fstat,
                   (void*)b->d_delta0, (void*)b->d_fmesh, (void*)b->d_fsrc, (void*)b->d_order, (void*)b->d_queue,
-                  (void*)b->d_gang, (void*)b->d_board, (void*)b->d_cost, (void*)b->d_wins})
+                  (void*)b->d_gang, (void*)b->d_board, (void*)b->d_cost, (void*)b->d_wins, (void*)b->d_fn,
+                  (void*)b->d_cdf, (void*)b->d_pbin})
     (void)hipFree(p);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -3350,6 +3860,12 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   if (o.k < 1 || o.teams_per_cu < 1 || !(o.eps_tiny >= 0.0) || (o.team_threads != 256 && o.team_threads != 512 && o.team_threads != 1024) ||
       o.hops < 1 || o.hops > kMaxHops || o.gang < 1 || o.gang > kMaxGang)
     return set_err(PCH_EINVAL, "bad batch option");
+  if (o.select_mode != PCH_SELECT_DELTA && o.select_mode != PCH_SELECT_LEARNED)
+    return set_err(PCH_EINVAL, "batched fields take the adaptive step or the learned cutoff");
+  if (o.select_mode == PCH_SELECT_LEARNED && !o.predicted)
+    return set_err(PCH_EINVAL, "learned selection needs predicted distances");
+  if (!(o.w0 >= 0.0)) return set_err(PCH_EINVAL, "bad batch option");
+  if (o.w0 == 0.0) o.w0 = 4.0;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   for (int i = 0; i < n_meshes; ++i) {
@@ -3383,7 +3899,8 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   b->delta0.resize(n_meshes);
   for (int i = 0; i < n_meshes; ++i) {
     pch_mesh_s* M = meshes[i];
-    dm[i] = DevMesh{M->hl, M->phi, M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff, M->corner, M->crec};
+    dm[i] = DevMesh{M->hl,    M->phi,    M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff,
+                    M->corner, M->crec, (int32_t)M->host.nv, (int32_t)M->host.nh};
     nv[i] = M->host.nv;
     nh[i] = M->host.nh;
     double sum = 0.0;
@@ -3440,6 +3957,18 @@ pch_status pch_batch_create(const pch_mesh* meshes, int32_t n_meshes, const int3
   B.gang = b->d_gang;
   B.board = b->d_board;
   B.max_rounds = kMaxRounds;
+  B.mode = o.select_mode;
+  B.w0 = o.w0;
+  if (o.select_mode == PCH_SELECT_LEARNED) {
+    std::vector<int64_t> fn(n_fields);
+    for (int f = 0; f < n_fields; ++f) fn[f] = nv[field_mesh[f]];
+    HIP_TRY(dalloc(&b->d_fn, n_fields));
+    HIP_TRY(dalloc(&b->d_cdf, (int64_t)n_fields * (kCdfBins + 1)));
+    HIP_TRY(dalloc(&b->d_pbin, n_fields));
+    HIP_TRY(hipMemcpy(b->d_fn, fn.data(), sizeof(int64_t) * n_fields, hipMemcpyHostToDevice));
+    B.cdf = b->d_cdf;
+    B.pbin = b->d_pbin;
+  }
   pch_status s = alloc_slots(b);
   if (s != PCH_OK) return s;
   *out = b;

@@ -94,3 +94,28 @@ def learned_geodesic(mlp: pch.MLP, gen_mesh, dev_mesh: pch.Mesh, xyz_dev, source
     """Exact field with the learned cutoff; returns (distances, stats)."""
     pred = predict_field(mlp, gen_mesh, xyz_dev, source)
     return pch.geodesic(dev_mesh, [source], k=k, predicted=pred, w0=w0, return_stats=True, **opts)
+
+
+def chord_geodesic(gen_mesh, dev_mesh: pch.Mesh, xyz_dev, source: int, k: int = 8192, w0: float = 4.0, **opts):
+    """The same cutoff rule without the network: the predicted distance of a
+    vertex is its chord length to the source (the network's base term, a
+    lower bound of the geodesic distance). Returns (distances, stats)."""
+    c, r = mesh_frame(gen_mesh.xyz)
+    _, base = pch.MLP.features(xyz_dev, source, c, r)
+    return pch.geodesic(dev_mesh, [source], k=k, predicted=base, w0=w0, return_stats=True, **opts)
+
+
+def batch_predictions(mlp, gens: Sequence, field_mesh, field_source, offsets, chord: bool = False):
+    """Predicted distances of every field of a batch in the output's layout
+    (field f at offsets[f]): the network's, or with chord=True the chord
+    lengths (the same rule without the network). Returns a device float
+    tensor for Batch(..., predicted=...)."""
+    import torch
+    out = torch.empty(int(offsets[-1]), dtype=torch.float32, device="cuda")
+    xyz = [torch.from_numpy(g.xyz).to("cuda") for g in gens]
+    frames = [mesh_frame(g.xyz) for g in gens]
+    for f, (mi, s) in enumerate(zip(field_mesh, field_source)):
+        c, r = frames[int(mi)]
+        feats, base = pch.MLP.features(xyz[int(mi)], int(s), c, r)
+        out[int(offsets[f]):int(offsets[f + 1])] = base if chord else mlp.forward(feats, base)
+    return out

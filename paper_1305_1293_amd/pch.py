@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("cutoff_table", ctypes.c_void_p),
                 ("n_cutoff", ctypes.c_int64), ("collect_timing", ctypes.c_int32), ("hops", ctypes.c_int32),
                 ("delta0", ctypes.c_double), ("predicted", ctypes.c_void_p), ("w0", ctypes.c_double),
-                ("organize", ctypes.c_int32), ("counts", ctypes.c_int32), ("fuse_hops", ctypes.c_int32)]
+                ("organize", ctypes.c_int32), ("counts", ctypes.c_int32), ("fuse_hops", ctypes.c_int32),
+                ("fuse_scan", ctypes.c_int32), ("round_graph", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -53,10 +54,13 @@ class Stats(ctypes.Structure):
                  "angle_events", "fans", "fan_windows", "deferred", "peak_pool", "restarts"]] + \
                [("ms_total", ctypes.c_double), ("ms_propagate", ctypes.c_double),
                 ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double),
-                ("hop_launches", ctypes.c_int64)]
+                ("hop_launches", ctypes.c_int64), ("ms_phase", ctypes.c_double * 4),
+                ("timed_rounds", ctypes.c_int64)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_}
+        d["ms_phase"] = dict(zip(("select", "propagate", "organize", "events"), list(self.ms_phase)))
+        return d
 
 
 _lib = None
@@ -205,7 +209,8 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("teams_per_cu", ctypes.c_int32), ("filters", ctypes.c_int32),
                 ("eps_tiny", ctypes.c_double), ("pool_capacity", ctypes.c_int64), ("use_graph", ctypes.c_int32),
                 ("team_threads", ctypes.c_int32), ("hops", ctypes.c_int32), ("gang", ctypes.c_int32),
-                ("wait_ticks", ctypes.c_int64)]
+                ("wait_ticks", ctypes.c_int64), ("select_mode", ctypes.c_int32), ("predicted", ctypes.c_void_p),
+                ("w0", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -222,7 +227,17 @@ class BatchStats(ctypes.Structure):
 BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "team_ticks",
                      "helpers", "helper_ticks"]
 EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
-            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune", "pch_voronoi"]
+            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune", "pch_voronoi", "pch_field_status_string"]
+# field status codes (first column of Batch.field_stats)
+FIELD_STATUS = {0: "PCH_FIELD_OK", 1: "PCH_FIELD_OVERFLOW", 2: "PCH_FIELD_MAX_ROUNDS", 3: "PCH_FIELD_ABANDONED",
+                4: "PCH_FIELD_NOT_RUN", 5: "PCH_FIELD_NONFINITE", 6: "PCH_FIELD_BAD_INDEX"}
+
+
+def field_status_string(status: int) -> str:
+    L = lib()
+    L.pch_field_status_string.restype = ctypes.c_char_p
+    L.pch_field_status_string.argtypes = [ctypes.c_int64]
+    return L.pch_field_status_string(int(status)).decode()
 
 
 def _batch_lib():
@@ -255,6 +270,12 @@ class Batch:
             raise ValueError("field_mesh and field_source differ in length")
         o = BatchOptions()
         L.pch_batch_options_default(ctypes.byref(o))
+        predicted = opts.pop("predicted", None)
+        if predicted is not None:
+            # device float tensor laid out like the output (field f at offsets[f])
+            o.select_mode = PCH_SELECT_LEARNED
+            o.predicted = predicted.data_ptr() if hasattr(predicted, "data_ptr") else int(predicted)
+            self._pred = predicted  # keep alive
         for k, v in opts.items():
             if not hasattr(o, k):
                 raise TypeError(f"unknown batch option {k}")

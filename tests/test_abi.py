@@ -60,3 +60,15 @@ def test_invalid_meshes_rejected_before_device_work(pch):
     assert _code(pch, [[0, 1, 2], [0, 3, 4]], bow) == -2                   # two fans at a vertex
     assert _code(pch, [[0, 1, 2]], he_len=np.array([1.0, 1.0, 3.0]), nv=3) == -2  # lengths violate triangle ineq.
     assert _code(pch, [[0, 1, 2]], he_len=np.array([1.0, -1.0, 1.0]), nv=3) == -1
+
+
+def test_field_status_codes_match_header(pch):
+    text = open(os.path.join(ROOT, "include", "pch.h")).read()
+    codes = {name: int(v) for name, v in re.findall(r"(PCH_FIELD_\w+)\s*=\s*(\d+)", text)}
+    assert codes == {v: k for k, v in pch.FIELD_STATUS.items()}
+    names = {c: pch.field_status_string(c) for c in pch.FIELD_STATUS}
+    assert names[0] == "ok"
+    assert len(set(names.values())) == len(names)  # every status has its own message
+    assert "non-finite" in names[5] and "outside the mesh" in names[6]
+    assert all("rerun" in names[c] for c in (1, 2, 3, 4))  # the statuses a rerun completes
+    assert pch.field_status_string(99) == "unknown field status"

@@ -250,3 +250,37 @@ def test_tune_keeps_fields_exact(pch, setup):
         ref = single(pch, meshes[int(b.field_mesh[f])], int(b.field_source[f]), chosen["k"], chosen["hops"])
         assert np.array_equal(got[b.offsets[f]:b.offsets[f + 1]].view(np.uint64), ref.view(np.uint64)), f
     b.close()
+
+
+def test_full_size_batch_every_field(pch, oracle):
+    """The 512-field batch at full size (16 meshes of 14k-330k faces, 32
+    sources each) with the benchmark's options: every field equals its
+    single-field run with the same rule, k and hops bit for bit, and the
+    first field of every mesh is within 1e-9 of ICH."""
+    import torch
+    gens = G.batch_meshes(3)
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
+    fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
+    k, hops = 32768, 4
+    b = pch.Batch(meshes, fm, fs, k=k, team_threads=512, teams_per_cu=1, hops=hops, gang=8)
+    say(f"batch of {b.n_fields} fields on {len(gens)} meshes")
+    out, _ = b.run()
+    out, st = b.run(out)  # a graph replay, as timed by the benchmark
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    say(f"  reruns {st['reruns']} processed {st['processed']}")
+    for f in range(b.n_fields):
+        ref = single(pch, meshes[fm[f]], int(fs[f]), k, hops)
+        gf = got[b.offsets[f]:b.offsets[f + 1]]
+        assert np.array_equal(gf.view(np.uint64), ref.view(np.uint64)), f"field {f} differs from the single run"
+    for i, g in enumerate(gens):
+        f = 32 * i
+        d_ich, _ = oracle.ich(g, [int(fs[f])])
+        hbar = float(oracle.lengths(g).mean())
+        gf = got[b.offsets[f]:b.offsets[f + 1]]
+        assert np.array_equal(np.isfinite(gf), np.isfinite(d_ich))
+        assert np.max(np.abs(gf - d_ich) / np.maximum(d_ich, hbar)) <= 1e-9, (g.name, f)
+    b.close()
+    for dm in meshes:
+        dm.close()

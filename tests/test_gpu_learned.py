@@ -144,3 +144,68 @@ def test_learned_gain_over_plain(pch, trained):
             f"adaptive step {1000*td:.1f} ms {sd['processed']} windows {sd['rounds']} rounds")
         dm.close()
     assert sum(r[2] for r in rows) < sum(r[1] for r in rows)
+
+
+def test_learned_cutoff_full_size_bump_grid(pch, trained):
+    """The learned cutoff on the 1024^2 bump grid from vertex 0 (the first test
+    field of the learned workload), every vertex against the stored exact
+    field, and the network-free ablation (chord predictions) likewise."""
+    import os
+    import torch
+    from paper_1305_1293_amd import learned as Lr
+    mlp, _ = trained
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bump_grid1024_s2_ich.npz"))
+    m = G.config_mesh(3)
+    s = int(gold["source"])
+    dm = pch.Mesh.from_generated(m)
+    xyz = torch.from_numpy(m.xyz).cuda()
+    ref, hbar = gold["dist"], float(gold["mean_edge"])
+    for name, run in (("learned", lambda: Lr.learned_geodesic(mlp, m, dm, xyz, s, k=131072, hops=5)),
+                      ("chord", lambda: Lr.chord_geodesic(m, dm, xyz, s, k=131072, hops=5))):
+        d, st = run()
+        torch.cuda.synchronize()
+        got = d.cpu().numpy()
+        fin = np.isfinite(ref)
+        assert np.array_equal(fin, np.isfinite(got)), name
+        err = np.max(np.abs(got[fin] - ref[fin]) / np.maximum(ref[fin], hbar))
+        say(f"{name}: rounds {st['rounds']} processed {st['processed']} max rel err {err:.2e}")
+        assert err <= 1e-9, name
+    dm.close()
+
+
+@pytest.mark.parametrize("gang", [1, 4])
+def test_learned_cutoff_batched_equals_single_fields(pch, oracle, trained, gang):
+    """The learned cutoff in the batched persistent launch: every field equals
+    its single-field run with the same predictions, k and hops bit for bit,
+    and ICH within 1e-9."""
+    import torch
+    from paper_1305_1293_amd import learned as Lr
+    mlp, _ = trained
+    gens = [G.bumpy_icosphere(4, seed=41), G.bump_grid(48, seed=42), G.sinusoid_grid(32, 5)]
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    rng = np.random.default_rng(9)
+    fm = np.repeat(np.arange(len(gens)), 4).astype(np.int32)
+    fs = np.concatenate([rng.choice(m.nv, 4, replace=False) for m in gens]).astype(np.int32)
+    k, hops = 512, 3
+    off = np.zeros(fm.size + 1, np.int64)
+    off[1:] = np.cumsum([gens[i].nv for i in fm])
+    pred = Lr.batch_predictions(mlp, gens, fm, fs, off)
+    b = pch.Batch(meshes, fm, fs, k=k, hops=hops, teams_per_cu=1, gang=gang, predicted=pred)
+    assert np.array_equal(b.offsets, off)
+    out, st = b.run()
+    out, st = b.run(out)  # a graph replay
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    say(f"learned batch gang {gang}: processed {st['processed']} reruns {st['reruns']}")
+    for f in range(fm.size):
+        g, s = gens[fm[f]], int(fs[f])
+        xyz = torch.from_numpy(g.xyz).cuda()
+        d, _ = Lr.learned_geodesic(mlp, g, meshes[fm[f]], xyz, s, k=k, hops=hops)
+        gf = got[off[f]:off[f + 1]]
+        assert np.array_equal(gf.view(np.uint64), d.cpu().numpy().view(np.uint64)), f"field {f}"
+        ref, _ = oracle.ich(g, [s])
+        hbar = float(oracle.lengths(g).mean())
+        assert np.max(np.abs(gf - ref) / np.maximum(ref, hbar)) <= 1e-9, f
+    b.close()
+    for dm in meshes:
+        dm.close()
