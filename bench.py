@@ -1,29 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark: exact single-source geodesic fields with PCH on one MI355X.
 
-A step is one exact FP64 distance field on the bumpy icosphere with 7
-subdivisions (327,680 faces, the face count of the paper's Sphere row in
-Table 3), from one seeded random source vertex; every step uses a new source,
-like the paper's mean over random sources (Section 5.3). The mesh is resident
-in device memory before the timed region; each step runs every phase of the
-method (selection, propagation, organization, events) until the window pool
-is empty.
+A step is one exact FP64 distance field on the 1024 x 1024 jittered bump grid
+(2,093,058 faces, 16 seeded Gaussian bumps, anisotropic and obtuse
+triangles): the first timed step starts at vertex 0, the others at seeded
+random vertices. The mesh is resident in device memory before the timed
+region; each step runs every phase of the method (selection, propagation,
+organization, events) until the window pool is empty.
 
 Prints one JSON line. Besides the headline (ms per field) it carries:
-  roofline     - the propagation kernel's algorithmic bytes per launch over
-                 its average launch time, measured with HIP events on the
-                 library's stream during the timed steps, against 8 TB/s;
+  roofline     - the propagation kernel's algorithmic bytes (and FP64
+                 operations) per launch over its average launch time,
+                 measured with HIP events on the library's stream during
+                 the timed steps, against 8 TB/s (78.6 TFLOP/s FP64);
+  phases       - the GPU time of each phase of the timed rounds;
   cpu_baseline - the CPU oracle (sequential ICH, one core) on a bounded
-                 sample of the same workload, whose fields also check the
-                 first GPU fields;
-  batched      - 512 fields (16 meshes of 20k-330k faces, 32 sources each)
-                 in one persistent launch against plain PCH (k-th-key
-                 selection, one face per round, k tuned per mesh) run field
-                 after field on a sample of the same fields.
+                 sample of the vertex-0 field, run in a child process that
+                 starts before any GPU work;
+  icosphere    - the same measurement on the bumpy icosphere with 7
+                 subdivisions (327,680 faces, the face count of the paper's
+                 Sphere row);
+  batched      - 512 fields (16 meshes of 14k-330k faces, 32 sources each)
+                 in one persistent launch against the single-field path run
+                 field after field, both with the best single-field setting
+                 and with plain k-th-key selection.
 
 --workload learned prints a separate line for the learned selection cutoff:
 the network is trained on 200 fields of bumpy icospheres and sets the
-cutoffs on 1024 x 1024 bump grids, against plain PCH on the same fields.
+cutoffs on 1024 x 1024 bump grids, against the same rule without the
+network (chord-length predictions) and the adaptive step.
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -41,6 +47,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 # Algorithmic bytes of one propagation (Algorithm 2) per processed window:
 # the window record (6 doubles, 2 ints), its 64-byte half-edge record,
 # geod_dist of the face's three vertices and the corner's angle_split pair.
@@ -48,6 +55,15 @@ PROP_READ_BYTES = 56 + 64 + 24 + 16
 WINDOW_BYTES = 56        # one child window written
 DIST_EVENT_BYTES = 20    # vertex id, distance, incoming angle
 ANGLE_EVENT_BYTES = 20   # oriented edge id, distance, crossing
+# Algorithmic FP64 operations (add, mul, div, sqrt) of Algorithm 2: the apex
+# crossing, occupancy test and apex distance of a window, and the interval,
+# unfolded pseudo-source, filter distances and key of each child it examines.
+FLOP_PER_WINDOW = 18
+FLOP_PER_CHILD = 50
+# cpu_baseline sample: windows the ICH oracle propagates (about 15-25 s on one
+# host core)
+CPU_SAMPLE_WINDOWS = 20_000_000
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "bump_grid1024_s2_ich.npz")
 
 
 def kernel_source_hash() -> str:
@@ -55,20 +71,57 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str, workload_tag: str, config_tag: str):
-    """HBM bytes per propagation launch from the committed counter summary, or
-    None when the summary is missing or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_tag}_traffic.md")
+def profile_value(name: str, key: str, config_tag: str):
+    """A per-launch figure from a committed counter summary, or None when the
+    summary is missing or the kernel source or configuration changed since."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    b = re.search(key + r":\s*([0-9.eE+]+)", text)
     cfg = re.search(r"bench_config:\s*(.+)", text)
     if not m or not b or not cfg or m.group(1) != kernel_source_hash() or cfg.group(1).strip() != config_tag:
         return None
     return float(b.group(1))
 
+
+def host_cpu():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_child(windows: int):
+    """The CPU-baseline leg (child process): sequential ICH on one core over
+    the first `windows` propagated windows of the bump-grid field from vertex
+    0. Prints one JSON line."""
+    from oracle import oracle as O
+    from paper_1305_1293_amd import meshgen as G
+    m = G.config_mesh(3)
+    O.lib()
+    t = time.perf_counter()
+    _, st = O.ich(m, [0], max_processed=windows)
+    el = time.perf_counter() - t
+    print(json.dumps({"seconds": el, "processed": st["processed"], **host_cpu()}), flush=True)
+
+
+def start_cpu_child(windows: int):
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", str(windows)],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def finish_cpu_child(proc):
+    out, err = proc.communicate(timeout=900)
+    if proc.returncode != 0:
+        raise RuntimeError(f"CPU-baseline child failed ({proc.returncode}): {err[-2000:]}")
+    return json.loads(out.strip().splitlines()[-1])
 
 
 def _timed(torch, fn):
@@ -89,8 +142,104 @@ def batch_roofline(windows_per_s: float) -> dict:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_window": per_window, "lower_bound": True}
 
 
+def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
+    """Warm-up fields, then the timed fields (statistics counters off), then
+    the same fields again untimed with the counters on."""
+    out = torch.empty(mesh.info()["nv"], dtype=torch.float64, device="cuda")
+    for s in srcs[:warmup]:
+        pch.geodesic(mesh, [int(s)], out=out, **opts)
+    torch.cuda.synchronize()
+    timed = srcs[warmup:]
+    keep = []
+    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0, timed_rounds=0)
+    phase = dict(select=0.0, propagate=0.0, organize=0.0, events=0.0)
+    hop_launches = 1
+    t0 = time.perf_counter()
+    for i, s in enumerate(timed):
+        _, st = pch.geodesic(mesh, [int(s)], out=out, return_stats=True, counts=0, **opts)
+        for kk in tot:
+            tot[kk] += st[kk]
+        for kk in phase:
+            phase[kk] += st["ms_phase"][kk]
+        hop_launches = st["hop_launches"]
+        if i < keep_first:
+            keep.append(out.clone())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = dict(processed=0, rounds=0, created=0, fan_windows=0, dist_events=0, angle_events=0, tiny=0,
+               ich_dropped=0)
+    copts = dict(opts, collect_timing=0)
+    for s in timed:
+        _, st = pch.geodesic(mesh, [int(s)], out=out, return_stats=True, counts=1, **copts)
+        for kk in cnt:
+            cnt[kk] += st[kk]
+    assert cnt["processed"] == tot["processed"] and cnt["rounds"] == tot["rounds"]
+    tot.update({kk: cnt[kk] for kk in cnt if kk not in ("processed", "rounds")})
+    return wall, tot, phase, hop_launches, keep
+
+
+def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
+    kids = tot["created"] - tot["fan_windows"]
+    prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
+                  + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
+    flops = FLOP_PER_WINDOW * tot["processed"] + FLOP_PER_CHILD * (kids + tot["tiny"] + tot["ich_dropped"])
+    # every round launches the propagation kernel once (all hops fused) or
+    # once per hop; the HIP events bracket the phases of every n-th round
+    timed = max(tot["propagate_launches"], 1)
+    avg_launch_s = tot["ms_propagate"] / 1000.0 / timed
+    all_launches = max(tot["rounds"] * hop_launches, 1)
+    bytes_per_launch = prop_bytes / all_launches
+    flops_per_launch = flops / all_launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    tflops = flops_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+    kernel = "k_propagate_fused" if hop_launches == 1 else "k_propagate"
+    fp64 = {"bound": "fp64", "achieved": round(tflops, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / FP64_PEAK_TFLOPS, 6), "alg_flop_per_launch": round(flops_per_launch, 1),
+            "counter_flop_per_launch": counter_flops}
+    # share of the timed rounds' GPU time per phase
+    ptot = sum(phase.values())
+    phases = {"ms_per_field": {k: round(v / max(tot["timed_rounds"], 1) * tot["rounds"] / steps, 3)
+                               for k, v in phase.items()},
+              "share": {k: round(v / ptot, 4) if ptot > 0 else 0.0 for k, v in phase.items()},
+              "timed_rounds": tot["timed_rounds"]}
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
+            "timed_launches": tot["propagate_launches"],
+            "propagate_share_of_wall": round(avg_launch_s * all_launches / wall, 4), "fp64": fp64}, phases
+
+
+def measure_icosphere(args, pch, G, torch):
+    """The bumpy icosphere (327,680 faces) at its own best setting; two fields
+    checked against ICH."""
+    from oracle import oracle as O
+    m = G.config_mesh(2)
+    rng = np.random.default_rng(2024)
+    srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
+    mesh = pch.Mesh.from_generated(m)
+    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=5)
+    wall, tot, phase, hl, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=2)
+    hbar = float(O.lengths(m).mean())
+    errs = []
+    for i in range(2):
+        ref, _ = O.ich(m, [int(srcs[args.warmup + i])])
+        errs.append(float(np.max(np.abs(keep[i].cpu().numpy() - ref) / np.maximum(ref, hbar))))
+    mesh.close()
+    traffic = profile_value("k_propagate_fused_icosphere7_traffic.md", "hbm_bytes_per_launch",
+                            "select=1 k=12288 hops=5 fuse_hops=1")
+    roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, None)
+    return {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, seeded random sources",
+            "ms_per_field": round(1000.0 * wall / args.steps, 4), "steps": args.steps,
+            "windows_per_s": round(tot["processed"] / wall, 1), "rounds_per_field": tot["rounds"] / args.steps,
+            "options": {k: v for k, v in opts.items() if k != "collect_timing"},
+            "max_rel_err_vs_oracle": max(errs), "roofline": roof, "phases": phases}
+
+
 def measure_batched(pch, G, torch):
-    """512 fields in one persistent launch against plain PCH field by field."""
+    """512 fields in one persistent launch against the single-field path run
+    field after field: with the batch's own rule, k and hops, with the best
+    single-field setting, and with plain k-th-key selection."""
     gens = G.batch_meshes(3)
     meshes = [pch.Mesh.from_generated(m) for m in gens]
     fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
@@ -103,43 +252,55 @@ def measure_batched(pch, G, torch):
     windows = int(b.field_stats()[:, 2].sum())
     got = out.cpu().numpy()
     ks = (4096, 8192, 16384, 32768)
-    plain_ms, worst = 0.0, 0.0
+    plain_ms, same_ms, best_ms, worst = 0.0, 0.0, 0.0, 0.0
     for i, (g, dm) in enumerate(zip(gens, meshes)):
         srcs = [int(x) for x in g.meta["sources"]]
         times = {k: _timed(torch, lambda: pch.geodesic(dm, [srcs[0]], k=k, select_mode=0))[0] for k in ks}
         kbest = min(times, key=times.get)
-        tt = 0.0
+        tp = ts = tb = 0.0
         for j in (1, 2):
             t, d = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=kbest, select_mode=0))
-            tt += t
+            tp += t
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=32768, select_mode=1, hops=4))
+            ts += t
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=5))
+            tb += t
             f = i * 32 + j
             ref = got[b.offsets[f]:b.offsets[f + 1]]
             worst = max(worst, float(np.max(np.abs(d.cpu().numpy() - ref) / np.maximum(ref, 1e-3))))
-        plain_ms += 1000.0 * 32 * tt / 2
+        plain_ms += 1000.0 * 32 * tp / 2
+        same_ms += 1000.0 * 32 * ts / 2
+        best_ms += 1000.0 * 32 * tb / 2
     b.close()
     for dm in meshes:
         dm.close()
     return {"fields": int(fm.size), "meshes": len(gens), "faces": [int(m.nf) for m in gens], "ms": round(batch_ms, 2),
             "ms_per_field": round(batch_ms / fm.size, 4), "windows_per_s": round(windows / dt, 1), "options": opts,
-            "plain_ms_est": round(plain_ms, 1),
-            "plain": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on its first "
-                     "source; 2 more sources per mesh timed and scaled to 32",
-            "speedup_vs_plain": round(plain_ms / batch_ms, 3), "max_rel_diff_vs_plain": worst,
-            "roofline": batch_roofline(windows / dt)}
+            "single_field_ms_est": {"same_rule": round(same_ms, 1), "best_setting": round(best_ms, 1),
+                                    "plain_kth": round(plain_ms, 1)},
+            "single_field_settings": {
+                "same_rule": "adaptive step, k 32768, 4 hops (the batch's own rule: equal results bit for bit)",
+                "best_setting": "adaptive step, k 12288, 5 hops in one launch per round",
+                "plain_kth": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on "
+                             "its first source"},
+            "sample": "2 sources per mesh timed field by field and scaled to 32",
+            "speedup": {"vs_same_rule": round(same_ms / batch_ms, 3), "vs_best_setting": round(best_ms / batch_ms, 3),
+                        "vs_plain_kth": round(plain_ms / batch_ms, 3)},
+            "max_rel_diff_vs_plain": worst, "roofline": batch_roofline(windows / dt)}
 
 
-def measure_concurrent(args, pch, m, mesh, srcs, keep, torch):
-    """Fields of the same mesh computed together: 64 sources (the timed ones
-    first) in one batched launch whose idle workgroups share running fields;
-    same selection rule, k and hops as the single-field steps, so each field
+def measure_concurrent(pch, m, mesh, torch):
+    """Fields of the same mesh computed together: 64 seeded sources in one
+    batched launch whose idle workgroups share running fields; same selection
+    rule, k and hops as the icosphere's single-field steps, so each field
     equals its single-field result bit for bit."""
-    extra = np.setdiff1d(np.random.default_rng(7).choice(m.nv, size=128, replace=False), srcs)
-    fs = np.concatenate([srcs[args.warmup:], extra])[:64].astype(np.int32)
-    opts = dict(k=args.k, team_threads=512, teams_per_cu=1, hops=args.hops, gang=16)
+    fs = np.random.default_rng(7).choice(m.nv, size=64, replace=False).astype(np.int32)
+    opts = dict(k=12288, team_threads=512, teams_per_cu=1, hops=5, gang=16)
     b = pch.Batch([mesh], np.zeros(fs.size, np.int32), fs, **opts)
     out, _ = b.run()  # first run captures the graph and measures each field's time
     dt, (out, st) = _timed(torch, lambda: b.run(out))
-    same = all(torch.equal(b.field(out, f), keep[f]) for f in range(min(len(keep), fs.size)))
+    same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=5))
+               for f in range(8))
     windows = int(b.field_stats()[:, 2].sum())
     b.close()
     return {"fields": int(fs.size), "ms": round(1000.0 * dt, 2), "ms_per_field": round(1000.0 * dt / fs.size, 4),
@@ -148,7 +309,8 @@ def measure_concurrent(args, pch, m, mesh, srcs, keep, torch):
 
 
 def measure_learned(args, pch, G, torch):
-    """Learned selection cutoff against plain PCH on the 1024 x 1024 bump grids."""
+    """Learned selection cutoff on the 1024 x 1024 bump grids against the same
+    rule without the network and the other selection rules."""
     from paper_1305_1293_amd import learned as Lr
     train, test = G.learned_cutoff_sets(4)
     t0 = time.perf_counter()
@@ -157,33 +319,42 @@ def measure_learned(args, pch, G, torch):
     losses = Lr.train(mlp, data, epochs=6, batch=16384, lr=2e-3, log_every=50)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    k = args.k_learned
-    rows = []
+    k, hops = args.k_learned, args.hops_learned
+    names = ("learned", "chord", "adaptive_step", "kth")
+    rows = {n: [] for n in names}
+    err = 0.0
     for g in test:
         dm = pch.Mesh.from_generated(g)
         xyz = torch.from_numpy(g.xyz).cuda()
         for s in [int(x) for x in g.meta["sources"][:args.learned_sources]]:
-            tp, (dp, sp) = _timed(torch, lambda: pch.geodesic(dm, [s], k=k, select_mode=0, return_stats=True))
-            tl, (dl, sl) = _timed(torch, lambda: Lr.learned_geodesic(mlp, g, dm, xyz, s, k=k))
-            td, (dd, sd) = _timed(torch, lambda: pch.geodesic(dm, [s], k=k, select_mode=1, return_stats=True))
-            ref = dp.cpu().numpy()
-            err = float(np.max(np.abs(dl.cpu().numpy() - ref) / np.maximum(ref, 1e-3)))
-            rows.append((tp, tl, td, sp["rounds"], sl["rounds"], sd["rounds"], sp["processed"], sl["processed"], err))
+            runs = {
+                "learned": lambda: Lr.learned_geodesic(mlp, g, dm, xyz, s, k=k, hops=hops),
+                "chord": lambda: Lr.chord_geodesic(g, dm, xyz, s, k=k, hops=hops),
+                "adaptive_step": lambda: pch.geodesic(dm, [s], k=k, select_mode=1, hops=hops, return_stats=True),
+                "kth": lambda: pch.geodesic(dm, [s], k=k, select_mode=0, hops=hops, return_stats=True),
+            }
+            ref = None
+            for n in names:
+                t, (d, st) = _timed(torch, runs[n])
+                rows[n].append((t, st["rounds"], st["processed"]))
+                if ref is None:
+                    ref = d.cpu().numpy()
+                else:
+                    err = max(err, float(np.max(np.abs(d.cpu().numpy() - ref) / np.maximum(ref, 1e-3))))
         dm.close()
-    a = np.array(rows)
-    plain_ms, learned_ms, step_ms = 1000 * a[:, 0].mean(), 1000 * a[:, 1].mean(), 1000 * a[:, 2].mean()
+    mean = {n: np.array(rows[n]).mean(axis=0) for n in names}
+    ms = {n: round(1000 * float(mean[n][0]), 2) for n in names}
     return {"metric": "learned-cutoff vs plain speedup (ms per exact single-source field)",
-            "value": round(plain_ms / learned_ms, 4), "unit": "x", "higher_is_better": True,
+            "value": round(ms["kth"] / ms["learned"], 4), "unit": "x", "higher_is_better": True,
             "n_gpus": 1, "dtype": "f64 fields, bf16/f32 network", "data": "synthetic",
             "config": {"workload": "train: 200 fields of bumpy icospheres (levels 5 and 6, 20 meshes x 10 sources); "
                                    "test: 1024 x 1024 bump grids (seeds 2, 20, 21), 2,093,058 faces",
-                       "fields": len(rows), "k": k, "hops": 1},
-            "ms_per_field": {"plain_kth": round(plain_ms, 2), "learned": round(learned_ms, 2),
-                             "adaptive_step": round(step_ms, 2)},
-            "rounds_per_field": {"plain_kth": float(a[:, 3].mean()), "learned": float(a[:, 4].mean()),
-                                 "adaptive_step": float(a[:, 5].mean())},
-            "windows_per_field": {"plain_kth": float(a[:, 6].mean()), "learned": float(a[:, 7].mean())},
-            "max_rel_diff_learned_vs_plain": float(a[:, 8].max()),
+                       "fields": len(rows["learned"]), "k": k, "hops": hops},
+            "ms_per_field": ms,
+            "speedup_of_learned": {n: round(ms[n] / ms["learned"], 4) for n in names if n != "learned"},
+            "rounds_per_field": {n: float(mean[n][1]) for n in names},
+            "windows_per_field": {n: float(mean[n][2]) for n in names},
+            "max_rel_diff_vs_learned": err,
             "training": {"samples": int(data.feats.shape[0]), "seconds": round(train_s, 2),
                          "loss_first": losses[0], "loss_last": losses[-1]}}
 
@@ -191,30 +362,41 @@ def measure_learned(args, pch, G, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["field", "learned"], default="field")
-    ap.add_argument("--k", type=int, default=12288, help="windows selected per round")
+    ap.add_argument("--k", type=int, default=131072, help="windows selected per round (bump grid)")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
     ap.add_argument("--hops", type=int, default=5, help="propagation hops per round")
     ap.add_argument("--fuse-hops", type=int, default=1,
                     help="1: all hops of a round in one propagation launch (hops <= 6); 0: one launch per hop")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-versus-plain measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
+    ap.add_argument("--no-icosphere", action="store_true", help="skip the icosphere measurement")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
+    ap.add_argument("--hops-learned", type=int, default=5, help="hops of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
     ap.add_argument("--time-every", type=int, default=8,
-                    help="time the propagation kernel of every n-th round with HIP events")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
+                    help="time the phases of every n-th round with HIP events")
+    ap.add_argument("--cpu-windows", type=int, default=CPU_SAMPLE_WINDOWS,
+                    help="windows of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 5 times (the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args.cpu_child)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's fields are "
               "independent per GPU, see the multi-GPU design notes)", file=sys.stderr)
         sys.exit(2)
+    # the CPU-oracle leg runs beside the GPU legs, started before any GPU call
+    child = None
+    if args.workload == "field" and not args.no_cpu_baseline and args.copy_bytes == 0:
+        child = start_cpu_child(args.cpu_windows)
 
     import torch
 
@@ -235,87 +417,55 @@ def main():
     if args.workload == "learned":
         print(json.dumps(measure_learned(args, pch, G, torch)), flush=True)
         return
-    m = G.config_mesh(2)
+    m = G.config_mesh(3)
     rng = np.random.default_rng(2024)
-    srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
+    pool = [int(x) for x in rng.choice(m.nv, size=args.warmup + args.steps, replace=False) if x != 0]
+    srcs = pool[:args.warmup] + [0] + pool[args.warmup:args.warmup + args.steps - 1]
     mesh = pch.Mesh.from_generated(m)
-    out = torch.empty(m.nv, dtype=torch.float64, device="cuda")
-    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0, hops=args.hops,
-                fuse_hops=args.fuse_hops)
-
-    for i in range(args.warmup):
-        pch.geodesic(mesh, [int(srcs[i])], out=out, **opts)
-    torch.cuda.synchronize()
-
-    keep = []
-    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0)
-    hop_launches = None
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        # the statistics counters (windows created, events) stay off in the
-        # timed fields, as in a plain call; they are taken below
-        _, st = pch.geodesic(mesh, [int(srcs[args.warmup + i])], out=out, return_stats=True, counts=0, **opts)
-        for kk in tot:
-            tot[kk] += st[kk]
-        hop_launches = st["hop_launches"]
-        if len(keep) < 8:
-            keep.append(out.clone())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+    opts = dict(k=args.k, collect_timing=args.time_every, select_mode=args.select, delta0=args.delta0,
+                hops=args.hops, fuse_hops=args.fuse_hops)
+    print(f"bench: bump grid 1024^2, {args.steps} fields, k {args.k}, hops {args.hops}", file=sys.stderr, flush=True)
+    wall, tot, phase, hop_launches, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=1)
     ms_per_field = 1000.0 * wall / args.steps
-    # the same fields again, untimed, with the counters on (the method is
-    # deterministic: same rounds, windows and events)
-    cnt = dict(processed=0, rounds=0, created=0, fan_windows=0, dist_events=0, angle_events=0)
-    copts = dict(opts, collect_timing=0)
-    for i in range(args.steps):
-        _, st = pch.geodesic(mesh, [int(srcs[args.warmup + i])], out=out, return_stats=True, counts=1, **copts)
-        for kk in cnt:
-            cnt[kk] += st[kk]
-    assert cnt["processed"] == tot["processed"] and cnt["rounds"] == tot["rounds"]
-    tot.update({kk: cnt[kk] for kk in ("created", "fan_windows", "dist_events", "angle_events")})
-
-    kids = tot["created"] - tot["fan_windows"]
-    prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
-                  + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
-    # every round launches the propagation kernel once (all hops fused) or
-    # once per hop; the HIP events bracket the launches of every n-th round
-    timed = max(tot["propagate_launches"], 1)
-    avg_launch_s = tot["ms_propagate"] / 1000.0 / timed
-    all_launches = max(tot["rounds"] * hop_launches, 1)
-    bytes_per_launch = prop_bytes / all_launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    tag = f"select={args.select} k={args.k} hops={args.hops} fuse_hops={args.fuse_hops}"
     kernel = "k_propagate_fused" if hop_launches == 1 else "k_propagate"
-    traffic = traffic_from_profile(kernel, "icosphere7", f"select={args.select} k={args.k} hops={args.hops} "
-                                                        f"fuse_hops={args.fuse_hops}")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
-                "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
-                "timed_launches": tot["propagate_launches"],
-                "propagate_share_of_wall": round(avg_launch_s * all_launches / wall, 4)}
+    traffic = profile_value(f"{kernel}_bump_grid1024_traffic.md", "hbm_bytes_per_launch", tag)
+    cflops = profile_value(f"{kernel}_bump_grid1024_traffic.md", "fp64_flop_per_launch", tag)
+    roofline, phases = roofline_of(tot, phase, hop_launches, wall, args.steps, traffic, cflops)
+
+    # the vertex-0 field against the stored exact field (every vertex)
+    max_err = None
+    if os.path.exists(GOLDEN_C3):
+        gold = np.load(GOLDEN_C3)
+        ref = gold["dist"]
+        hbar = float(gold["mean_edge"])
+        got = keep[0].cpu().numpy()
+        fin = np.isfinite(ref)
+        assert np.array_equal(fin, np.isfinite(got)), "reachability differs from the stored field"
+        max_err = float(np.max(np.abs(got[fin] - ref[fin]) / np.maximum(ref[fin], hbar)))
+
+    print("bench: icosphere and batched legs", file=sys.stderr, flush=True)
+    ico = None if args.no_icosphere else measure_icosphere(args, pch, G, torch)
+    batched = None if args.no_batched else measure_batched(pch, G, torch)
+    concurrent = None
+    if not args.no_batched:
+        mi = G.config_mesh(2)
+        dmi = pch.Mesh.from_generated(mi)
+        concurrent = measure_concurrent(pch, mi, dmi, torch)
+        dmi.close()
 
     cpu = None
-    max_err = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        hbar = float(O.lengths(m).mean())
-        n, t_cpu, errs = 0, 0.0, []
-        while n < len(keep) and (t_cpu < args.cpu_seconds or n < 2):
-            s = int(srcs[args.warmup + n])
-            tc = time.perf_counter()
-            ref, _ = O.ich(m, [s])
-            t_cpu += time.perf_counter() - tc
-            got = keep[n].cpu().numpy()
-            errs.append(float(np.max(np.abs(got - ref) / np.maximum(ref, hbar))))
-            n += 1
-        cpu = {"value": round(1000.0 * t_cpu / n, 3), "unit": "ms", "cores": 1, "kind": "oracle",
-               "sample": f"{n} fields (the first timed sources) on the same mesh, sequential ICH on one core"}
-        max_err = max(errs)
-
-    batched = None if args.no_batched else measure_batched(pch, G, torch)
-    concurrent = None if args.no_batched or args.select != 1 else measure_concurrent(args, pch, m, mesh, srcs, keep,
-                                                                                       torch)
+    if child is not None:
+        c = finish_cpu_child(child)
+        full = None
+        if os.path.exists(GOLDEN_C3):
+            full = int(np.load(GOLDEN_C3)["processed"])
+        rate = c["processed"] / c["seconds"]
+        cpu = {"value": round(1000.0 * full / rate, 1) if full else None, "unit": "ms", "cores": 1,
+               "kind": "oracle", "windows_per_s": round(rate, 1), "nproc": c["nproc"], "cpu_model": c["cpu_model"],
+               "sample": f"sequential ICH on one core, the vertex-0 field of the same mesh stopped after its first "
+                         f"{c['processed']:,} propagated windows ({c['seconds']:.1f} s); value = the full field's "
+                         f"{full:,} ICH windows at the sample's rate" if full else "no stored full-field count"}
 
     line = {
         "metric": "ms per exact single-source field",
@@ -330,8 +480,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, one seeded random "
-                               "source per field", "faces": m.nf, "vertices": m.nv, "k": args.k,
+        "config": {"workload": "1024 x 1024 jittered bump grid (16 Gaussian bumps, seed 2), 2,093,058 faces; the "
+                               "first timed field from vertex 0, the others from seeded random vertices",
+                   "faces": m.nf, "vertices": m.nv, "k": args.k,
                    "select": ["kth", "adaptive-step"][args.select], "hops": args.hops,
                    "propagation_launches_per_round": hop_launches},
         "windows_per_s": round(tot["processed"] / wall, 1),
@@ -340,7 +491,9 @@ def main():
         "rounds_per_field": round(tot["rounds"] / args.steps, 1),
         "max_rel_err_vs_oracle": max_err,
         "roofline": roofline,
+        "phases": phases,
         "cpu_baseline": cpu,
+        "icosphere": ico,
         "batched": batched,
         "same_mesh_concurrent": concurrent,
     }
