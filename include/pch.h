@@ -208,6 +208,27 @@ typedef struct {
 pch_status pch_geodesic(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist,
                         void* hip_stream, const pch_options* opts, pch_stats* stats);
 
+/* pch_geodesic for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same fields, bit for bit, and the same arguments, but no hipMalloc,
+ * hipFree or other allocation. The work buffers of the field (window pools,
+ * selection, event buffers, and the device copies of the sources, cutoff
+ * table and predicted-distance table) come from one static device array of
+ * 256 MiB per GPU, which the library holds until the process ends; the mesh
+ * handle's own state (created by pch_mesh_create) is used as by
+ * pch_geodesic. Limits: at most 1024 sources; the work buffers of a pool of
+ * capacity c take about 572 c bytes (c = opts->pool_capacity, else
+ * max(2^18, 2 * 3 nf)), so the default capacity fits meshes up to about
+ * 78,000 faces, and larger ones with a smaller pool_capacity (an overflowing
+ * pool doubles within the 256 MiB). A field that would need more returns
+ * PCH_EOVERFLOW before any device work. opts may not set collect_timing,
+ * collect_stats, organize, or hops > 1 with fuse_hops = 0 (PCH_EINVAL);
+ * round_graph is ignored (instantiating a graph allocates).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two host threads, or two streams) race and must not be made. */
+pch_status pch_geodesic_noalloc(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist,
+                                void* hip_stream, const pch_options* opts, pch_stats* stats);
+
 /* Per-round integer log of the last pch_geodesic call on this mesh that had
  * opts->collect_stats set, one int64 [14] record per round:
  *   pool size at round start, cutoff (bit pattern >> shift, -1 = all or

@@ -68,8 +68,9 @@ constexpr int kHistBins = 4096;
 constexpr int kSmallGrid = 128;
 constexpr u64 kAllOnes = ~0ull;
 constexpr int64_t kMaxRounds = 1 << 24;
-// sources kept in a stack array before they are sorted
+// the no-alloc entry point: its work buffers live in `scratch` (below)
 constexpr int kNoallocMaxSources = 1024;
+constexpr size_t kScratchBytes = (size_t)256 << 20;
 
 // constants of the window arithmetic (same values as the method description)
 constexpr double kTau = 1e-12;             // endpoint / occupancy tolerance, relative to L
@@ -2747,6 +2748,11 @@ __global__ void k_batch_reset(BatchDev B) {
 
 }  // namespace
 
+// Work buffers of pch_geodesic_noalloc: one array per GPU, held until the
+// process ends. Host code never uses this name as an address: each device's
+// address comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 int pch::set_error(int s, const std::string& msg) {
   t_err = msg;
   return s;
@@ -2759,7 +2765,7 @@ int pch::set_error(int s, const std::string& msg) {
 // The work buffers of one field: window pools, selection, hop queues, events,
 // and the per-call tables (sources, cutoff table, predicted-distance table,
 // round log). pch_geodesic keeps them in the mesh handle and grows them on
-// demand; carve_work lays them out in a fixed device arena instead.
+// demand; the no-alloc entry point carves them from its static scratch array.
 struct WorkBufs {
   int64_t cap = 0, ecap = 0, acap = 0;
   Pool pool[2] = {};
@@ -2893,7 +2899,7 @@ pch_status ensure_work(pch_mesh_s* M, int64_t cap, bool hop_queues) {
   return PCH_OK;
 }
 
-// Device memory that a field's work buffers can be carved from.
+// Device memory that the no-alloc entry point takes its work buffers from.
 struct ScratchArena {
   char* base;
   size_t bytes;
@@ -3279,7 +3285,7 @@ pch_status pch_round_log(pch_mesh M, int64_t* out, int64_t max_rounds, int64_t* 
 
 // Algorithm 1 on one mesh. sc == nullptr: the work buffers live in the mesh
 // handle and grow on demand (pch_geodesic); otherwise they are carved from
-// the arena and nothing is allocated.
+// the arena and nothing is allocated (pch_geodesic_noalloc).
 static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
                                 const pch_options* opts, pch_stats* stats, const ScratchArena* sc) {
   auto t_start = std::chrono::steady_clock::now();
@@ -3304,10 +3310,10 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
   if (o.hops < 1 || o.hops > kMaxHops) return set_err(PCH_EINVAL, "hops must be in [1, 16]");
   const bool fused_hops = o.fuse_hops != 0 && o.hops <= kFuseHops;
   if (sc) {
-    if (m > kNoallocMaxSources) return set_err(PCH_EINVAL, "an arena run takes at most 1024 sources");
+    if (m > kNoallocMaxSources) return set_err(PCH_EINVAL, "the no-alloc entry point takes at most 1024 sources");
     if (o.collect_timing || o.collect_stats || o.organize || (o.hops > 1 && !fused_hops))
       return set_err(PCH_EINVAL,
-                     "an arena run does not take collect_timing, collect_stats, organize or unfused hops");
+                     "the no-alloc entry point does not take collect_timing, collect_stats, organize or unfused hops");
   }
   const pch::HostMesh& H = M->host;
   // the sources, sorted and without duplicates (a stack array for up to
@@ -3340,7 +3346,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
                                    o.select_mode == PCH_SELECT_LEARNED);
     if (need > sc->bytes)
       return set_err(PCH_EOVERFLOW, "the field needs " + std::to_string(need >> 20) +
-                                        " MiB of work buffers, more than the arena of " +
+                                        " MiB of work buffers, more than the no-alloc scratch of " +
                                         std::to_string(sc->bytes >> 20) + " MiB");
   } else if ((int64_t)nsrc > M->dsrc_cap) {
     (void)hipFree(M->w.dsrc);
@@ -3404,7 +3410,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
       // a restart with a larger pool stays inside the arena or fails
       const size_t need = carve_work(wl, sc->base, sc->bytes, cap, nsrc, use_table ? o.n_cutoff : 0,
                                      o.select_mode == PCH_SELECT_LEARNED);
-      if (need > sc->bytes) return set_err(PCH_EOVERFLOW, "window pool outgrew the arena");
+      if (need > sc->bytes) return set_err(PCH_EOVERFLOW, "window pool outgrew the no-alloc scratch");
     } else {
       pch_status s = ensure_work(M, cap, o.hops > 1 && !fused_hops);
       if (s != PCH_OK) return s;
@@ -3458,7 +3464,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     u64 rounds_before = 0;
     // rounds_per_sync rounds from a captured graph: only without timing
     // events, with an even chunk (every chunk starts at parity 0), and not in
-    // an arena run (instantiating a graph allocates)
+    // the no-alloc entry point (instantiating a graph allocates)
     const bool graph = o.round_graph != 0 && !o.collect_timing && o.rounds_per_sync % 2 == 0 && !sc;
     for (;;) {
       if (graph) {
@@ -3574,6 +3580,43 @@ pch_status pch_geodesic(pch_mesh M, const int32_t* sources, int32_t m, double* d
   return geodesic_core(M, sources, m, dist, hip_stream, opts, stats, nullptr);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+pch_status noalloc_scratch(ScratchArena* out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDev] = {};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) return set_err(PCH_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(PCH_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptr[dev] = p;
+  }
+  *out = ScratchArena{static_cast<char*>(ptr[dev]), kScratchBytes};
+  return PCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pch_status pch_geodesic_noalloc(pch_mesh M, const int32_t* sources, int32_t m, double* dist, void* hip_stream,
+                                const pch_options* opts, pch_stats* stats) {
+  if (!M || !sources || !dist) return set_err(PCH_EINVAL, "null pointer argument");
+  ScratchArena arena;
+  const pch_status s = noalloc_scratch(&arena);
+  if (s != PCH_OK) return s;
+  return geodesic_core(M, sources, m, dist, hip_stream, opts, stats, &arena);
+}
 
 }  // extern "C"
 

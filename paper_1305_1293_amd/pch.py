@@ -27,7 +27,7 @@ ROUND_LOG_FIELDS = ["N", "cutbits", "shift", "sel", "stale", "kids", "tiny", "ic
 
 # every entry point declared in include/pch.h
 EXPORTS = ["pch_mesh_create", "pch_mesh_create_from_lengths", "pch_mesh_destroy", "pch_mesh_info",
-           "pch_mesh_vertex_tables", "pch_options_default", "pch_geodesic", "pch_round_log",
+           "pch_mesh_vertex_tables", "pch_options_default", "pch_geodesic", "pch_geodesic_noalloc", "pch_round_log",
            "pch_status_string", "pch_last_error"]
 
 
@@ -86,6 +86,7 @@ def lib():
         L.pch_options_default.argtypes = [ctypes.POINTER(Options)]
         L.pch_options_default.restype = None
         L.pch_geodesic.argtypes = [P, P, i32, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
+        L.pch_geodesic_noalloc.argtypes = [P, P, i32, P, P, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
         L.pch_round_log.argtypes = [P, P, i64, P]
         _lib = L
         for n in EXPORTS:
@@ -186,8 +187,11 @@ def options(**kw) -> Options:
     return o
 
 
-def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_stats: bool = False, **opts):
-    """Exact geodesic distance from ``sources`` at every vertex (device float64 tensor)."""
+def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_stats: bool = False,
+             noalloc: bool = False, **opts):
+    """Exact geodesic distance from ``sources`` at every vertex (device float64
+    tensor). noalloc=True calls pch_geodesic_noalloc (no device allocation in
+    the call; pass ``out``)."""
     import torch
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     if out is None:
@@ -196,8 +200,9 @@ def geodesic(mesh: Mesh, sources: Sequence[int], out=None, stream=None, return_s
         raise ValueError("out must be a contiguous float64 CUDA tensor with nv elements")
     o = options(**opts)
     st = Stats()
-    _check(lib().pch_geodesic(mesh.handle, src.ctypes.data, src.size, out.data_ptr(), _stream_handle(stream),
-                              ctypes.byref(o), ctypes.byref(st)))
+    fn = lib().pch_geodesic_noalloc if noalloc else lib().pch_geodesic
+    _check(fn(mesh.handle, src.ctypes.data, src.size, out.data_ptr(), _stream_handle(stream), ctypes.byref(o),
+              ctypes.byref(st)))
     return (out, st.as_dict()) if return_stats else out
 
 
