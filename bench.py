@@ -55,6 +55,10 @@ PROP_READ_BYTES = 56 + 64 + 24 + 16
 WINDOW_BYTES = 56        # one child window written
 DIST_EVENT_BYTES = 20    # vertex id, distance, incoming angle
 ANGLE_EVENT_BYTES = 20   # oriented edge id, distance, crossing
+# the selection's pool scan, per live window it does not select: key and
+# sigma (16), half-edge and pseudo-source (8), geod_dist of the pseudo-source
+# (8); a selected window's record is counted once, in PROP_READ_BYTES
+SCAN_BYTES = 32
 # Algorithmic FP64 operations (add, mul, div, sqrt) of Algorithm 2: the apex
 # crossing, occupancy test and apex distance of a window, and the interval,
 # unfolded pseudo-source, filter distances and key of each child it examines.
@@ -151,7 +155,7 @@ def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
     torch.cuda.synchronize()
     timed = srcs[warmup:]
     keep = []
-    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0, timed_rounds=0)
+    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0, timed_rounds=0, scan_fused=0)
     phase = dict(select=0.0, propagate=0.0, organize=0.0, events=0.0)
     hop_launches = 1
     t0 = time.perf_counter()
@@ -167,7 +171,7 @@ def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cnt = dict(processed=0, rounds=0, created=0, fan_windows=0, dist_events=0, angle_events=0, tiny=0,
-               ich_dropped=0)
+               ich_dropped=0, pool_windows=0, selected=0)
     copts = dict(opts, collect_timing=0)
     for s in timed:
         _, st = pch.geodesic(mesh, [int(s)], out=out, return_stats=True, counts=1, **copts)
@@ -182,6 +186,9 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
     kids = tot["created"] - tot["fan_windows"]
     prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
                   + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
+    fused_scan = tot["scan_fused"] > 0
+    if fused_scan:  # the same launch scans the pool
+        prop_bytes += SCAN_BYTES * (tot["pool_windows"] - tot["selected"])
     flops = FLOP_PER_WINDOW * tot["processed"] + FLOP_PER_CHILD * (kids + tot["tiny"] + tot["ich_dropped"])
     # every round launches the propagation kernel once (all hops fused) or
     # once per hop; the HIP events bracket the phases of every n-th round
@@ -192,7 +199,7 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
     flops_per_launch = flops / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     tflops = flops_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
-    kernel = "k_propagate_fused" if hop_launches == 1 else "k_propagate"
+    kernel = "k_select_propagate" if fused_scan else ("k_propagate_fused" if hop_launches == 1 else "k_propagate")
     fp64 = {"bound": "fp64", "achieved": round(tflops, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / FP64_PEAK_TFLOPS, 6), "alg_flop_per_launch": round(flops_per_launch, 1),
             "counter_flop_per_launch": counter_flops}
@@ -226,7 +233,8 @@ def measure_icosphere(args, pch, G, torch):
         ref, _ = O.ich(m, [int(srcs[args.warmup + i])])
         errs.append(float(np.max(np.abs(keep[i].cpu().numpy() - ref) / np.maximum(ref, hbar))))
     mesh.close()
-    traffic = profile_value("k_propagate_fused_icosphere7_traffic.md", "hbm_bytes_per_launch",
+    kernel = "k_select_propagate" if tot["scan_fused"] else "k_propagate_fused"
+    traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch",
                             "select=1 k=12288 hops=5 fuse_hops=1")
     roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, None)
     return {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, seeded random sources",
@@ -236,17 +244,28 @@ def measure_icosphere(args, pch, G, torch):
             "max_rel_err_vs_oracle": max(errs), "roofline": roof, "phases": phases}
 
 
-def measure_batched(pch, G, torch):
-    """512 fields in one persistent launch against the single-field path run
-    field after field: with the batch's own rule, k and hops, with the best
-    single-field setting, and with plain k-th-key selection."""
+def measure_batched(args, pch, G, torch):
+    """512 fields in one persistent launch, with the options the autotuner
+    recorded for the batch's size bucket (a tuning run when it has none),
+    against the single-field path run field after field: with the batch's
+    own rule, k and hops, with the best single-field setting, and with plain
+    k-th-key selection."""
     gens = G.batch_meshes(3)
     meshes = [pch.Mesh.from_generated(m) for m in gens]
     fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
     fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
-    opts = dict(k=32768, team_threads=512, teams_per_cu=1, hops=4, gang=8)
-    b = pch.Batch(meshes, fm, fs, **opts)
-    out, _ = b.run()  # first run captures the graph and measures each field's time
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        pch.tune_cache_load(args.tune_cache)
+    b = pch.Batch(meshes, fm, fs, k=32768, team_threads=512, teams_per_cu=1, hops=4, gang=8)
+    out = b.empty_output()
+    t0 = time.perf_counter()
+    chosen, hit = b.tune_cached(out)
+    tune_s = time.perf_counter() - t0
+    if not hit and args.tune_cache_save:
+        pch.tune_cache_save(args.tune_cache_save)
+    opts = {k: chosen[k] for k in ("k", "team_threads", "teams_per_cu", "hops", "gang")}
+    k_b, hops_b = int(opts["k"]), int(opts["hops"])
+    out, _ = b.run(out)  # first run captures the graph and measures each field's time
     dt, (out, st) = _timed(torch, lambda: b.run(out))
     batch_ms = 1000.0 * dt
     windows = int(b.field_stats()[:, 2].sum())
@@ -261,7 +280,7 @@ def measure_batched(pch, G, torch):
         for j in (1, 2):
             t, d = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=kbest, select_mode=0))
             tp += t
-            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=32768, select_mode=1, hops=4))
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=k_b, select_mode=1, hops=hops_b))
             ts += t
             t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=5))
             tb += t
@@ -276,10 +295,12 @@ def measure_batched(pch, G, torch):
         dm.close()
     return {"fields": int(fm.size), "meshes": len(gens), "faces": [int(m.nf) for m in gens], "ms": round(batch_ms, 2),
             "ms_per_field": round(batch_ms / fm.size, 4), "windows_per_s": round(windows / dt, 1), "options": opts,
+            "tuner": {"cache_hit": hit, "seconds": round(tune_s, 2),
+                      "bucket": "largest mesh, total half-edges and field count by power of two"},
             "single_field_ms_est": {"same_rule": round(same_ms, 1), "best_setting": round(best_ms, 1),
                                     "plain_kth": round(plain_ms, 1)},
             "single_field_settings": {
-                "same_rule": "adaptive step, k 32768, 4 hops (the batch's own rule: equal results bit for bit)",
+                "same_rule": "adaptive step with the batch's k and hops (equal results bit for bit)",
                 "best_setting": "adaptive step, k 12288, 5 hops in one launch per round",
                 "plain_kth": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on "
                              "its first source"},
@@ -306,6 +327,57 @@ def measure_concurrent(pch, m, mesh, torch):
     return {"fields": int(fs.size), "ms": round(1000.0 * dt, 2), "ms_per_field": round(1000.0 * dt / fs.size, 4),
             "windows_per_s": round(windows / dt, 1), "options": opts, "reruns": int(st["reruns"]),
             "equal_to_single_field_runs": bool(same), "roofline": batch_roofline(windows / dt)}
+
+
+def measure_learned_batched(pch, G, Lr, mlp, torch):
+    """The learned cutoff in the batched launch: the 512 fields of the batch
+    workload with the network's predictions, against the same batch with the
+    chord lengths (no network) and with the adaptive step, and against plain
+    PCH field by field (k-th-key selection, one face per round)."""
+    gens = G.batch_meshes(3)
+    meshes = [pch.Mesh.from_generated(m) for m in gens]
+    fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
+    fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
+    opts = dict(k=32768, team_threads=512, teams_per_cu=1, hops=4, gang=8)
+    res, outs = {}, {}
+    for name in ("learned", "chord", "adaptive_step"):
+        if name == "adaptive_step":
+            b = pch.Batch(meshes, fm, fs, **opts)
+        else:
+            off = np.zeros(fm.size + 1, np.int64)
+            off[1:] = np.cumsum([gens[i].nv for i in fm])
+            t0 = time.perf_counter()
+            pred = Lr.batch_predictions(mlp, gens, fm, fs, off, chord=name == "chord")
+            torch.cuda.synchronize()
+            tpred = time.perf_counter() - t0
+            b = pch.Batch(meshes, fm, fs, predicted=pred, **opts)
+        out, _ = b.run()
+        dt, (out, st) = _timed(torch, lambda: b.run(out))
+        res[name] = {"ms": round(1000.0 * dt, 2), "reruns": int(st["reruns"]),
+                     "windows": int(b.field_stats()[:, 2].sum()), "max_rounds": int(st["max_rounds"])}
+        if name != "adaptive_step":
+            res[name]["predict_ms"] = round(1000.0 * tpred, 2)
+        outs[name] = out.cpu().numpy()
+        b.close()
+    ref = outs["adaptive_step"]
+    diff = max(float(np.max(np.abs(outs[n] - ref) / np.maximum(ref, 1e-3))) for n in ("learned", "chord"))
+    ks = (4096, 8192, 16384, 32768)
+    plain_ms = 0.0
+    for g, dm in zip(gens, meshes):
+        srcs = [int(x) for x in g.meta["sources"]]
+        times = {k: _timed(torch, lambda: pch.geodesic(dm, [srcs[0]], k=k, select_mode=0))[0] for k in ks}
+        kbest = min(times, key=times.get)
+        tt = sum(_timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=kbest, select_mode=0))[0] for j in (1, 2))
+        plain_ms += 1000.0 * 32 * tt / 2
+    for dm in meshes:
+        dm.close()
+    lb = res["learned"]["ms"] + res["learned"]["predict_ms"]
+    return {"fields": int(fm.size), "options": opts, "runs": res, "plain_kth_ms_est": round(plain_ms, 1),
+            "learned_batched_vs_plain": round(plain_ms / lb, 3),
+            "learned_batched_vs_adaptive_batched": round(res["adaptive_step"]["ms"] / lb, 3),
+            "learned_vs_chord_batched": round((res["chord"]["ms"] + res["chord"]["predict_ms"]) / lb, 3),
+            "max_rel_diff_vs_adaptive": diff,
+            "note": "learned and chord times include the predictions of all 512 fields (predict_ms)"}
 
 
 def measure_learned(args, pch, G, torch):
@@ -344,6 +416,7 @@ def measure_learned(args, pch, G, torch):
         dm.close()
     mean = {n: np.array(rows[n]).mean(axis=0) for n in names}
     ms = {n: round(1000 * float(mean[n][0]), 2) for n in names}
+    batched = measure_learned_batched(pch, G, Lr, mlp, torch)
     return {"metric": "learned-cutoff vs plain speedup (ms per exact single-source field)",
             "value": round(ms["kth"] / ms["learned"], 4), "unit": "x", "higher_is_better": True,
             "n_gpus": 1, "dtype": "f64 fields, bf16/f32 network", "data": "synthetic",
@@ -355,6 +428,7 @@ def measure_learned(args, pch, G, torch):
             "rounds_per_field": {n: float(mean[n][1]) for n in names},
             "windows_per_field": {n: float(mean[n][2]) for n in names},
             "max_rel_diff_vs_learned": err,
+            "batched": batched,
             "training": {"samples": int(data.feats.shape[0]), "seconds": round(train_s, 2),
                          "loss_first": losses[0], "loss_last": losses[-1]}}
 
@@ -365,22 +439,25 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["field", "learned"], default="field")
-    ap.add_argument("--k", type=int, default=131072, help="windows selected per round (bump grid)")
+    ap.add_argument("--k", type=int, default=524288, help="windows selected per round (bump grid)")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
-    ap.add_argument("--hops", type=int, default=5, help="propagation hops per round")
+    ap.add_argument("--hops", type=int, default=4, help="propagation hops per round")
     ap.add_argument("--fuse-hops", type=int, default=1,
                     help="1: all hops of a round in one propagation launch (hops <= 6); 0: one launch per hop")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
     ap.add_argument("--no-icosphere", action="store_true", help="skip the icosphere measurement")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
-    ap.add_argument("--hops-learned", type=int, default=5, help="hops of the learned-cutoff comparison")
+    ap.add_argument("--hops-learned", type=int, default=4, help="hops of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
     ap.add_argument("--time-every", type=int, default=8,
                     help="time the phases of every n-th round with HIP events")
     ap.add_argument("--cpu-windows", type=int, default=CPU_SAMPLE_WINDOWS,
                     help="windows of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1305_1293_amd", "tune_cache.txt"),
+                    help="autotuner cache read before the batched measurement")
+    ap.add_argument("--tune-cache-save", default="", help="write the autotuner cache here after a tuning run")
     ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 5 times (the reference "
@@ -428,7 +505,7 @@ def main():
     wall, tot, phase, hop_launches, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=1)
     ms_per_field = 1000.0 * wall / args.steps
     tag = f"select={args.select} k={args.k} hops={args.hops} fuse_hops={args.fuse_hops}"
-    kernel = "k_propagate_fused" if hop_launches == 1 else "k_propagate"
+    kernel = "k_select_propagate" if tot["scan_fused"] else ("k_propagate_fused" if hop_launches == 1 else "k_propagate")
     traffic = profile_value(f"{kernel}_bump_grid1024_traffic.md", "hbm_bytes_per_launch", tag)
     cflops = profile_value(f"{kernel}_bump_grid1024_traffic.md", "fp64_flop_per_launch", tag)
     roofline, phases = roofline_of(tot, phase, hop_launches, wall, args.steps, traffic, cflops)
@@ -446,7 +523,7 @@ def main():
 
     print("bench: icosphere and batched legs", file=sys.stderr, flush=True)
     ico = None if args.no_icosphere else measure_icosphere(args, pch, G, torch)
-    batched = None if args.no_batched else measure_batched(pch, G, torch)
+    batched = None if args.no_batched else measure_batched(args, pch, G, torch)
     concurrent = None
     if not args.no_batched:
         mi = G.config_mesh(2)

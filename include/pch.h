@@ -191,6 +191,14 @@ typedef struct {
                                 [3] events (Algorithm 4 and the next round's
                                 set-up) */
   int64_t timed_rounds;      /* rounds timed in ms_phase */
+  int64_t pool_windows;      /* sum over rounds of the live windows in the
+                                pool at round start (what the selection
+                                scans) */
+  int64_t selected;          /* windows the selection took from the pool,
+                                summed over rounds (processed minus those that
+                                hopped on); with counts only */
+  int32_t scan_fused;        /* 1 when the pool scan ran inside the
+                                propagation launch (fuse_scan) */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).
@@ -344,6 +352,19 @@ pch_status pch_batch_field_stats(pch_batch batch, int64_t* out);
  * best of those, each on the whole batch (into dist); keeps the fastest in
  * the batch and returns it in chosen (may be NULL). */
 pch_status pch_batch_tune(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen);
+
+/* Tuner cache. pch_batch_tune records its choice for the batch's size
+ * bucket: the GPU architecture, and floor(log2) of the largest mesh's
+ * half-edges, of the half-edges summed over the fields, and of the field
+ * count. pch_batch_tune_cached applies the recorded choice for the batch's
+ * bucket (*hit = 1, no trial runs), or runs pch_batch_tune when there is none
+ * (*hit = 0). The cache lives in the process. pch_tune_cache_save and
+ * pch_tune_cache_load write and read it as text, one bucket per line (load
+ * adds to it; PCH_EINVAL on an unreadable file or a malformed line). */
+pch_status pch_batch_tune_cached(pch_batch batch, double* dist, void* hip_stream, pch_batch_options* chosen,
+                                 int32_t* hit);
+pch_status pch_tune_cache_save(const char* path);
+pch_status pch_tune_cache_load(const char* path);
 
 /* Geodesic Voronoi labels (the multi-source setting of Section 4 and the
  * paper's outlook on Voronoi diagrams): for every vertex the index in

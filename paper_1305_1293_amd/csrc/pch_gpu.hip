@@ -31,7 +31,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -90,7 +93,7 @@ enum {
   C_NEND, C_NUM
 };
 // extra counters (not in the log)
-enum { X_NOTWIN = 0, X_NUM = 4 };
+enum { X_NOTWIN = 0, X_SEL1 = 1, X_NUM = 4 };  // X_SEL1: windows the pool scans selected (hop 1)
 
 struct Ctl {
   u64 npool[2];     // slots used in pool buffer 0 and 1 (live windows and tombstones)
@@ -194,11 +197,18 @@ struct DevMesh {
   int32_t nv, nh;  // vertices and half-edges: every gathered index is checked against them
 };
 
+// geod_dist and angle_split are kept twice. The round reads g and as, the
+// values at its start (the delayed update of Remark 3), while the events it
+// raises lower gw and asw at once; the event passes then copy the values
+// that changed back into g and as, so that both pairs agree again when the
+// next round starts.
 struct DevState {
   u64* g;      // geod_dist as bit patterns (non-negative doubles order as u64)
   Split* as;   // angle_split per oriented edge
   u64* fanth;  // smallest incoming angle key among this round's winning events
   u32* claim;  // round stamp of the last fan expanded at a vertex
+  u64* gw;     // geod_dist taking this round's minima
+  Split* asw;  // angle_split taking this round's minima
 };
 
 struct RoundArgs {
@@ -724,6 +734,10 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
       }
       kept++;
     }
+    // deferred events lower geod_dist's write copy now; they are recorded in
+    // the next round's event buffer, whose passes copy the winners back
+    if (o.ea) atomicMin(&a.s.gw[o.va], bits(o.da));
+    if (o.eb) atomicMin(&a.s.gw[o.vb], bits(o.db));
     if (o.ea) {
       if (je < (u64)a.ecap) {
         E.vq[je] = make_int2(o.va, -1);
@@ -844,12 +858,12 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
   for (int f = 0; f < C_NUM; ++f) c->cnt[f] = 0;
   c->cnt[C_N] = N;
   // the pool: keep the windows in place while at most half of the slots are
-  // tombstones and half of the buffer is used, else compact them into the
-  // other buffer
+  // tombstones and at most a quarter of the buffer is used (the round
+  // appends to the rest), else compact them into the other buffer
   c->pin = pout;
   c->nscan = slots;
   c->keptin = 0;
-  if (slots - N > N || slots > (u64)a.cap / 2) {
+  if (slots - N > N || slots > (u64)a.cap / 4) {
     c->pout = pout ^ 1;
     c->npool[(pout ^ 1) & 1] = 0;
     c->s0 = 0;
@@ -983,9 +997,9 @@ __global__ void k_fill_u32(u32* p, int64_t n, u32 v) {
     p[i] = v;
 }
 
-__global__ void k_set_sources(u64* g, const int32_t* src, int m) {
+__global__ void k_set_sources(u64* g, u64* gw, const int32_t* src, int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) g[src[i]] = 0ull;
+  if (i < m) g[src[i]] = gw[src[i]] = 0ull;
 }
 
 // Initialization (Algorithm 1, lines 1-2): every source gets a full fan into
@@ -1554,7 +1568,10 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   if (cr) put_child(qr, rb0, rb1, rpx, rpy, rkey, re);
   // the incoming angle of an event at a pseudo-source is evaluated later,
   // only for the events that win their vertex (event_angle)
+  // each event lowers geod_dist's write copy at once and is recorded for
+  // the event passes (winners, fans)
   auto put_event = [&](int32_t v, double dv, int32_t q) {
+    atomicMin(&a.s.gw[v], bits(dv));
     const u64 j = jd++;
     if (j < (u64)a.ecap) {
       x.E.vq[j] = make_int2(v, q);
@@ -1568,6 +1585,10 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   if (e1) put_event(ev1, ed1, eq1);
   if (e2) put_event(ev2, ed2, eq2);
   if (has_aev) {
+    // the corner's write copy takes the apex distance at once; a corner whose
+    // distance improves forgets its old crossing (the crossings are compared
+    // in the second event pass)
+    if (atomicMin(&a.s.asw[e].D, bits(aD)) > bits(aD)) a.s.asw[e].X = kAllOnes;
     if (ja < (u64)a.acap) {
       a.aev.e[ja] = e;
       a.aev.D[ja] = aD;
@@ -1642,10 +1663,12 @@ __device__ __forceinline__ void ph_propagate(const RoundArgs& a, int p, int hop,
   const double cv = c->cutval;
   const PropCtx x{Q, &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
   if (t0 == 0 && active) {
-    if (hop <= 1)
+    if (hop <= 1) {
       c->cnt[C_SEL] = n_in;
-    else
+      if (a.counts) atomicAdd(&c->xcnt[X_SEL1], n_in);
+    } else {
       c->cnt[C_SEL] = c->cnt[C_SEL] + n_in;
+    }
   }
   PropAcc acc;
   for (u64 i = t0; i - lane_id() < N; i += stride) {
@@ -1764,7 +1787,10 @@ __global__ void __launch_bounds__(kBlock) k_propagate_fused(RoundArgs a, int p) 
   const u64 pout = c->pout;
   const PropCtx x{pout ? a.pool[1] : a.pool[0], &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
   const int hops = a.hops < kTop ? a.hops : kTop;
-  if (t0 == 0 && active) atomicAdd(&c->cnt[C_SEL], n_in);
+  if (t0 == 0 && active) {
+    atomicAdd(&c->cnt[C_SEL], n_in);
+    if (a.counts) atomicAdd(&c->xcnt[X_SEL1], n_in);
+  }
   __syncthreads();
   PropAcc acc;
   u64 base = blockIdx.x * (u64)kBlock;  // the workgroup's next chunk of the selection
@@ -1934,6 +1960,7 @@ __global__ void __launch_bounds__(kBlock) k_select_propagate(RoundArgs a, int p)
     if (tot[0] && a.counts) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
     if (tot[1]) atomicAdd(&c->keptin, (u64)tot[1]);
     if (tot[2] + hopped) atomicAdd(&c->cnt[C_SEL], (u64)tot[2] + hopped);
+    if (tot[2] && a.counts) atomicAdd(&c->xcnt[X_SEL1], (u64)tot[2]);
   }
   prop_finish(a, p, acc);
 }
@@ -1965,36 +1992,14 @@ __device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u
   return f;
 }
 
-__device__ __forceinline__ void ph_events1(const RoundArgs& a, int p, u64 t0, u64 stride) {
-  Ctl* c = a.ctl;
-  const FirstEvents f = first_events(a, p, t0);
-  const bool active = c->active != 0;
-  const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
-  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
-  for (u64 i = t0; i < nd; i += stride) {
-    const int32_t v = i == t0 ? f.vq.x : a.ev[p].vq[i].x;
-    const double d = i == t0 ? f.d : a.ev[p].d[i];
-    if (idx_ok(c, v, a.m.nv)) atomicMin(&a.s.g[v], bits(d));
-  }
-  for (u64 i = t0; i < na; i += stride) {
-    const int32_t e = i == t0 ? f.e : a.aev.e[i];
-    const double D = i == t0 ? f.D : a.aev.D[i];
-    if (!idx_ok(c, e, a.m.nh)) continue;
-    // a corner whose apex distance improves forgets its old crossing (the
-    // crossings are only compared in the next pass)
-    if (atomicMin(&a.s.as[e].D, bits(D)) > bits(D)) a.s.as[e].X = kAllOnes;
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_events1(RoundArgs a, int p) {
-  ph_events1(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
-}
-
-// Second pass: each corner keeps the smallest crossing among the angle events
-// that reached its (new or unchanged) apex distance, together with a kept old
-// crossing: the lexicographic minimum of (distance, crossing). Each improved
-// pseudo-source vertex records the smallest incoming angle among the events
-// that reached its new distance.
+// Algorithm 4, first event pass (the minima themselves were taken by the
+// propagation and the previous round's fans, in geod_dist's and
+// angle_split's write copies): each corner keeps the smallest crossing among
+// the angle events that reached its (new or unchanged) apex distance,
+// together with a kept old crossing: the lexicographic minimum of (distance,
+// crossing). An event that reached its vertex's new distance copies it into
+// geod_dist, and each improved pseudo-source vertex records the smallest
+// incoming angle among those events.
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
@@ -2005,14 +2010,16 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     const int32_t e = i == t0 ? f.e : a.aev.e[i];
     const double D = i == t0 ? f.D : a.aev.D[i];
     const double X = i == t0 ? f.X : a.aev.X[i];
-    if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.as[e].D)) atomicMin(&a.s.as[e].X, ordkey(X));
+    if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.asw[e].D)) atomicMin(&a.s.asw[e].X, ordkey(X));
   }
   for (u64 i = t0; i < nd; i += stride) {
     const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
     const double d = i == t0 ? f.d : a.ev[p].d[i];
     const double2 xy = i == t0 ? f.xy : a.ev[p].xy[i];
     const int32_t v = vq.x;
-    const bool win = idx_ok(c, v, a.m.nv) && bits(d) == lda(&a.s.g[v]) && (a.m.flags[v] & pch::VF_PSEUDO);
+    const bool top = idx_ok(c, v, a.m.nv) && bits(d) == lda(&a.s.gw[v]);
+    if (top) a.s.g[v] = bits(d);
+    const bool win = top && (a.m.flags[v] & pch::VF_PSEUDO);
     double th = 0.0;
     if (win) {
       // the incoming angle of an event that wins a pseudo-source vertex
@@ -2043,8 +2050,10 @@ __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
   ph_events2(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
-// Third pass: one fan per improved pseudo-source vertex, windows into the
-// next pool, deferred endpoint events into the next round's event buffer.
+// Second event pass: the corners' final values into angle_split, and one fan
+// per improved pseudo-source vertex: windows into the next pool, deferred
+// endpoint events into geod_dist's write copy and the next round's event
+// buffer.
 __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   // Distance events are dealt round-robin over the launch's wavefronts (event
@@ -2063,8 +2072,15 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   }
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ncand, (u64)a.ecap) : 0;
+  const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   const u32 stamp = (u32)c->round;
   const int po = (int)(c->pout & 1);
+  // the corners this round's angle events touched take their final values
+  // (the first event pass is over) from the write copy
+  for (u64 i = t0; i < na; i += stride) {
+    const int32_t e = a.aev.e[i];
+    if (idx_ok(c, e, a.m.nh)) a.s.as[e] = a.s.asw[e];
+  }
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
   for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
@@ -2167,9 +2183,9 @@ struct BatchDev {
   double2* ev_xy;
   int32_t* ae_e;  // [n_teams][acap]
   double *ae_D, *ae_X;
-  u64 *g, *fanth;  // [n_teams][max_nv]
-  u32* claim;      // [n_teams][max_nv]
-  Split* as;       // [n_teams][max_nh]
+  u64 *g, *gw, *fanth;  // [n_teams][max_nv]
+  u32* claim;           // [n_teams][max_nv]
+  Split *as, *asw;      // [n_teams][max_nh]
   int64_t cap, ecap, acap, max_nv, max_nh;
   int64_t k;
   double eps;
@@ -2292,7 +2308,8 @@ __device__ __forceinline__ Pool slot_pool(const BatchDev& B, int t, int b) {
 __device__ __forceinline__ void team_args(const BatchDev& B, int t, int f, RoundArgs& a) {
   const int mi = B.field_mesh[f];
   a.m = B.meshes[mi];
-  a.s = DevState{B.g + t * B.max_nv, B.as + t * B.max_nh, B.fanth + t * B.max_nv, B.claim + t * B.max_nv};
+  a.s = DevState{B.g + t * B.max_nv,     B.as + t * B.max_nh,  B.fanth + t * B.max_nv,
+                 B.claim + t * B.max_nv, B.gw + t * B.max_nv, B.asw + t * B.max_nh};
   a.pool[0] = slot_pool(B, t, 0);
   a.pool[1] = slot_pool(B, t, 1);
   a.sel = slot_pool(B, t, 2);
@@ -2340,7 +2357,6 @@ __device__ __noinline__ void nl_partition(const RoundArgs& a, int p, u64 t0, u64
 __device__ __noinline__ void nl_propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 s) {
   ph_propagate(a, p, hop, t0, s);
 }
-__device__ __noinline__ void nl_events1(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events1(a, p, t0, s); }
 __device__ __noinline__ void nl_events2(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events2(a, p, t0, s); }
 __device__ __noinline__ void nl_events3(const RoundArgs& a, int p, u64 t0, u64 s) { ph_events3(a, p, t0, s); }
 __device__ __noinline__ void nl_begin(const RoundArgs& a, int p) { round_begin(a, p); }
@@ -2377,9 +2393,6 @@ struct TeamPhases {
   static __device__ __forceinline__ void propagate(const RoundArgs& a, int p, int hop, u64 t0, u64 s) {
     if constexpr (kOOL) nl_propagate(a, p, hop, t0, s); else ph_propagate(a, p, hop, t0, s);
   }
-  static __device__ __forceinline__ void events1(const RoundArgs& a, int p, u64 t0, u64 s) {
-    if constexpr (kOOL) nl_events1(a, p, t0, s); else ph_events1(a, p, t0, s);
-  }
   static __device__ __forceinline__ void events2(const RoundArgs& a, int p, u64 t0, u64 s) {
     if constexpr (kOOL) nl_events2(a, p, t0, s); else ph_events2(a, p, t0, s);
   }
@@ -2413,8 +2426,6 @@ __device__ __forceinline__ int team_round(const RoundArgs& a, int p, int idx, in
     Ph::propagate(a, p, h, t0, stride);
     if (!bar()) return 0;
   }
-  Ph::events1(a, p, t0, stride);
-  if (!bar()) return 0;
   Ph::events2(a, p, t0, stride);
   if (!bar()) return 0;
   Ph::events3(a, p, t0, stride);
@@ -2602,12 +2613,12 @@ __global__ void __launch_bounds__(BS) k_batch(BatchDev B) {
     }
     team_sync();
     for (u64 i = t0; i < (u64)nv; i += stride) {
-      sa.s.g[i] = i == (u64)B.field_src[f] ? 0ull : 0x7ff0000000000000ull;
+      sa.s.g[i] = sa.s.gw[i] = i == (u64)B.field_src[f] ? 0ull : 0x7ff0000000000000ull;
       sa.s.fanth[i] = kAllOnes;
       sa.s.claim[i] = 0u;
     }
     for (u64 i = t0; i < (u64)nh; i += stride) {
-      sa.s.as[i] = Split{0x7ff0000000000000ull, kAllOnes};
+      sa.s.as[i] = sa.s.asw[i] = Split{0x7ff0000000000000ull, kAllOnes};
     }
     // every wavefront's initial values are in the L2 before the field is
     // offered to helpers
@@ -2793,8 +2804,8 @@ struct pch_mesh_s {
   pch::Corner* crec = nullptr;
   uint8_t* flags = nullptr;
   // state (sized with the mesh)
-  u64 *g = nullptr, *fanth = nullptr;
-  Split* as = nullptr;
+  u64 *g = nullptr, *gw = nullptr, *fanth = nullptr;
+  Split *as = nullptr, *asw = nullptr;
   u32* claim = nullptr;
   Ctl* ctl = nullptr;
   u32* hist = nullptr;
@@ -2980,6 +2991,8 @@ pch_status upload_mesh(pch_mesh_s* M, hipStream_t st) {
   HIP_TRY(dalloc(&M->coff, H.nv + 1));
   HIP_TRY(dalloc(&M->g, H.nv));
   HIP_TRY(dalloc(&M->as, H.nh));
+  HIP_TRY(dalloc(&M->gw, H.nv));
+  HIP_TRY(dalloc(&M->asw, H.nh));
   HIP_TRY(dalloc(&M->fanth, H.nv));
   HIP_TRY(dalloc(&M->claim, H.nv));
   HIP_TRY(dalloc(&M->ctl, 1));
@@ -3020,6 +3033,8 @@ void free_mesh(pch_mesh_s* M) {
   (void)hipFree(M->coff);
   (void)hipFree(M->g);
   (void)hipFree(M->as);
+  (void)hipFree(M->gw);
+  (void)hipFree(M->asw);
   (void)hipFree(M->fanth);
   (void)hipFree(M->claim);
   (void)hipFree(M->ctl);
@@ -3049,7 +3064,7 @@ RoundArgs make_args(pch_mesh_s* M, const WorkBufs& w, const pch_options& o) {
   RoundArgs a{};  // zeroed padding: captured round graphs compare arguments bytewise
   a.m = DevMesh{M->hl,    M->phi,    M->alpha, M->twin, M->hv, M->theta, M->flags, M->coff,
                  M->corner, M->crec, (int32_t)M->host.nv, (int32_t)M->host.nh};
-  a.s = DevState{M->g, M->as, M->fanth, M->claim};
+  a.s = DevState{M->g, M->as, M->fanth, M->claim, M->gw, M->asw};
   a.pool[0] = w.pool[0];
   a.pool[1] = w.pool[1];
   a.sel = w.sel;
@@ -3145,7 +3160,6 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
     if (ev) (void)hipEventRecord(ev[2], st);
     launch_select_fused(a, p, st, pool_blocks);
     if (ev) (void)hipEventRecord(ev[3], st);
-    k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
     k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
     k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
     if (ev) (void)hipEventRecord(ev[4], st);
@@ -3163,7 +3177,6 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
   else
     for (int h = 1; h <= a.hops; ++h) k_propagate<<<prop_blocks, kBlock, 0, st>>>(a, p, h);
   if (ev) (void)hipEventRecord(ev[3], st);
-  k_events1<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
   if (ev) (void)hipEventRecord(ev[4], st);
@@ -3403,6 +3416,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
   } ev_guard{tev};
   int64_t prop_n = 0, timed_rounds = 0;
   double phase_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  RoundPlan plan_used = kSplit;
   for (;;) {
     // the hop queues in device memory serve only one launch per hop (fused
     // hops keep their windows in LDS)
@@ -3429,7 +3443,9 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     a.pbin = pbin;
     const int fill_blocks = 1024;
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->g, H.nv, bits_host(INFINITY));
+    k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->gw, H.nv, bits_host(INFINITY));
     k_fill_split<<<fill_blocks, kBlock, 0, st>>>(M->as, H.nh, bits_host(INFINITY), kAllOnes);
+    k_fill_split<<<fill_blocks, kBlock, 0, st>>>(M->asw, H.nh, bits_host(INFINITY), kAllOnes);
     k_fill_u64<<<fill_blocks, kBlock, 0, st>>>(M->fanth, H.nv, kAllOnes);
     k_fill_u32<<<fill_blocks, kBlock, 0, st>>>(M->claim, H.nv, 0u);
     std::memset(&ctl_init, 0, sizeof(ctl_init));
@@ -3437,7 +3453,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     ctl_init.delta = delta0;
     ctl_init.lfac = 1.0;
     HIP_TRY(hipMemcpyAsync(M->ctl, &ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, w.dsrc, nsrc);
+    k_set_sources<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(M->g, M->gw, w.dsrc, nsrc);
     k_init_fans<<<(nsrc + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, w.dsrc, nsrc);
     k_begin<<<1, kWave, 0, st>>>(a, 0);
     HIP_TRY(hipGetLastError());
@@ -3456,6 +3472,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     // the pool scan runs inside the fused propagation unless the round needs
     // the whole selection first (strided selection, grouping by edge)
     const RoundPlan plan = (fused && o.fuse_scan != 0 && !strided && !o.organize) ? kScanFused : kSplit;
+    plan_used = plan;
     int p = 0;
     bool overflow = false;
     for (double& x : phase_ms) x = 0.0;
@@ -3466,8 +3483,14 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     // events, with an even chunk (every chunk starts at parity 0), and not in
     // the no-alloc entry point (instantiating a graph allocates)
     const bool graph = o.round_graph != 0 && !o.collect_timing && o.rounds_per_sync % 2 == 0 && !sc;
+    // Rounds enqueued before the next poll of the control block: all
+    // rounds_per_sync while the pool grows; while it shrinks, about the
+    // rounds it has left at its current rate (at least 2), so that few empty
+    // rounds are enqueued after the last one.
+    int chunk = o.rounds_per_sync;
+    u64 n_prev = 0;
     for (;;) {
-      if (graph) {
+      if (graph && chunk == o.rounds_per_sync && p == 0) {
         const int key[6] = {pool_blocks, prop_blocks, kth ? 1 : 0, fused ? 1 : 0, (int)plan, o.rounds_per_sync};
         if (!M->rg_exec || std::memcmp(key, M->rg_key, sizeof key) != 0 ||
             std::memcmp(&a, &M->rg_args, sizeof a) != 0) {
@@ -3490,7 +3513,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
         }
         HIP_TRY(hipGraphLaunch(M->rg_exec, st));
       } else {
-        for (int r = 0; r < o.rounds_per_sync; ++r) {
+        for (int r = 0; r < chunk; ++r) {
           const bool timed = o.collect_timing && ((rounds_before + (u64)r) % (u64)o.collect_timing == 0);
           enqueue_round(a, p, st, pool_blocks, prop_blocks, kth, fused,
                         timed ? &tev[kRoundEvents * (size_t)r] : nullptr, plan);
@@ -3502,7 +3525,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
       HIP_TRY(hipStreamSynchronize(st));
       if (o.collect_timing) {
         const u64 ran = host_ctl.round - rounds_before;
-        for (u64 r = 0; r < ran && r < (u64)o.rounds_per_sync; ++r) {
+        for (u64 r = 0; r < ran && r < (u64)chunk; ++r) {
           if ((rounds_before + r) % (u64)o.collect_timing != 0) continue;
           const hipEvent_t* ev = &tev[kRoundEvents * (size_t)r];
           // phases in pch_stats.ms_phase order: selection, propagation,
@@ -3516,6 +3539,17 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
           timed_rounds++;
           prop_n += fused ? 1 : o.hops;
         }
+      }
+      {
+        const u64 ran = host_ctl.round - rounds_before;
+        const u64 n_now = host_ctl.cnt[C_N];
+        chunk = o.rounds_per_sync;
+        if (ran > 0 && n_prev > n_now) {
+          const double rate = (double)(n_prev - n_now) / (double)ran;
+          const double left = (double)n_now / rate + 1.0;
+          if (left < (double)chunk) chunk = left < 2.0 ? 2 : (int)left;
+        }
+        n_prev = n_now;
       }
       rounds_before = host_ctl.round;
       if (!strided) pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
@@ -3570,6 +3604,9 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     stats->timed_rounds = timed_rounds;
     stats->propagate_launches = prop_n;
     stats->hop_launches = (o.fuse_hops != 0 && o.hops <= kFuseHops) ? 1 : o.hops;
+    stats->pool_windows = (int64_t)T[C_N];
+    stats->selected = (int64_t)host_ctl.xcnt[X_SEL1];
+    stats->scan_fused = plan_used == kScanFused ? 1 : 0;
     stats->delta0 = delta0;
   }
   return PCH_OK;
@@ -3663,7 +3700,8 @@ void free_slots(pch_batch_s* b) {
   if (!b->slots) return;
   BatchDev& B = b->B;
   for (void* p : {(void*)B.pbb, (void*)B.ppp, (void*)B.psk, (void*)B.pes, (void*)B.ev_vq, (void*)B.ev_d, (void*)B.ev_xy, (void*)B.ae_e, (void*)B.ae_D,
-                  (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.as})
+                  (void*)B.ae_X, (void*)B.g, (void*)B.fanth, (void*)B.claim, (void*)B.as, (void*)B.gw,
+                  (void*)B.asw})
     (void)hipFree(p);
   b->slots = false;
 }
@@ -3715,6 +3753,8 @@ pch_status alloc_slots(pch_batch_s* b) {
   HIP_TRY(dalloc(&B.ae_D, na));
   HIP_TRY(dalloc(&B.ae_X, na));
   HIP_TRY(dalloc(&B.g, T * b->max_nv));
+  HIP_TRY(dalloc(&B.gw, T * b->max_nv));
+  HIP_TRY(dalloc(&B.asw, T * b->max_nh));
   HIP_TRY(dalloc(&B.fanth, T * b->max_nv));
   HIP_TRY(dalloc(&B.claim, T * b->max_nv));
   HIP_TRY(dalloc(&B.as, T * b->max_nh));
@@ -4040,6 +4080,52 @@ pch_status pch_batch_field_stats(pch_batch b, int64_t* out) {
   return PCH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tuner results by batch size bucket: floor(log2) of the largest mesh's
+// half-edges, of the half-edges summed over the fields, and of the field
+// count, on one GPU architecture. Held for the process; saved to and loaded
+// from a text file by pch_tune_cache_save / pch_tune_cache_load.
+struct TuneKey {
+  std::string arch;
+  int max_nh, total_nh, fields;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, max_nh, total_nh, fields) < std::tie(o.arch, o.max_nh, o.total_nh, o.fields);
+  }
+};
+struct TuneVal {
+  int64_t k;
+  int32_t team_threads, teams_per_cu, hops, gang;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+int ilog2(int64_t x) {
+  int b = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+pch_status tune_key(pch_batch_s* b, TuneKey* key) {
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, b->device));
+  int64_t total = 0;
+  for (int32_t mi : b->fmesh) total += b->meshes[mi]->host.nh;
+  *key = TuneKey{std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':')),
+                 ilog2(b->max_nh), ilog2(total), ilog2((int64_t)b->fmesh.size())};
+  return PCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen) {
   if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
   const int64_t ks[] = {8192, 16384, 32768, 65536};
@@ -4085,7 +4171,87 @@ pch_status pch_batch_tune(pch_batch b, double* dist, void* hip_stream, pch_batch
   pch_status s = alloc_slots(b);
   if (s != PCH_OK) return s;
   if (chosen) *chosen = best;
+  TuneKey key;
+  s = tune_key(b, &key);
+  if (s != PCH_OK) return s;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = TuneVal{best.k, best.team_threads, best.teams_per_cu, best.hops, best.gang, best_ms};
   return PCH_OK;
+}
+
+pch_status pch_batch_tune_cached(pch_batch b, double* dist, void* hip_stream, pch_batch_options* chosen,
+                                 int32_t* hit) {
+  if (!b || !dist) return set_err(PCH_EINVAL, "null pointer argument");
+  TuneKey key;
+  pch_status s = tune_key(b, &key);
+  if (s != PCH_OK) return s;
+  bool found = false;
+  TuneVal v{};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      found = true;
+      v = it->second;
+    }
+  }
+  if (hit) *hit = found ? 1 : 0;
+  if (!found) return pch_batch_tune(b, dist, hip_stream, chosen);
+  b->o.k = v.k;
+  b->o.team_threads = v.team_threads;
+  b->o.teams_per_cu = v.teams_per_cu;
+  b->o.hops = v.hops;
+  b->o.gang = v.gang;
+  s = alloc_slots(b);
+  if (s != PCH_OK) return s;
+  if (chosen) *chosen = b->o;
+  return PCH_OK;
+}
+
+pch_status pch_tune_cache_save(const char* path) {
+  if (!path) return set_err(PCH_EINVAL, "null pointer argument");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return set_err(PCH_EINVAL, std::string("cannot write ") + path);
+  std::fprintf(f, "# arch max_nh_log2 total_nh_log2 fields_log2 k team_threads teams_per_cu hops gang ms\n");
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto& kv : g_tune)
+      std::fprintf(f, "%s %d %d %d %lld %d %d %d %d %.3f\n", kv.first.arch.c_str(), kv.first.max_nh,
+                   kv.first.total_nh, kv.first.fields, (long long)kv.second.k, kv.second.team_threads,
+                   kv.second.teams_per_cu, kv.second.hops, kv.second.gang, kv.second.ms);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? PCH_OK : set_err(PCH_EINVAL, std::string("cannot write ") + path);
+}
+
+pch_status pch_tune_cache_load(const char* path) {
+  if (!path) return set_err(PCH_EINVAL, "null pointer argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return set_err(PCH_EINVAL, std::string("cannot read ") + path);
+  char line[512];
+  int n = 0;
+  pch_status rc = PCH_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char arch[64];
+    TuneKey key;
+    TuneVal v;
+    long long k = 0;
+    if (std::sscanf(line, "%63s %d %d %d %lld %d %d %d %d %lf", arch, &key.max_nh, &key.total_nh, &key.fields, &k,
+                    &v.team_threads, &v.teams_per_cu, &v.hops, &v.gang, &v.ms) != 10 ||
+        k < 1 || (v.team_threads != 256 && v.team_threads != 512 && v.team_threads != 1024) ||
+        v.teams_per_cu < 1 || v.hops < 1 || v.hops > kMaxHops || v.gang < 1 || v.gang > kMaxGang) {
+      rc = set_err(PCH_EINVAL, std::string("bad line in ") + path);
+      break;
+    }
+    key.arch = arch;
+    v.k = k;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = v;
+    ++n;
+  }
+  std::fclose(f);
+  return rc;
 }
 
 pch_status pch_voronoi(pch_mesh mesh, const int32_t* sources, int32_t m, double* dist, int32_t* label,

@@ -22,6 +22,14 @@ def mesh_frame(xyz: np.ndarray):
     return c, r
 
 
+def frame_of(gen_mesh):
+    """mesh_frame of a generated mesh, computed once per mesh (a per-mesh
+    constant, not part of a field's cost)."""
+    if "frame" not in gen_mesh.meta:
+        gen_mesh.meta["frame"] = mesh_frame(gen_mesh.xyz)
+    return gen_mesh.meta["frame"]
+
+
 @dataclass
 class FieldSamples:
     feats: "object"   # device float [n, 7]
@@ -33,7 +41,7 @@ class FieldSamples:
 def field_samples(gen_mesh, dev_mesh: pch.Mesh, xyz_dev, source: int, k: int = 8192):
     """Features and exact PCH distances of one field (all vertices)."""
     import torch
-    c, r = mesh_frame(gen_mesh.xyz)
+    c, r = frame_of(gen_mesh)
     feats, base = pch.MLP.features(xyz_dev, source, c, r)
     d = pch.geodesic(dev_mesh, [source], k=k, select_mode=pch.PCH_SELECT_DELTA)
     hbar = float(np.mean(np.linalg.norm(gen_mesh.xyz[gen_mesh.faces[:, 1]] - gen_mesh.xyz[gen_mesh.faces[:, 0]],
@@ -84,7 +92,7 @@ def train(mlp: pch.MLP, data: FieldSamples, epochs: int = 3, batch: int = 16384,
 
 
 def predict_field(mlp: pch.MLP, gen_mesh, xyz_dev, source: int):
-    c, r = mesh_frame(gen_mesh.xyz)
+    c, r = frame_of(gen_mesh)
     feats, base = pch.MLP.features(xyz_dev, source, c, r)
     return mlp.forward(feats, base)
 
@@ -100,7 +108,7 @@ def chord_geodesic(gen_mesh, dev_mesh: pch.Mesh, xyz_dev, source: int, k: int = 
     """The same cutoff rule without the network: the predicted distance of a
     vertex is its chord length to the source (the network's base term, a
     lower bound of the geodesic distance). Returns (distances, stats)."""
-    c, r = mesh_frame(gen_mesh.xyz)
+    c, r = frame_of(gen_mesh)
     _, base = pch.MLP.features(xyz_dev, source, c, r)
     return pch.geodesic(dev_mesh, [source], k=k, predicted=base, w0=w0, return_stats=True, **opts)
 
@@ -113,7 +121,7 @@ def batch_predictions(mlp, gens: Sequence, field_mesh, field_source, offsets, ch
     import torch
     out = torch.empty(int(offsets[-1]), dtype=torch.float32, device="cuda")
     xyz = [torch.from_numpy(g.xyz).to("cuda") for g in gens]
-    frames = [mesh_frame(g.xyz) for g in gens]
+    frames = [frame_of(g) for g in gens]
     for f, (mi, s) in enumerate(zip(field_mesh, field_source)):
         c, r = frames[int(mi)]
         feats, base = pch.MLP.features(xyz[int(mi)], int(s), c, r)

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                [("ms_total", ctypes.c_double), ("ms_propagate", ctypes.c_double),
                 ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double),
                 ("hop_launches", ctypes.c_int64), ("ms_phase", ctypes.c_double * 4),
-                ("timed_rounds", ctypes.c_int64)]
+                ("timed_rounds", ctypes.c_int64), ("pool_windows", ctypes.c_int64), ("selected", ctypes.c_int64),
+                ("scan_fused", ctypes.c_int32)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_}
@@ -232,7 +233,8 @@ class BatchStats(ctypes.Structure):
 BATCH_FIELD_STATS = ["status", "rounds", "processed", "created", "fans", "peak_pool", "stale", "team_ticks",
                      "helpers", "helper_ticks"]
 EXPORTS += ["pch_batch_options_default", "pch_batch_create", "pch_batch_destroy", "pch_batch_offsets",
-            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune", "pch_voronoi", "pch_field_status_string"]
+            "pch_batch_run", "pch_batch_field_stats", "pch_batch_tune", "pch_voronoi", "pch_field_status_string",
+            "pch_batch_tune_cached", "pch_tune_cache_save", "pch_tune_cache_load"]
 # field status codes (first column of Batch.field_stats)
 FIELD_STATUS = {0: "PCH_FIELD_OK", 1: "PCH_FIELD_OVERFLOW", 2: "PCH_FIELD_MAX_ROUNDS", 3: "PCH_FIELD_ABANDONED",
                 4: "PCH_FIELD_NOT_RUN", 5: "PCH_FIELD_NONFINITE", 6: "PCH_FIELD_BAD_INDEX"}
@@ -259,6 +261,9 @@ def _batch_lib():
         L.pch_batch_field_stats.argtypes = [P, P]
         L.pch_batch_tune.argtypes = [P, P, P, ctypes.POINTER(BatchOptions)]
         L.pch_voronoi.argtypes = [P, P, i32, P, P, P, ctypes.POINTER(BatchOptions)]
+        L.pch_batch_tune_cached.argtypes = [P, P, P, ctypes.POINTER(BatchOptions), ctypes.POINTER(i32)]
+        L.pch_tune_cache_save.argtypes = [ctypes.c_char_p]
+        L.pch_tune_cache_load.argtypes = [ctypes.c_char_p]
         L._batch_ready = True
     return L
 
@@ -315,6 +320,17 @@ class Batch:
         fs = np.zeros((self.n_fields, len(BATCH_FIELD_STATS)), np.int64)
         _check(_batch_lib().pch_batch_field_stats(self.handle, fs.ctypes.data))
         return fs
+
+    def tune_cached(self, out=None, stream=None):
+        """The tuner's recorded choice for this batch's size bucket, or a
+        tuning run when there is none; returns (options, hit)."""
+        if out is None:
+            out = self.empty_output()
+        o = BatchOptions()
+        hit = ctypes.c_int32()
+        _check(_batch_lib().pch_batch_tune_cached(self.handle, out.data_ptr(), _stream_handle(stream), ctypes.byref(o),
+                                                  ctypes.byref(hit)))
+        return o.as_dict(), bool(hit.value)
 
     def tune(self, out=None, stream=None) -> dict:
         if out is None:
@@ -488,3 +504,11 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def tune_cache_save(path: str):
+    _check(_batch_lib().pch_tune_cache_save(path.encode()))
+
+
+def tune_cache_load(path: str):
+    _check(_batch_lib().pch_tune_cache_load(path.encode()))

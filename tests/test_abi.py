@@ -72,3 +72,21 @@ def test_field_status_codes_match_header(pch):
     assert "non-finite" in names[5] and "outside the mesh" in names[6]
     assert all("rerun" in names[c] for c in (1, 2, 3, 4))  # the statuses a rerun completes
     assert pch.field_status_string(99) == "unknown field status"
+
+
+def test_tune_cache_round_trip(pch, tmp_path):
+    src = tmp_path / "in.txt"
+    src.write_text("# comment\ngfx950 20 29 9 32768 512 1 4 8 213.800\ngfx950 17 25 6 8192 256 1 1 2 12.500\n")
+    pch.tune_cache_load(str(src))
+    out = tmp_path / "out.txt"
+    pch.tune_cache_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "gfx950 20 29 9 32768 512 1 4 8 213.800" in lines
+    assert "gfx950 17 25 6 8192 256 1 1 2 12.500" in lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 20 29 9 32768 300 1 4 8 1.0\n")  # no such workgroup size
+    with pytest.raises(pch.PchError) as e:
+        pch.tune_cache_load(str(bad))
+    assert e.value.code == -1
+    with pytest.raises(pch.PchError):
+        pch.tune_cache_load(str(tmp_path / "missing.txt"))

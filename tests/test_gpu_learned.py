@@ -6,7 +6,11 @@
 * fields computed with the learned cutoff are exact (ICH, 1e-9) and their
   per-round records replay bit for bit in the round-based replica fed with the
   logged cutoffs;
-* what the trained network gains over plain k-th-key selection.
+* what the trained network gains: predictions closer to the exact field than
+  its chord-length base term, and the rounds and times of the learned cutoff
+  against the same rule without the network, the adaptive step and the
+  k-th-key rule;
+* the learned cutoff in the batched launch, and on the 1024^2 bump grid.
 """
 import sys
 import time
@@ -112,38 +116,51 @@ def test_learned_cutoff_exact_and_replayable(pch, oracle, trained):
 
 
 def test_learned_gain_over_plain(pch, trained):
-    """Learned cutoff against the plain method (k-th-key selection) with the
-    same k on held-out meshes: both exact; the learned rounds skip the three
-    histogram passes per round."""
+    """What the trained network gains, on held-out meshes: on a mesh of the
+    family it was trained on (bumpy icospheres) its predicted distances are
+    closer to the exact field than its base term alone (the chord length,
+    the same rule without the network); on a bump grid, outside that family,
+    the errors are reported only (there the chord is already close). The
+    fields it steers stay exact. The rounds, windows and times of the learned
+    cutoff, of the chord ablation, of the adaptive step and of k-th-key
+    selection are reported; the learned rounds skip the histogram passes, so
+    they beat the k-th-key rule."""
     import torch
     from paper_1305_1293_amd import learned as Lr
     mlp, _ = trained
     rows = []
-    for m, s in [(G.bumpy_icosphere(5, seed=77), 11), (G.bump_grid(128, seed=13), 0)]:
+    for m, s, in_family in [(G.bumpy_icosphere(5, seed=77), 11, True), (G.bump_grid(128, seed=13), 0, False)]:
         dm = pch.Mesh.from_generated(m)
         xyz = torch.from_numpy(m.xyz).cuda()
         k = 4096
-        for rep in range(2):  # second repetition is the timed one
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            dp, sp = pch.geodesic(dm, [s], k=k, select_mode=pch.PCH_SELECT_KTH, return_stats=True)
-            torch.cuda.synchronize()
-            tp = time.perf_counter() - t
-            t = time.perf_counter()
-            dl, sl = Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k)
-            torch.cuda.synchronize()
-            tl = time.perf_counter() - t
-            t = time.perf_counter()
-            dd, sd = pch.geodesic(dm, [s], k=k, select_mode=pch.PCH_SELECT_DELTA, return_stats=True)
-            torch.cuda.synchronize()
-            td = time.perf_counter() - t
-        assert torch.equal(dp, dl) or float((dp - dl).abs().max()) <= 1e-9 * float(dp.max())
-        rows.append((m.name, tp, tl, sp["processed"], sl["processed"], sp["rounds"], sl["rounds"]))
-        say(f"{m.name}: plain {1000*tp:.1f} ms {sp['processed']} windows {sp['rounds']} rounds | "
-            f"learned {1000*tl:.1f} ms {sl['processed']} windows {sl['rounds']} rounds | "
-            f"adaptive step {1000*td:.1f} ms {sd['processed']} windows {sd['rounds']} rounds")
+        exact = pch.geodesic(dm, [s], k=k, select_mode=pch.PCH_SELECT_DELTA)
+        pred = Lr.predict_field(mlp, m, xyz, s).double()
+        c, r = Lr.frame_of(m)
+        _, chord = pch.MLP.features(xyz, s, c, r)
+        far = exact > 0
+        err_net = float(((pred - exact).abs() / exact)[far].mean())
+        err_chord = float(((chord.double() - exact).abs() / exact)[far].mean())
+        say(f"{m.name}: mean relative prediction error: network {err_net:.4f}, chord {err_chord:.4f}")
+        if in_family:
+            assert err_net < err_chord
+        times = {}
+        for rep in range(2):  # the second repetition is the timed one
+            for name, run in (("kth", lambda: pch.geodesic(dm, [s], k=k, select_mode=0, return_stats=True)),
+                              ("learned", lambda: Lr.learned_geodesic(mlp, m, dm, xyz, s, k=k)),
+                              ("chord", lambda: Lr.chord_geodesic(m, dm, xyz, s, k=k)),
+                              ("adaptive", lambda: pch.geodesic(dm, [s], k=k, select_mode=1, return_stats=True))):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                d, st = run()
+                torch.cuda.synchronize()
+                times[name] = (time.perf_counter() - t, st, d)
+        for name, (t, st, d) in times.items():
+            assert float(((d - exact).abs() / exact.clamp(min=1e-3)).max()) <= 1e-9, name
+        say("  " + " | ".join(f"{n} {1000 * t:.1f} ms {st['rounds']} rounds {st['processed']} windows"
+                              for n, (t, st, _) in times.items()))
+        rows.append({n: t for n, (t, _, _) in times.items()})
         dm.close()
-    assert sum(r[2] for r in rows) < sum(r[1] for r in rows)
+    assert sum(r["learned"] for r in rows) < sum(r["kth"] for r in rows)
 
 
 def test_learned_cutoff_full_size_bump_grid(pch, trained):

@@ -7,7 +7,8 @@
   with the same k, and the distance bit patterns identical to it;
 * full size: the bumpy icosphere against live ICH on every vertex and the
   1024^2 bump grid against its stored exact ICH field on every vertex, at the
-  benchmark's setting and with plain k-th-key selection.
+  benchmark's setting, with the adaptive step below the pool size and with
+  plain k-th-key selection.
 """
 import os
 import sys
@@ -346,9 +347,11 @@ def bump_grid_gold():
 
 
 @pytest.mark.parametrize("setting", [
-    # the timed benchmark's launch configuration: adaptive step, k = 131072,
-    # 5 hops in one launch per round
-    dict(k=131072, select_mode=1, hops=5),
+    # the timed benchmark's launch configuration: adaptive step, k = 524288,
+    # 4 hops, the pool scan and all hops in one launch per round
+    dict(k=524288, select_mode=1, hops=4),
+    # the adaptive step below the pool size (the cutoff decides)
+    dict(k=131072, select_mode=1, hops=4, fuse_scan=0),
     # plain k-th-key selection, one face per round
     dict(k=1 << 17, select_mode=0, hops=1),
 ])
@@ -367,3 +370,23 @@ def test_full_size_bump_grid_every_vertex(pch, oracle, bump_grid_gold, setting):
     chord = np.linalg.norm(m.xyz - m.xyz[s], axis=1)
     assert np.all(d >= chord * (1 - 1e-12))
     say(f"  rounds {st['rounds']} processed {st['processed']}")
+
+
+def test_round_graph_replays_equal_launch_by_launch(pch, oracle):
+    """round_graph: rounds enqueued as one captured HIP graph, replayed across
+    fields with other eager work in between, give the same bits as launch by
+    launch."""
+    import torch
+    m = G.config_mesh(1)
+    dm = pch.Mesh.from_generated(m)
+    ref = {s: pch.geodesic(dm, [s], k=1024, select_mode=1, hops=4).cpu().numpy() for s in (0, 77, 1234)}
+    for rep in range(3):
+        for s in (0, 77, 1234):
+            say(f"round graph replay {rep} source {s}")
+            d = pch.geodesic(dm, [s], k=1024, select_mode=1, hops=4, round_graph=1)
+            torch.cuda.synchronize()
+            assert np.array_equal(d.cpu().numpy().view(np.uint64), ref[s].view(np.uint64)), (rep, s)
+            pch.geodesic(dm, [5], k=64, select_mode=0)  # eager work between the replays
+    d_ich, _ = oracle.ich(m, [77])
+    assert np.max(np.abs(ref[77] - d_ich) / np.maximum(d_ich, mean_edge(oracle, m))) <= 1e-9
+    dm.close()
