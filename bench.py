@@ -225,7 +225,7 @@ def measure_icosphere(args, pch, G, torch):
     rng = np.random.default_rng(2024)
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
-    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=5)
+    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=4)
     wall, tot, phase, hl, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=2)
     hbar = float(O.lengths(m).mean())
     errs = []
@@ -235,7 +235,7 @@ def measure_icosphere(args, pch, G, torch):
     mesh.close()
     kernel = "k_select_propagate" if tot["scan_fused"] else "k_propagate_fused"
     traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch",
-                            "select=1 k=12288 hops=5 fuse_hops=1")
+                            "select=1 k=12288 hops=4 fuse_hops=1")
     roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, None)
     return {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, seeded random sources",
             "ms_per_field": round(1000.0 * wall / args.steps, 4), "steps": args.steps,
@@ -282,7 +282,7 @@ def measure_batched(args, pch, G, torch):
             tp += t
             t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=k_b, select_mode=1, hops=hops_b))
             ts += t
-            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=5))
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=4))
             tb += t
             f = i * 32 + j
             ref = got[b.offsets[f]:b.offsets[f + 1]]
@@ -301,7 +301,7 @@ def measure_batched(args, pch, G, torch):
                                     "plain_kth": round(plain_ms, 1)},
             "single_field_settings": {
                 "same_rule": "adaptive step with the batch's k and hops (equal results bit for bit)",
-                "best_setting": "adaptive step, k 12288, 5 hops in one launch per round",
+                "best_setting": "adaptive step, k 12288, 4 hops, scan and hops in one launch per round",
                 "plain_kth": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on "
                              "its first source"},
             "sample": "2 sources per mesh timed field by field and scaled to 32",
@@ -316,11 +316,11 @@ def measure_concurrent(pch, m, mesh, torch):
     rule, k and hops as the icosphere's single-field steps, so each field
     equals its single-field result bit for bit."""
     fs = np.random.default_rng(7).choice(m.nv, size=64, replace=False).astype(np.int32)
-    opts = dict(k=12288, team_threads=512, teams_per_cu=1, hops=5, gang=16)
+    opts = dict(k=12288, team_threads=512, teams_per_cu=1, hops=4, gang=16)
     b = pch.Batch([mesh], np.zeros(fs.size, np.int32), fs, **opts)
     out, _ = b.run()  # first run captures the graph and measures each field's time
     dt, (out, st) = _timed(torch, lambda: b.run(out))
-    same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=5))
+    same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=4))
                for f in range(8))
     windows = int(b.field_stats()[:, 2].sum())
     b.close()
@@ -442,13 +442,13 @@ def main():
     ap.add_argument("--k", type=int, default=524288, help="windows selected per round (bump grid)")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
-    ap.add_argument("--hops", type=int, default=4, help="propagation hops per round")
+    ap.add_argument("--hops", type=int, default=5, help="propagation hops per round")
     ap.add_argument("--fuse-hops", type=int, default=1,
                     help="1: all hops of a round in one propagation launch (hops <= 6); 0: one launch per hop")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
     ap.add_argument("--no-icosphere", action="store_true", help="skip the icosphere measurement")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
-    ap.add_argument("--hops-learned", type=int, default=4, help="hops of the learned-cutoff comparison")
+    ap.add_argument("--hops-learned", type=int, default=5, help="hops of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
     ap.add_argument("--time-every", type=int, default=8,
                     help="time the phases of every n-th round with HIP events")

@@ -156,13 +156,17 @@ typedef struct {
                                  lists in LDS, depth first (default); 0 = one
                                  launch per hop. Same windows, events and
                                  results either way */
-  int32_t fuse_scan;          /* 1 = with fused hops, the pool scan of the
+  int32_t fuse_scan;          /* with fused hops, the pool scan of the
                                  selection runs in the same launch: each
                                  workgroup propagates the windows it selects
-                                 at once, with no selection buffer (default;
-                                 not with PCH_SELECT_STRIDED or organize);
-                                 0 = a partition launch first. Same windows,
-                                 events and results either way */
+                                 at once, with no selection buffer (not with
+                                 PCH_SELECT_STRIDED or organize). 2 = a
+                                 thread's first hopping child stays in its
+                                 registers, later ones go to the LDS lists
+                                 (default); 1 = every hopping child goes to
+                                 the LDS lists; 0 = a partition launch first.
+                                 Same windows, events and results either
+                                 way */
   int32_t round_graph;        /* 1 = enqueue each rounds_per_sync rounds as one
                                  captured HIP graph (kept in the mesh handle
                                  and replayed while the launch arguments stay

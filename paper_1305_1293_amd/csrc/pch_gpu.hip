@@ -314,11 +314,13 @@ __device__ __forceinline__ void wave_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, 
 // The four reservations of wave_reserve4 for a whole workgroup: one atomic
 // per counter and workgroup instead of one per wavefront, so 4x fewer
 // same-address atomics meet at the counters. Every thread of the workgroup
-// must call it (it holds two barriers); a counter may be in LDS.
+// must call it (it holds two barriers); a counter may be in LDS. BS is the
+// workgroup size.
+template <int BS = kBlock>
 __device__ __forceinline__ void block_reserve4(u64* c0, u32 n0, u64* c1, u32 n1, u64* c2, u32 n2, u64* c3, u32 n3,
                                                u64& s0, u64& s1, u64& s2, u64& s3, u32& t0, u32& t1, u32& t2,
                                                u32& t3) {
-  constexpr int kW = kBlock / kWave;
+  constexpr int kW = BS / kWave;
   __shared__ u32 s_w[kW][4];  // wavefront totals
   __shared__ u64 s_b[kW][4];  // wavefront bases
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -1315,6 +1317,15 @@ struct PropCtx {
   double cv;
 };
 
+// A window a lane keeps in registers for its next propagation step (the
+// first child of its last window that hops on).
+struct RegWin {
+  bool has = false;
+  double2 bb, pp;
+  double sg;
+  int2 es;
+};
+
 // A lane's counts over the windows it propagated.
 struct PropAcc {
   u32 n_tiny = 0, n_ich = 0, n_notwin = 0, n_nonfin = 0, n_kids = 0, n_dev = 0, n_aev = 0;
@@ -1327,10 +1338,10 @@ struct PropAcc {
 // round's selection test go to HQ (capacity hq_cap) through the counter
 // nq_ctr when to_hop is set, the others to the next pool; events go to this
 // round's buffers.
-template <bool kBlockRes, class HopQ>
+template <bool kBlockRes, class HopQ, bool kReg = false, int BS = kBlock>
 __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const PropCtx& x, bool have, double2 wbb,
                                             double2 wpp, double2 wsk, int2 wes, bool to_hop, const HopQ& HQ,
-                                            u64* nq_ctr, u64 hq_cap, PropAcc& acc) {
+                                            u64* nq_ctr, u64 hq_cap, PropAcc& acc, RegWin* rw = nullptr) {
   Ctl* c = a.ctl;
   const DevMesh& m = a.m;
   const u64* g = a.s.g;
@@ -1533,19 +1544,33 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
   const bool ql = cl && to_hop && (x.tab ? (lkey <= x.cv) : (x.all || ((bits(lkey) >> x.sh) <= x.T)));
   const bool qr = cr && to_hop && (x.tab ? (rkey <= x.cv) : (x.all || ((bits(rkey) >> x.sh) <= x.T)));
   const int nk = (cl ? 1 : 0) + (cr ? 1 : 0);
-  const int nq = (ql ? 1 : 0) + (qr ? 1 : 0);
+  const int nh = (ql ? 1 : 0) + (qr ? 1 : 0);  // children that hop on
+  // with kReg the first of them stays in the lane's registers (rw), the
+  // second goes to the hop list
+  const int nq = kReg ? (nh > 1 ? 1 : 0) : nh;
   const int nd = (e0 ? 1 : 0) + (e1 ? 1 : 0) + (e2 ? 1 : 0);
   // append children, distance events and angle events (one reservation per
   // wavefront each)
   u32 tk, td, ta, tq;
   u64 jk, jd, ja, jq;
   if constexpr (kBlockRes)
-    block_reserve4(x.qctr, (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+    block_reserve4<BS>(x.qctr, (u32)(nk - nh), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
                    (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
   else
-    wave_reserve4(x.qctr, (u32)(nk - nq), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
+    wave_reserve4(x.qctr, (u32)(nk - nh), &c->ndev[p], (u32)nd, &c->naev, has_aev ? 1u : 0u, nq_ctr,
                   (u32)nq, jk, jd, ja, jq, tk, td, ta, tq);
+  if constexpr (kReg) rw->has = false;
   auto put_child = [&](bool toq, double cb0, double cb1, double cpx, double cpy, double ckey, int32_t ce) {
+    if constexpr (kReg) {
+      if (toq && !rw->has) {
+        rw->has = true;
+        rw->bb = make_double2(cb0, cb1);
+        rw->pp = make_double2(cpx, cpy);
+        rw->sg = sg;
+        rw->es = make_int2(ce, src);
+        return;
+      }
+    }
     if (toq) {
       const u64 j = jq++;
       if (j < hq_cap)
@@ -1603,6 +1628,7 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
     acc.n_dev += td;
     acc.n_aev += ta;
   }
+  if constexpr (kReg) acc.n_kids += rw->has ? 1u : 0u;  // each lane its register child
 }
 
 // End of a propagation launch: the workgroup's key range and counts.
@@ -1990,6 +2016,156 @@ __device__ __forceinline__ FirstEvents first_events(const RoundArgs& a, int p, u
     f.X = a.aev.X[t0];
   }
   return f;
+}
+
+// k_select_propagate with the first hopping child of every window kept in
+// the lane's registers: only the second goes to the LDS list of the next hop,
+// so a step adds at most one window per lane to a list and each list holds
+// kBlock windows (12 KiB per hop level instead of 24 KiB), which leaves room
+// for twice the workgroups per compute unit. A step at hop h propagates the
+// register windows of hop h and, on the lanes without one, windows taken from
+// the list of hop h; the steps go depth first as in k_propagate_fused (the
+// deepest hop with work next), so when a step at hop h runs, the lists of the
+// deeper hops are empty. The windows propagated at each hop, and every count,
+// are those of the other launch plans.
+// The workgroup (of BS threads) is thread t0 - threadIdx.x ... of the stride
+// threads that share the round's scan: a whole launch, or the workgroups of
+// a batched field's gang.
+template <int NL, int BS>
+__device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u64 t0, u64 stride) {
+  __shared__ double2 l_bb[NL][BS], l_pp[NL][BS];
+  __shared__ double l_sg[NL][BS];
+  __shared__ int2 l_es[NL][BS];
+  __shared__ u64 l_n[NL + 2];  // l_n[h]: windows in the list of hop h (h >= 2)
+  __shared__ u32 s_idle[BS / kWave];
+  constexpr int kTop = NL + 1;  // the deepest hop
+  Ctl* c = a.ctl;
+  if (threadIdx.x <= (unsigned)kTop) l_n[threadIdx.x] = 0;
+  const bool active = c->active != 0;
+  const u64 pin = c->pin, pout = c->pout;
+  const u64 N = active ? min(c->nscan, (u64)a.cap) : 0;
+  const int sh = (int)c->shift;
+  const u64 T = c->want;
+  const bool all = c->sel_all;
+  const bool tab = c->use_table;
+  const double cv = c->cutval;
+  const bool inplace = pin == pout;
+  const Pool P = pin ? a.pool[1] : a.pool[0];
+  const PropCtx x{pout ? a.pool[1] : a.pool[0], &c->npool[pout & 1], a.ev[p], sh, T, all, tab, cv};
+  const int hops = a.hops < kTop ? a.hops : kTop;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  __syncthreads();
+  PropAcc acc;
+  RegWin rw;
+  u32 stale_n = 0, kept_in = 0, n_sel = 0, n_hop = 0;
+  u64 base = t0 - threadIdx.x;  // the workgroup's next chunk of the pool
+  int lvl = 1;                          // hop of the next step (the same in every thread)
+  for (;;) {
+    bool have = false;
+    double2 wbb = make_double2(0.0, 0.0), wpp = wbb, wsk = wbb;
+    int2 wes = make_int2(0, 0);
+    if (lvl == 1) {
+      if (base >= N) break;
+      const u64 i = base + threadIdx.x;
+      base += stride;
+      bool keep = false, gone = false;
+      if (i < N) {
+        wsk = P.sk[i];
+        wes = P.es[i];
+        wbb = P.bb[i];
+        wpp = P.pp[i];
+        if (bits(wsk.y) != kDead) {
+          const bool stale = !idx_ok(c, wes.y, a.m.nv) || wsk.x > from_bits(lda(&a.s.g[wes.y]));
+          if (stale) {
+            stale_n++;
+            gone = true;
+          } else {
+            have = tab ? (wsk.y <= cv) : (all || ((bits(wsk.y) >> sh) <= T));
+            keep = !have;
+          }
+        }
+      }
+      if (have) n_sel++;
+      if (inplace) {
+        if (have || gone) reinterpret_cast<double*>(P.sk)[2 * i + 1] = from_bits(kDead);
+        if (keep) kept_in++;
+      } else {
+        u64 jk, j1, j2;
+        u32 tk, t1, t2;
+        wave_reserve3(x.qctr, keep ? 1u : 0u, x.qctr, 0u, x.qctr, 0u, jk, j1, j2, tk, t1, t2);
+        if (keep) {
+          if (jk < (u64)a.cap)
+            store_window(x.Q, jk, wbb.x, wbb.y, wpp.x, wpp.y, wsk.x, wsk.y, wes.x, wes.y);
+          else
+            flag_overflow(c);
+        }
+      }
+      if (keep) {
+        const u64 kb = bits(wsk.y);
+        acc.kmn = kb < acc.kmn ? kb : acc.kmn;
+        acc.kmx = kb > acc.kmx ? kb : acc.kmx;
+      }
+    } else {
+      // the lane's register window of this hop, else one from the list: the
+      // lanes without a register window are ranked and take the list's last
+      // windows in rank order
+      const bool idle = !rw.has;
+      const u64 m = __ballot(idle);
+      const u32 wrank = (u32)__popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) s_idle[w] = (u32)__popcll(m);
+      __syncthreads();
+      u32 rank = wrank;
+      for (int q = 0; q < w; ++q) rank += s_idle[q];
+      u32 n_idle = 0;
+      for (int q = 0; q < BS / kWave; ++q) n_idle += s_idle[q];
+      const u64 n = l_n[lvl];
+      const u64 take = n < (u64)n_idle ? n : (u64)n_idle;
+      if (!idle) {
+        have = true;
+        wbb = rw.bb;
+        wpp = rw.pp;
+        wsk = make_double2(rw.sg, 0.0);
+        wes = rw.es;
+      } else if (rank < take) {
+        const u64 j = n - take + rank;
+        have = true;
+        wbb = l_bb[lvl - 2][j];
+        wpp = l_pp[lvl - 2][j];
+        wsk = make_double2(l_sg[lvl - 2][j], 0.0);
+        wes = l_es[lvl - 2][j];
+      }
+      __syncthreads();  // every thread has its window before the list shrinks
+      if (threadIdx.x == 0) l_n[lvl] = n - take;
+      if (have) n_hop++;
+    }
+    const int nl = lvl < kTop ? lvl + 1 : kTop;
+    const HopList HQ{l_bb[nl - 2], l_pp[nl - 2], l_sg[nl - 2], l_es[nl - 2]};
+    prop_window<true, HopList, true, BS>(a, p, x, have, wbb, wpp, wsk, wes, lvl < hops, HQ, &l_n[nl], (u64)BS,
+                                         acc, &rw);
+    // deeper when some lane holds a register window or the next list has
+    // windows (the list length is visible after the barrier)
+    const int deeper = __syncthreads_or(rw.has ? 1 : 0);
+    if (lvl < hops && (deeper || l_n[lvl + 1] != 0)) {
+      ++lvl;
+    } else {
+      while (lvl > 1 && l_n[lvl] == 0) --lvl;
+    }
+  }
+  u32 tot[4] = {stale_n, kept_in, n_sel, n_hop};
+  u64 z0 = kAllOnes, z1 = 0;
+  block_totals(z0, z1, tot);
+  if (threadIdx.x == 0) {
+    if (tot[0] && a.counts) atomicAdd(&c->cnt[C_STALE], (u64)tot[0]);
+    if (tot[1]) atomicAdd(&c->keptin, (u64)tot[1]);
+    if (tot[2] + tot[3]) atomicAdd(&c->cnt[C_SEL], (u64)tot[2] + tot[3]);
+    if (tot[2] && a.counts) atomicAdd(&c->xcnt[X_SEL1], (u64)tot[2]);
+  }
+  prop_finish(a, p, acc);
+}
+
+template <int NL>
+__global__ void __launch_bounds__(kBlock) k_select_propagate_r(RoundArgs a, int p) {
+  ph_select_propagate<NL, kBlock>(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
 // Algorithm 4, first event pass (the minima themselves were taken by the
@@ -3133,8 +3309,19 @@ void launch_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) {
   }
 }
 
-// The pool scan and the propagation of all hops in one launch.
-void launch_select_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) {
+// The pool scan and the propagation of all hops in one launch (reg: the
+// lists hold only the second hopping child of a window).
+void launch_select_fused(const RoundArgs& a, int p, hipStream_t st, int blocks, bool reg) {
+  if (reg) {
+    switch (a.hops <= 2 ? 1 : a.hops - 1) {
+      case 1: k_select_propagate_r<1><<<blocks, kBlock, 0, st>>>(a, p); break;
+      case 2: k_select_propagate_r<2><<<blocks, kBlock, 0, st>>>(a, p); break;
+      case 3: k_select_propagate_r<3><<<blocks, kBlock, 0, st>>>(a, p); break;
+      case 4: k_select_propagate_r<4><<<blocks, kBlock, 0, st>>>(a, p); break;
+      default: k_select_propagate_r<5><<<blocks, kBlock, 0, st>>>(a, p); break;
+    }
+    return;
+  }
   switch (a.hops <= 2 ? 1 : a.hops - 1) {
     case 1: k_select_propagate<1><<<blocks, kBlock, 0, st>>>(a, p); break;
     case 2: k_select_propagate<2><<<blocks, kBlock, 0, st>>>(a, p); break;
@@ -3145,8 +3332,10 @@ void launch_select_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) 
 }
 
 // Round launch plan: kSplit = partition, then propagation (fused hops or one
-// launch per hop); kScanFused = the pool scan inside the fused propagation.
-enum RoundPlan { kSplit = 0, kScanFused = 1 };
+// launch per hop); kScanFused = the pool scan inside the fused propagation;
+// kScanFusedReg = the same with the first hopping child of each window kept
+// in registers.
+enum RoundPlan { kSplit = 0, kScanFused = 1, kScanFusedReg = 2 };
 
 void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, int prop_blocks, bool kth, bool fused,
                    const hipEvent_t* ev = nullptr, RoundPlan plan = kSplit) {
@@ -3155,10 +3344,10 @@ void enqueue_round(const RoundArgs& a, int p, hipStream_t st, int pool_blocks, i
   if (ev) (void)hipEventRecord(ev[0], st);
   if (kth)
     for (int pass = 0; pass < 3; ++pass) k_hist<<<kSmallGrid, kBlock, 0, st>>>(a, p, pass);
-  if (plan == kScanFused) {
+  if (plan == kScanFused || plan == kScanFusedReg) {
     if (ev) (void)hipEventRecord(ev[1], st);
     if (ev) (void)hipEventRecord(ev[2], st);
-    launch_select_fused(a, p, st, pool_blocks);
+    launch_select_fused(a, p, st, pool_blocks, plan == kScanFusedReg);
     if (ev) (void)hipEventRecord(ev[3], st);
     k_events2<<<kSmallGrid, kBlock, 0, st>>>(a, p);
     k_events3<<<kSmallGrid, kBlock, 0, st>>>(a, p);
@@ -3234,7 +3423,7 @@ void pch_options_default(pch_options* o) {
   o->hops = 1;
   o->counts = 1;
   o->fuse_hops = 1;
-  o->fuse_scan = 1;
+  o->fuse_scan = 2;
   o->round_graph = 0;
 }
 
@@ -3471,7 +3660,9 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     if (strided) pool_blocks = grid_for(o.k, 1 << 30);
     // the pool scan runs inside the fused propagation unless the round needs
     // the whole selection first (strided selection, grouping by edge)
-    const RoundPlan plan = (fused && o.fuse_scan != 0 && !strided && !o.organize) ? kScanFused : kSplit;
+    const RoundPlan plan = (fused && o.fuse_scan != 0 && !strided && !o.organize)
+                               ? (o.fuse_scan == 2 ? kScanFusedReg : kScanFused)
+                               : kSplit;
     plan_used = plan;
     int p = 0;
     bool overflow = false;
@@ -3606,7 +3797,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     stats->hop_launches = (o.fuse_hops != 0 && o.hops <= kFuseHops) ? 1 : o.hops;
     stats->pool_windows = (int64_t)T[C_N];
     stats->selected = (int64_t)host_ctl.xcnt[X_SEL1];
-    stats->scan_fused = plan_used == kScanFused ? 1 : 0;
+    stats->scan_fused = plan_used != kSplit ? 1 : 0;
     stats->delta0 = delta0;
   }
   return PCH_OK;

@@ -13,8 +13,8 @@
 // Mapping: one wavefront per stream of samples, lane j = hidden unit j; the
 // 64-wide layers exchange activations with wavefront shuffles. Gradients are
 // reduced per block in LDS and added to the global gradient with one atomic
-// per parameter and block. The layers are 64 wide, far too small for matrix
-// cores to matter next to the geodesic rounds, so plain FMA is used.
+// per parameter and block (training). Inference runs on the matrix cores
+// (k_mlp_forward_mfma).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -157,6 +157,93 @@ __global__ void k_zero(float* p, int n) {
   if (i < n) p[i] = 0.f;
 }
 
+// Inference on the matrix cores (v_mfma_f32_16x16x16_bf16): each wavefront
+// takes tiles of 16 samples. Every layer computes the transposed product
+// Z^T = W^T A^T (rows: units, columns: samples), with the bias, ReLU and the
+// BF16 rounding of its output applied per element. In the 16 x 16 result
+// tile lane l holds rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16,
+// which is exactly where the next product's B operand wants them, so the
+// activations never leave the registers. The same arithmetic as k_mlp (BF16
+// operands, FP32 accumulation), in another summation order.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// bits of bf16r(x)
+__device__ __forceinline__ short bf16bits(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__global__ void __launch_bounds__(kMlpBlock) k_mlp_forward_mfma(const float* __restrict__ P,
+                                                                const float* __restrict__ X,
+                                                                const float* __restrict__ base, int64_t n,
+                                                                float* __restrict__ pred) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;  // A operand row; B, D column (the sample of the tile)
+  const int q = lane >> 4;  // rows (A: k) 4 q .. 4 q + 3
+  // W1^T in 4 row blocks (units 16 mb + r, inputs 4 q + i, zero past the 7th)
+  bf16x4 a1[4];
+  // W2^T in 4 x 4 blocks (output unit 16 mb + r, input unit 16 kb + 4 q + i)
+  bf16x4 a2[4][4];
+  // per D-layout row (unit 16 mb + 4 q + i): biases and the last layer
+  float b1v[4][4], b2v[4][4], w3v[4][4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * q + i;
+      a1[mb][i] = k < NIN ? bf16bits(P[OW1 + k * H + 16 * mb + r]) : (short)0;
+      const int u = 16 * mb + 4 * q + i;
+      b1v[mb][i] = P[OB1 + u];
+      b2v[mb][i] = P[OB2 + u];
+      w3v[mb][i] = bf16r(P[OW3 + u]);
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) a2[mb][kb][i] = bf16bits(P[OW2 + (16 * kb + 4 * q + i) * H + 16 * mb + r]);
+    }
+  }
+  const float b3 = P[OB3];
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t wid = (int64_t)blockIdx.x * (kMlpBlock / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kMlpBlock / 64);
+  for (int64_t t = wid; t < tiles; t += nw) {
+    const int64_t s = t * 16 + r;
+    const bool ok = s < n;
+    bf16x4 xb;  // X^T: inputs 4 q + i of sample s
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * q + i;
+      xb[i] = (ok && k < NIN) ? bf16bits(X[s * NIN + k]) : (short)0;
+    }
+    bf16x4 h1[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[mb], xb, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float zz = z[i] + b1v[mb][i];
+        h1[mb][i] = bf16bits(zz > 0.f ? zz : 0.f);
+      }
+    }
+    float y = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[mb][kb], h1[kb], z, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float zz = z[i] + b2v[mb][i];
+        y += bf16r(zz > 0.f ? zz : 0.f) * w3v[mb][i];
+      }
+    }
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    y += b3;
+    if (ok && q == 0) pred[s] = base[s] * (1.f + softplusf(y));
+  }
+}
+
 // Features of every vertex for a source s: [(v - c) / R, (s - c) / R,
 // |v - s| / R] and the chord |v - s|.
 __global__ void k_features(const double* xyz, int64_t nv, int32_t s, double cx, double cy, double cz, double R,
@@ -257,10 +344,9 @@ pch_status pch_mlp_forward(pch_mlp m, const float* feats, const float* base, int
                            void* hip_stream) {
   if (!m || !feats || !base || !pred || n < 1) return mlp_err(PCH_EINVAL, "bad forward argument");
   hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t waves = (n + 15) / 16;
-  const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((waves + 3) / 4, 1), 2048);
-  k_mlp<<<blocks, kMlpBlock, 0, st>>>(m->P, feats, base, nullptr, nullptr, n, 1.f / (float)n, pred, nullptr, nullptr,
-                                      0);
+  const int64_t tiles = (n + 15) / 16;  // one wavefront per 16-sample tile
+  const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((tiles + 3) / 4, 1), 4096);
+  k_mlp_forward_mfma<<<blocks, kMlpBlock, 0, st>>>(m->P, feats, base, n, pred);
   MLP_TRY(hipGetLastError());
   return PCH_OK;
 }

@@ -329,12 +329,12 @@ def test_full_size_bumpy_icosphere_all_vertices(pch, oracle):
     d, st, _ = gpu_field(pch, m, [s], k=16384)
     assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7")
     say(f"  rounds {st['rounds']} processed {st['processed']}")
-    # the launch configuration of the timed benchmark: adaptive step,
-    # k = 12288, 5 hops in one launch per round
-    d, st, _ = gpu_field(pch, m, [s], k=12288, select_mode=1, hops=5)
-    assert st["hop_launches"] == 1
-    assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7, adaptive step, 5 hops")
-    say(f"  adaptive step, 5 hops: rounds {st['rounds']} processed {st['processed']}")
+    # the launch configuration of the bench line's icosphere object: adaptive
+    # step, k = 12288, 4 hops, scan and hops in one launch per round
+    d, st, _ = gpu_field(pch, m, [s], k=12288, select_mode=1, hops=4)
+    assert st["hop_launches"] == 1 and st["scan_fused"] == 1
+    assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7, adaptive step, 4 hops")
+    say(f"  adaptive step, 4 hops: rounds {st['rounds']} processed {st['processed']}")
 
 
 @pytest.fixture(scope="module")
@@ -348,8 +348,8 @@ def bump_grid_gold():
 
 @pytest.mark.parametrize("setting", [
     # the timed benchmark's launch configuration: adaptive step, k = 524288,
-    # 4 hops, the pool scan and all hops in one launch per round
-    dict(k=524288, select_mode=1, hops=4),
+    # 5 hops, the pool scan and all hops in one launch per round
+    dict(k=524288, select_mode=1, hops=5),
     # the adaptive step below the pool size (the cutoff decides)
     dict(k=131072, select_mode=1, hops=4, fuse_scan=0),
     # plain k-th-key selection, one face per round
