@@ -155,17 +155,18 @@ def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
     torch.cuda.synchronize()
     timed = srcs[warmup:]
     keep = []
-    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0, timed_rounds=0, scan_fused=0)
+    tot = dict(processed=0, rounds=0, ms_propagate=0.0, propagate_launches=0, timed_rounds=0)
     phase = dict(select=0.0, propagate=0.0, organize=0.0, events=0.0)
     hop_launches = 1
     t0 = time.perf_counter()
     for i, s in enumerate(timed):
         _, st = pch.geodesic(mesh, [int(s)], out=out, return_stats=True, counts=0, **opts)
-        for kk in tot:
+        for kk in ("processed", "rounds", "ms_propagate", "propagate_launches", "timed_rounds"):
             tot[kk] += st[kk]
         for kk in phase:
             phase[kk] += st["ms_phase"][kk]
         hop_launches = st["hop_launches"]
+        tot["scan_fused"] = st["scan_fused"]  # the launch plan (the same every field)
         if i < keep_first:
             keep.append(out.clone())
     torch.cuda.synchronize()
@@ -187,6 +188,7 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
     prop_bytes = (PROP_READ_BYTES * tot["processed"] + WINDOW_BYTES * kids
                   + DIST_EVENT_BYTES * tot["dist_events"] + ANGLE_EVENT_BYTES * tot["angle_events"])
     fused_scan = tot["scan_fused"] > 0
+    plan_kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}
     if fused_scan:  # the same launch scans the pool
         prop_bytes += SCAN_BYTES * (tot["pool_windows"] - tot["selected"])
     flops = FLOP_PER_WINDOW * tot["processed"] + FLOP_PER_CHILD * (kids + tot["tiny"] + tot["ich_dropped"])
@@ -199,7 +201,7 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
     flops_per_launch = flops / all_launches
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     tflops = flops_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
-    kernel = "k_select_propagate" if fused_scan else ("k_propagate_fused" if hop_launches == 1 else "k_propagate")
+    kernel = plan_kernel.get(tot["scan_fused"], "k_propagate_fused" if hop_launches == 1 else "k_propagate")
     fp64 = {"bound": "fp64", "achieved": round(tflops, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / FP64_PEAK_TFLOPS, 6), "alg_flop_per_launch": round(flops_per_launch, 1),
             "counter_flop_per_launch": counter_flops}
@@ -225,7 +227,7 @@ def measure_icosphere(args, pch, G, torch):
     rng = np.random.default_rng(2024)
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
-    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=4)
+    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=5)
     wall, tot, phase, hl, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=2)
     hbar = float(O.lengths(m).mean())
     errs = []
@@ -233,9 +235,9 @@ def measure_icosphere(args, pch, G, torch):
         ref, _ = O.ich(m, [int(srcs[args.warmup + i])])
         errs.append(float(np.max(np.abs(keep[i].cpu().numpy() - ref) / np.maximum(ref, hbar))))
     mesh.close()
-    kernel = "k_select_propagate" if tot["scan_fused"] else "k_propagate_fused"
+    kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}.get(tot["scan_fused"], "k_propagate_fused")
     traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch",
-                            "select=1 k=12288 hops=4 fuse_hops=1")
+                            "select=1 k=12288 hops=5 fuse_hops=1")
     roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, None)
     return {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, seeded random sources",
             "ms_per_field": round(1000.0 * wall / args.steps, 4), "steps": args.steps,
@@ -282,7 +284,7 @@ def measure_batched(args, pch, G, torch):
             tp += t
             t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=k_b, select_mode=1, hops=hops_b))
             ts += t
-            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=4))
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=5))
             tb += t
             f = i * 32 + j
             ref = got[b.offsets[f]:b.offsets[f + 1]]
@@ -301,7 +303,7 @@ def measure_batched(args, pch, G, torch):
                                     "plain_kth": round(plain_ms, 1)},
             "single_field_settings": {
                 "same_rule": "adaptive step with the batch's k and hops (equal results bit for bit)",
-                "best_setting": "adaptive step, k 12288, 4 hops, scan and hops in one launch per round",
+                "best_setting": "adaptive step, k 12288, 5 hops, scan and hops in one launch per round",
                 "plain_kth": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on "
                              "its first source"},
             "sample": "2 sources per mesh timed field by field and scaled to 32",
@@ -316,11 +318,11 @@ def measure_concurrent(pch, m, mesh, torch):
     rule, k and hops as the icosphere's single-field steps, so each field
     equals its single-field result bit for bit."""
     fs = np.random.default_rng(7).choice(m.nv, size=64, replace=False).astype(np.int32)
-    opts = dict(k=12288, team_threads=512, teams_per_cu=1, hops=4, gang=16)
+    opts = dict(k=12288, team_threads=512, teams_per_cu=1, hops=5, gang=16)
     b = pch.Batch([mesh], np.zeros(fs.size, np.int32), fs, **opts)
     out, _ = b.run()  # first run captures the graph and measures each field's time
     dt, (out, st) = _timed(torch, lambda: b.run(out))
-    same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=4))
+    same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=5))
                for f in range(8))
     windows = int(b.field_stats()[:, 2].sum())
     b.close()
@@ -505,7 +507,8 @@ def main():
     wall, tot, phase, hop_launches, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=1)
     ms_per_field = 1000.0 * wall / args.steps
     tag = f"select={args.select} k={args.k} hops={args.hops} fuse_hops={args.fuse_hops}"
-    kernel = "k_select_propagate" if tot["scan_fused"] else ("k_propagate_fused" if hop_launches == 1 else "k_propagate")
+    kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}.get(
+        tot["scan_fused"], "k_propagate_fused" if hop_launches == 1 else "k_propagate")
     traffic = profile_value(f"{kernel}_bump_grid1024_traffic.md", "hbm_bytes_per_launch", tag)
     cflops = profile_value(f"{kernel}_bump_grid1024_traffic.md", "fp64_flop_per_launch", tag)
     roofline, phases = roofline_of(tot, phase, hop_launches, wall, args.steps, traffic, cflops)

@@ -201,8 +201,11 @@ typedef struct {
   int64_t selected;          /* windows the selection took from the pool,
                                 summed over rounds (processed minus those that
                                 hopped on); with counts only */
-  int32_t scan_fused;        /* 1 when the pool scan ran inside the
-                                propagation launch (fuse_scan) */
+  int32_t scan_fused;        /* the round's launch plan (fuse_scan): 0 = a
+                                partition launch, then propagation; 1 = the
+                                pool scan inside the propagation launch;
+                                2 = the same with each thread's first
+                                hopping child held in registers */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).

@@ -95,15 +95,37 @@ enum {
 // extra counters (not in the log)
 enum { X_NOTWIN = 0, X_SEL1 = 1, X_NUM = 4 };  // X_SEL1: windows the pool scans selected (hop 1)
 
+// A pair of counters indexed by parity, each alone in its 128-byte line.
+// Atomics that fall in the same 64-byte granule of memory are performed one
+// after another (about 12.5 ns apiece on gfx950, measured with one returning
+// atomicAdd per workgroup: one counter, or four 8 bytes apart, 80 M/s; four
+// 128 bytes apart, 280 M/s), so every counter that the workgroups of one
+// launch update with atomics gets a line of its own.
+struct Pair {
+  u64 d[2][16];
+  __host__ __device__ u64& operator[](u64 i) { return d[i][0]; }
+  __host__ __device__ const u64& operator[](u64 i) const { return d[i][0]; }
+};
+
 struct Ctl {
-  u64 npool[2];     // slots used in pool buffer 0 and 1 (live windows and tombstones)
-  u64 ndev[2];
-  u64 nsel;
-  u64 naev;
-  u64 kmin[2], kmax[2];
-  u64 overflow;
+  // updated with atomics by the workgroups of a launch
+  Pair npool;                // slots used in pool buffer 0 and 1 (live windows and tombstones)
+  Pair ndev;                 // distance events recorded for the round of each parity
+  Pair kmin, kmax;           // key range of the next pool, by parity
+  alignas(128) u64 naev;     // angle events of the current round
+  alignas(128) u64 ncand;    // fan candidates of the current round
+  alignas(128) u64 keptin;   // windows the pool scan kept in place
+  alignas(128) u64 ticket;   // last-block detection
+  alignas(128) u64 nsel;
+  alignas(128) u64 scan_next;  // next free ticket of the fused pool scan
+  alignas(128) u64 cnt[C_NUM];  // current round
+  alignas(128) u64 xcnt[X_NUM];
+  alignas(128) u64 nhop[kMaxHops + 1];  // nhop[h]: windows queued by hop h for hop h + 1
+  alignas(128) u64 overflow;  // rare flags
   u64 nonfinite;
-  u64 round;        // rounds run so far
+  u64 badidx;       // a window or event named a half-edge or vertex outside the mesh
+  // set by the round set-up, read by the launches
+  alignas(128) u64 round;  // rounds run so far
   u64 active;       // 1 while the current round has work
   u64 done;
   u64 sel_all;      // current round selects every window
@@ -116,15 +138,9 @@ struct Ctl {
   double delta;     // adaptive step
   u64 lmode;        // current round uses the learned cutoff
   double lfac;      // feedback factor of the learned cutoff
-  u64 ticket;       // last-block detection
-  u64 nhop[kMaxHops + 1];  // nhop[h]: windows queued by hop h for hop h + 1
-  u64 cnt[C_NUM];   // current round
-  u64 xcnt[X_NUM];
   u64 tot[C_NUM];   // totals over all rounds
   u64 peak;
   u64 smode;        // current round uses the strided selection
-  u64 ncand;        // fan candidates of the current round
-  u64 badidx;       // a window or event named a half-edge or vertex outside the mesh
   // The pool: the round's windows are the live slots [0, nscan) of buffer
   // pin. The partition either leaves the windows it keeps in place (selected
   // and stale ones become tombstones) and the round appends its new windows
@@ -132,9 +148,9 @@ struct Ctl {
   // into the other buffer (s0 = 0); pout is the buffer that receives them.
   // The next round's live windows are keptin (kept in place) plus the slots
   // appended after s0.
-  u64 pin, pout, nscan, s0, keptin;
-  u64 pad[5];
+  u64 pin, pout, nscan, s0;
 };
+static_assert(sizeof(Ctl) % 128 == 0, "control block is whole 128-byte lines");
 
 // key of a tombstone: a pool slot whose window was selected or dropped (no
 // finite non-negative key has this bit pattern, and no histogram prefix of
@@ -873,6 +889,7 @@ __device__ int round_begin_lane0(const RoundArgs& a, int p, u64* want_out, doubl
     c->s0 = slots;
   }
   c->ndev[1 - p] = 0;
+  c->scan_next = 0;
   c->nsel = 0;
   c->naev = 0;
   c->ncand = 0;
@@ -1768,6 +1785,32 @@ __global__ void __launch_bounds__(kBlock) k_propagate(RoundArgs a, int p, int ho
 constexpr int kFuseHops = 6;          // hops that one fused launch carries
 constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
 
+// The pool scan of the fused launches deals the pool in 64-slot chunks,
+// round-robin over the G workgroups: ticket t stands for workgroup slot t % G
+// of deal t / G, in which wave w of the workgroup scans chunk
+// ((t / G) nW + w) G + t % G. The newest windows, which hold most of a
+// round's selected ones, sit together at the end of the pool; dealt this way
+// they spread over every workgroup instead of loading a few with long hop
+// chains. Each workgroup takes ticket blockIdx.x first and then the next free
+// one from a counter, so workgroups whose windows hop little scan more.
+// Called by the whole workgroup (uniformly); returns false once the
+// workgroup's ticket lies past the pool, else sets i to this thread's slot.
+__device__ __forceinline__ bool scan_ticket(Ctl* c, u64 N, u32 G, u32 nW, bool& first, u32& ticket, u32* s_ticket,
+                                            u64& i) {
+  if (!first) {
+    if (threadIdx.x == 0) *s_ticket = (u32)atomicAdd(&c->scan_next, 1ull) + G;
+    __syncthreads();
+    ticket = *s_ticket;
+  }
+  first = false;
+  const u64 deal = ticket / G, slot = ticket % G;
+  if ((deal * nW * G + slot) * kWave >= N) return false;
+  i = ((deal * nW + threadIdx.x / kWave) * G + slot) * kWave + lane_id();
+  return true;
+}
+
+
+
 // All hops of a round in one launch (hops <= NL + 1 <= kFuseHops). Each
 // workgroup propagates its share of the selected windows and, depth first,
 // the children that pass the round's selection test, from NL per-hop lists in
@@ -1901,18 +1944,18 @@ __global__ void __launch_bounds__(kBlock) k_select_propagate(RoundArgs a, int p)
   __syncthreads();
   PropAcc acc;
   u32 stale_n = 0, kept_in = 0, n_sel = 0;
-  const u64 stride = (u64)gridDim.x * kBlock;
-  u64 base = blockIdx.x * (u64)kBlock;  // the workgroup's next chunk of the pool
-  u64 hopped = 0;                       // windows taken from the lists (thread 0)
-  int lvl = 1;                          // hop of the next step (the same in every thread)
+  __shared__ u32 s_ticket;
+  bool first = true;
+  u32 ticket = blockIdx.x;  // the workgroup's deal of the pool (scan_ticket)
+  u64 hopped = 0;           // windows taken from the lists (thread 0)
+  int lvl = 1;              // hop of the next step (the same in every thread)
   for (;;) {
     bool have = false;
     double2 wbb = make_double2(0.0, 0.0), wpp = wbb, wsk = wbb;
     int2 wes = make_int2(0, 0);
     if (lvl == 1) {
-      if (base >= N) break;
-      const u64 i = base + threadIdx.x;
-      base += stride;
+      u64 i = 0;
+      if (!scan_ticket(c, N, gridDim.x, kBlock / kWave, first, ticket, &s_ticket, i)) break;
       bool keep = false, gone = false;
       if (i < N) {
         // the whole slot in one batch of loads (a tombstone's other fields
@@ -2058,16 +2101,17 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
   PropAcc acc;
   RegWin rw;
   u32 stale_n = 0, kept_in = 0, n_sel = 0, n_hop = 0;
-  u64 base = t0 - threadIdx.x;  // the workgroup's next chunk of the pool
-  int lvl = 1;                          // hop of the next step (the same in every thread)
+  __shared__ u32 s_ticket;
+  bool first = true;
+  u32 ticket = (u32)(t0 / BS);  // the workgroup's deal of the pool (scan_ticket)
+  int lvl = 1;                  // hop of the next step (the same in every thread)
   for (;;) {
     bool have = false;
     double2 wbb = make_double2(0.0, 0.0), wpp = wbb, wsk = wbb;
     int2 wes = make_int2(0, 0);
     if (lvl == 1) {
-      if (base >= N) break;
-      const u64 i = base + threadIdx.x;
-      base += stride;
+      u64 i = 0;
+      if (!scan_ticket(c, N, (u32)(stride / BS), BS / kWave, first, ticket, &s_ticket, i)) break;
       bool keep = false, gone = false;
       if (i < N) {
         wsk = P.sk[i];
@@ -3309,6 +3353,38 @@ void launch_fused(const RoundArgs& a, int p, hipStream_t st, int blocks) {
   }
 }
 
+// Workgroups of the fused scan-and-propagation kernel for `hops` that the
+// current device holds at once (occupancy times compute units), per device.
+int resident_blocks(int hops, bool reg) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  const int nl = hops <= 2 ? 1 : (hops - 1 > 5 ? 5 : hops - 1);
+  const auto key = std::make_tuple(dev, nl, reg ? 1 : 0);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const void* fn = nullptr;
+  if (reg) {
+    const void* r[5] = {(const void*)k_select_propagate_r<1>, (const void*)k_select_propagate_r<2>,
+                        (const void*)k_select_propagate_r<3>, (const void*)k_select_propagate_r<4>,
+                        (const void*)k_select_propagate_r<5>};
+    fn = r[nl - 1];
+  } else {
+    const void* f[5] = {(const void*)k_select_propagate<1>, (const void*)k_select_propagate<2>,
+                        (const void*)k_select_propagate<3>, (const void*)k_select_propagate<4>,
+                        (const void*)k_select_propagate<5>};
+    fn = f[nl - 1];
+  }
+  int per_cu = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+  const int n = per_cu * ncu;
+  cache[key] = n;
+  return n;
+}
+
 // The pool scan and the propagation of all hops in one launch (reg: the
 // lists hold only the second hopping child of a window).
 void launch_select_fused(const RoundArgs& a, int p, hipStream_t st, int blocks, bool reg) {
@@ -3664,6 +3740,11 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
                                ? (o.fuse_scan == 2 ? kScanFusedReg : kScanFused)
                                : kSplit;
     plan_used = plan;
+    // the fused scan runs on as many workgroups as the device holds at once:
+    // none starts after others have finished, and the tickets balance the
+    // rest (scan_ticket)
+    const int fused_blocks = plan == kSplit ? 0 : resident_blocks(a.hops, plan == kScanFusedReg);
+    if (fused_blocks > 0) pool_blocks = fused_blocks;
     int p = 0;
     bool overflow = false;
     for (double& x : phase_ms) x = 0.0;
@@ -3743,7 +3824,8 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
         n_prev = n_now;
       }
       rounds_before = host_ctl.round;
-      if (!strided) pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
+      if (!strided && fused_blocks == 0)
+        pool_blocks = grid_for(std::max<int64_t>(2 * (int64_t)host_ctl.peak, 2 * o.k), 1024);
       if (host_ctl.badidx)
         return set_err(PCH_EDEVICE, "a window or event named a half-edge or vertex outside the mesh");
       if (host_ctl.overflow) {
@@ -3797,7 +3879,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     stats->hop_launches = (o.fuse_hops != 0 && o.hops <= kFuseHops) ? 1 : o.hops;
     stats->pool_windows = (int64_t)T[C_N];
     stats->selected = (int64_t)host_ctl.xcnt[X_SEL1];
-    stats->scan_fused = plan_used != kSplit ? 1 : 0;
+    stats->scan_fused = plan_used == kScanFusedReg ? 2 : (plan_used == kScanFused ? 1 : 0);
     stats->delta0 = delta0;
   }
   return PCH_OK;
