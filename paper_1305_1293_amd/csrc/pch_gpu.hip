@@ -509,6 +509,29 @@ __device__ __forceinline__ int child_filter(double c0, double c1, double cpx, do
   return 0;
 }
 
+// window_key and child_filter (with the apex test) with their square roots
+// taken before any decision: the same values and the same decisions in the
+// same order, as straight-line code whose independent roots overlap
+__device__ __forceinline__ double window_key_sl(double b0, double b1, double px, double py, double sg) {
+  const double dx = px < b0 ? b0 - px : px - b1;
+  const double dseg = sqrt(dx * dx + py * py);
+  return sg + ((px < b0 || px > b1) ? dseg : -py);
+}
+__device__ __forceinline__ int child_filter_sl(double c0, double c1, double cpx, double cpy, double sg, double lc,
+                                               double gu0, double gu1, bool r_at_c0, double gr, double rdist,
+                                               double eps, bool ich_on) {
+  const double dx1 = c1 - cpx;
+  const double f1 = sg + sqrt(dx1 * dx1 + cpy * cpy);
+  const double dx0 = c0 - cpx;
+  const double f0 = sg + sqrt(dx0 * dx0 + cpy * cpy);
+  if (!(c1 - c0 > eps * lc)) return 1;
+  if (!ich_on) return 0;
+  if (f1 > (gu0 + c1) * kFm) return 2;
+  if (f0 > (gu1 + (lc - c0)) * kFm) return 2;
+  if ((r_at_c0 ? f0 : f1) > (gr + rdist) * kFm) return 2;
+  return 0;
+}
+
 __device__ __forceinline__ void store_window(const Pool& P, u64 i, double b0, double b1, double px, double py,
                                              double sg, double key, int32_t e, int32_t src) {
   P.bb[i] = make_double2(b0, b1);
@@ -1413,29 +1436,61 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
       const double X = px + (x2 - px) * t;
       if (!isfinite(X)) acc.n_nonfin++;
       const bool occ = (X >= b0 - tol) && (X <= b1 + tol);
-      if (b0 <= tol) {
-        const double d = sg + sqrt(px * px + py * py);
-        if (d < g0 * kEv) {
-          e0 = true;
-          ev0 = v0;
-          ed0 = d;
-          eq0 = (h.pflags & 1) ? (e << 2) : -1;
-        }
+      // Every candidate value is computed before the decisions that use it,
+      // with no branch between the divisions and square roots, so that the
+      // independent chains of the three events and of both children overlap
+      // (a wavefront's lanes take different branches anyway). Each value is
+      // the same expression as where it is used; unused ones are dropped.
+      const double dE0 = sg + sqrt(px * px + py * py);
+      const double ex1 = px - L;
+      const double dE1 = sg + sqrt(ex1 * ex1 + py * py);
+      const double ax = x2 - px, ay = y2 - py;
+      const double d2 = sg + sqrt(ax * ax + ay * ay);
+      // left child, on the edge from v0 to v2
+      const double qL0 = (py * b0) / (x2 * py + y2 * (b0 - px));
+      const double qL1 = (py * b1) / (x2 * py + y2 * (b1 - px));
+      double cL0 = (b0 == 0.0 ? 0.0 : qL0) * l02, cL1 = (occ ? 1.0 : qL1) * l02;
+      if (cL0 < 0.0) cL0 = 0.0;
+      if (cL1 > l02) cL1 = l02;
+      const double uLx = ha.ulx, uLy = ha.uly;  // x2 / l02, y2 / l02
+      const double pLx = uLx * px + uLy * py;
+      double pLy = uLx * py - uLy * px;
+      if (pLy > 0.0) pLy = 0.0;
+      const double rLx = uLx * cL0 - L, rLy = uLy * cL0;
+      const double rLd = sqrt(rLx * rLx + rLy * rLy);
+      const int fL = child_filter_sl(cL0, cL1, pLx, pLy, sg, l02, g0, g2, true, g1, rLd, a.eps, a.ich_on);
+      const double kL = window_key_sl(cL0, cL1, pLx, pLy, sg);
+      // right child, on the edge from v2 to v1
+      const double ex = L - x2;
+      const double qR0 = ((x2 * py - py * b0) + y2 * (b0 - px)) / (y2 * (b0 - px) - ex * py);
+      const double qR1 = ((x2 * py - py * b1) + y2 * (b1 - px)) / (y2 * (b1 - px) - ex * py);
+      double cR0 = (occ ? 0.0 : qR0) * l12, cR1 = (b1 == L ? 1.0 : qR1) * l12;
+      if (cR0 < 0.0) cR0 = 0.0;
+      if (cR1 > l12) cR1 = l12;
+      const double uRx = ha.urx, uRy = ha.ury;  // (L - x2) / l12, (-y2) / l12
+      const double qx = px - x2, qy = py - y2;
+      const double pRx = uRx * qx + uRy * qy;
+      double pRy = uRx * qy - uRy * qx;
+      if (pRy > 0.0) pRy = 0.0;
+      const double rRx = x2 + uRx * cR1, rRy = y2 + uRy * cR1;
+      const double rRd = sqrt(rRx * rRx + rRy * rRy);
+      const int fR = child_filter_sl(cR0, cR1, pRx, pRy, sg, l12, g2, g1, false, g0, rRd, a.eps, a.ich_on);
+      const double kR = window_key_sl(cR0, cR1, pRx, pRy, sg);
+      // the decisions
+      if (b0 <= tol && dE0 < g0 * kEv) {
+        e0 = true;
+        ev0 = v0;
+        ed0 = dE0;
+        eq0 = (h.pflags & 1) ? (e << 2) : -1;
       }
-      if (b1 >= L - tol) {
-        const double dx = px - L;
-        const double d = sg + sqrt(dx * dx + py * py);
-        if (d < g1 * kEv) {
-          e1 = true;
-          ev1 = v1;
-          ed1 = d;
-          eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
-        }
+      if (b1 >= L - tol && dE1 < g1 * kEv) {
+        e1 = true;
+        ev1 = v1;
+        ed1 = dE1;
+        eq1 = (h.pflags & 2) ? ((e << 2) | 1) : -1;
       }
       bool doL = false, doR = false;
       if (occ) {
-        const double dx = x2 - px, dy = y2 - py;
-        const double d2 = sg + sqrt(dx * dx + dy * dy);
         if (d2 < g2 * kEv) {
           e2 = true;
           ev2 = v2;
@@ -1470,89 +1525,35 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
       if (doL) {
         if (h.tl < 0) {
           acc.n_notwin++;
+        } else if (fL == 1) {
+          acc.n_tiny++;
+        } else if (fL == 2) {
+          acc.n_ich++;
         } else {
-          double s0, s1;
-          if (b0 == 0.0) {
-            s0 = 0.0;
-          } else {
-            const double dn0 = x2 * py + y2 * (b0 - px);
-            s0 = (py * b0) / dn0;
-          }
-          if (occ) {
-            s1 = 1.0;
-          } else {
-            const double dn1 = x2 * py + y2 * (b1 - px);
-            s1 = (py * b1) / dn1;
-          }
-          double c0 = s0 * l02, c1 = s1 * l02;
-          if (c0 < 0.0) c0 = 0.0;
-          if (c1 > l02) c1 = l02;
-          const double ux = ha.ulx, uy = ha.uly;  // x2 / l02, y2 / l02
-          const double cpx = ux * px + uy * py;
-          double cpy = ux * py - uy * px;
-          if (cpy > 0.0) cpy = 0.0;
-          const double rx = ux * c0 - L, ry = uy * c0;
-          const double rdist = sqrt(rx * rx + ry * ry);
-          const int r = child_filter(c0, c1, cpx, cpy, sg, l02, g0, g2, true, true, g1, rdist, a.eps, a.ich_on);
-          if (r == 1) {
-            acc.n_tiny++;
-          } else if (r == 2) {
-            acc.n_ich++;
-          } else {
-            cl = true;
-            lb0 = c0;
-            lb1 = c1;
-            lpx = cpx;
-            lpy = cpy;
-            lkey = window_key(c0, c1, cpx, cpy, sg);
-            le = h.tl;
-          }
+          cl = true;
+          lb0 = cL0;
+          lb1 = cL1;
+          lpx = pLx;
+          lpy = pLy;
+          lkey = kL;
+          le = h.tl;
         }
       }
       if (doR) {
         if (h.tr < 0) {
           acc.n_notwin++;
+        } else if (fR == 1) {
+          acc.n_tiny++;
+        } else if (fR == 2) {
+          acc.n_ich++;
         } else {
-          const double ex = L - x2;
-          double r0, r1;
-          if (occ) {
-            r0 = 0.0;
-          } else {
-            const double nm0 = (x2 * py - py * b0) + y2 * (b0 - px);
-            const double dn0 = y2 * (b0 - px) - ex * py;
-            r0 = nm0 / dn0;
-          }
-          if (b1 == L) {
-            r1 = 1.0;
-          } else {
-            const double nm1 = (x2 * py - py * b1) + y2 * (b1 - px);
-            const double dn1 = y2 * (b1 - px) - ex * py;
-            r1 = nm1 / dn1;
-          }
-          double c0 = r0 * l12, c1 = r1 * l12;
-          if (c0 < 0.0) c0 = 0.0;
-          if (c1 > l12) c1 = l12;
-          const double ux = ha.urx, uy = ha.ury;  // (L - x2) / l12, (-y2) / l12
-          const double qx = px - x2, qy = py - y2;
-          const double cpx = ux * qx + uy * qy;
-          double cpy = ux * qy - uy * qx;
-          if (cpy > 0.0) cpy = 0.0;
-          const double rx = x2 + ux * c1, ry = y2 + uy * c1;
-          const double rdist = sqrt(rx * rx + ry * ry);
-          const int r = child_filter(c0, c1, cpx, cpy, sg, l12, g2, g1, true, false, g0, rdist, a.eps, a.ich_on);
-          if (r == 1) {
-            acc.n_tiny++;
-          } else if (r == 2) {
-            acc.n_ich++;
-          } else {
-            cr = true;
-            rb0 = c0;
-            rb1 = c1;
-            rpx = cpx;
-            rpy = cpy;
-            rkey = window_key(c0, c1, cpx, cpy, sg);
-            re = h.tr;
-          }
+          cr = true;
+          rb0 = cR0;
+          rb1 = cR1;
+          rpx = pRx;
+          rpy = pRy;
+          rkey = kR;
+          re = h.tr;
         }
       }
     }
