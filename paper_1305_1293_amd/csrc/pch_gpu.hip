@@ -471,20 +471,16 @@ __device__ void dev_sincos(double t, double* s, double* c) {
   *c = sc * cc;
 }
 
+
+
 // Selection key: distance from the source to the nearest point of the window
-// (the pseudo-source's distance plus its distance to the interval).
+// (the pseudo-source's distance plus its distance to the interval). The key
+// and the child filter below take their square roots before any decision
+// (straight-line code, so that independent roots overlap).
 __device__ __forceinline__ double window_key(double b0, double b1, double px, double py, double sg) {
-  double dseg;
-  if (px < b0) {
-    const double dx = b0 - px;
-    dseg = sqrt(dx * dx + py * py);
-  } else if (px > b1) {
-    const double dx = px - b1;
-    dseg = sqrt(dx * dx + py * py);
-  } else {
-    dseg = -py;
-  }
-  return sg + dseg;
+  const double dx = px < b0 ? b0 - px : px - b1;
+  const double dseg = sqrt(dx * dx + py * py);
+  return sg + ((px < b0 || px > b1) ? dseg : -py);
 }
 
 // Tiny-window trim and the Xin-Wang filter of Figure 4(b). u0/u1 are the
@@ -494,32 +490,6 @@ __device__ __forceinline__ double window_key(double b0, double b1, double px, do
 __device__ __forceinline__ int child_filter(double c0, double c1, double cpx, double cpy, double sg, double lc,
                                             double gu0, double gu1, bool rtest, bool r_at_c0, double gr,
                                             double rdist, double eps, bool ich_on) {
-  if (!(c1 - c0 > eps * lc)) return 1;
-  if (!ich_on) return 0;
-  const double dx1 = c1 - cpx;
-  const double f1 = sg + sqrt(dx1 * dx1 + cpy * cpy);
-  if (f1 > (gu0 + c1) * kFm) return 2;
-  const double dx0 = c0 - cpx;
-  const double f0 = sg + sqrt(dx0 * dx0 + cpy * cpy);
-  if (f0 > (gu1 + (lc - c0)) * kFm) return 2;
-  if (rtest) {
-    const double lhs = r_at_c0 ? f0 : f1;
-    if (lhs > (gr + rdist) * kFm) return 2;
-  }
-  return 0;
-}
-
-// window_key and child_filter (with the apex test) with their square roots
-// taken before any decision: the same values and the same decisions in the
-// same order, as straight-line code whose independent roots overlap
-__device__ __forceinline__ double window_key_sl(double b0, double b1, double px, double py, double sg) {
-  const double dx = px < b0 ? b0 - px : px - b1;
-  const double dseg = sqrt(dx * dx + py * py);
-  return sg + ((px < b0 || px > b1) ? dseg : -py);
-}
-__device__ __forceinline__ int child_filter_sl(double c0, double c1, double cpx, double cpy, double sg, double lc,
-                                               double gu0, double gu1, bool r_at_c0, double gr, double rdist,
-                                               double eps, bool ich_on) {
   const double dx1 = c1 - cpx;
   const double f1 = sg + sqrt(dx1 * dx1 + cpy * cpy);
   const double dx0 = c0 - cpx;
@@ -528,7 +498,7 @@ __device__ __forceinline__ int child_filter_sl(double c0, double c1, double cpx,
   if (!ich_on) return 0;
   if (f1 > (gu0 + c1) * kFm) return 2;
   if (f0 > (gu1 + (lc - c0)) * kFm) return 2;
-  if ((r_at_c0 ? f0 : f1) > (gr + rdist) * kFm) return 2;
+  if (rtest && (r_at_c0 ? f0 : f1) > (gr + rdist) * kFm) return 2;
   return 0;
 }
 
@@ -669,17 +639,17 @@ __device__ void fan_corner(const RoundArgs& a, int v, double d, double th, bool 
   if (t1 >= al) {
     c0 = 0.0;
   } else {
-    double s, c;
-    dev_sincos(t1, &s, &c);
-    const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+    double sn, cs;
+    dev_sincos(t1, &sn, &cs);
+    const double dx = cs * x2n - sn * y2n, dy = sn * x2n + cs * y2n;
     c0 = ipx - ipy * (dx / dy);
   }
   if (t0 <= 0.0) {
     c1 = Ln;
   } else {
-    double s, c;
-    dev_sincos(t0, &s, &c);
-    const double dx = c * x2n - s * y2n, dy = s * x2n + c * y2n;
+    double sn, cs;
+    dev_sincos(t0, &sn, &cs);
+    const double dx = cs * x2n - sn * y2n, dy = sn * x2n + cs * y2n;
     c1 = ipx - ipy * (dx / dy);
   }
   if (c0 < 0.0) c0 = 0.0;
@@ -1458,8 +1428,8 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
       if (pLy > 0.0) pLy = 0.0;
       const double rLx = uLx * cL0 - L, rLy = uLy * cL0;
       const double rLd = sqrt(rLx * rLx + rLy * rLy);
-      const int fL = child_filter_sl(cL0, cL1, pLx, pLy, sg, l02, g0, g2, true, g1, rLd, a.eps, a.ich_on);
-      const double kL = window_key_sl(cL0, cL1, pLx, pLy, sg);
+      const int fL = child_filter(cL0, cL1, pLx, pLy, sg, l02, g0, g2, true, true, g1, rLd, a.eps, a.ich_on);
+      const double kL = window_key(cL0, cL1, pLx, pLy, sg);
       // right child, on the edge from v2 to v1
       const double ex = L - x2;
       const double qR0 = ((x2 * py - py * b0) + y2 * (b0 - px)) / (y2 * (b0 - px) - ex * py);
@@ -1474,8 +1444,8 @@ __device__ __forceinline__ void prop_window(const RoundArgs& a, int p, const Pro
       if (pRy > 0.0) pRy = 0.0;
       const double rRx = x2 + uRx * cR1, rRy = y2 + uRy * cR1;
       const double rRd = sqrt(rRx * rRx + rRy * rRy);
-      const int fR = child_filter_sl(cR0, cR1, pRx, pRy, sg, l12, g2, g1, false, g0, rRd, a.eps, a.ich_on);
-      const double kR = window_key_sl(cR0, cR1, pRx, pRy, sg);
+      const int fR = child_filter(cR0, cR1, pRx, pRy, sg, l12, g2, g1, true, false, g0, rRd, a.eps, a.ich_on);
+      const double kR = window_key(cR0, cR1, pRx, pRy, sg);
       // the decisions
       if (b0 <= tol && dE0 < g0 * kEv) {
         e0 = true;
@@ -2221,49 +2191,79 @@ __global__ void __launch_bounds__(kBlock) k_select_propagate_r(RoundArgs a, int 
 // crossing). An event that reached its vertex's new distance copies it into
 // geod_dist, and each improved pseudo-source vertex records the smallest
 // incoming angle among those events.
+// A winning event at a pseudo-source vertex goes to the fan pass's candidate
+// list, one reservation per wavefront (every lane of the wavefront calls it).
+__device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool win, int32_t v, double d, double th) {
+  const u64 mask = __ballot(win);
+  if (!mask) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  u64 base = 0;
+  if (lane_id() == leader) base = atomicAdd(&c->ncand, (u64)__popcll(mask));
+  base = shfl64(base, leader);
+  if (win) {
+    const u64 j = base + (u64)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    if (j < (u64)a.ecap) {
+      a.cand.vq[j] = make_int2(v, -1);
+      a.cand.d[j] = d;
+      a.cand.xy[j] = make_double2(th, 0.0);
+    }
+  }
+}
+
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
   const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
-  for (u64 i = t0; i < na; i += stride) {
-    const int32_t e = i == t0 ? f.e : a.aev.e[i];
-    const double D = i == t0 ? f.D : a.aev.D[i];
-    const double X = i == t0 ? f.X : a.aev.X[i];
-    if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.asw[e].D)) atomicMin(&a.s.asw[e].X, ordkey(X));
-  }
-  for (u64 i = t0; i < nd; i += stride) {
-    const int2 vq = i == t0 ? f.vq : a.ev[p].vq[i];
-    const double d = i == t0 ? f.d : a.ev[p].d[i];
-    const double2 xy = i == t0 ? f.xy : a.ev[p].xy[i];
-    const int32_t v = vq.x;
-    const bool top = idx_ok(c, v, a.m.nv) && bits(d) == lda(&a.s.gw[v]);
-    if (top) a.s.g[v] = bits(d);
-    const bool win = top && (a.m.flags[v] & pch::VF_PSEUDO);
+  // The lane's first angle event and first distance event take every load
+  // that depends only on their records in one batch: the corner's apex
+  // distance and the vertex's write-copy distance and flags.
+  const bool aok = t0 < na && idx_ok(c, f.e, a.m.nh);
+  const bool vok = t0 < nd && idx_ok(c, f.vq.x, a.m.nv);
+  const int32_t ea = aok ? f.e : 0;
+  const int32_t v = vok ? f.vq.x : 0;
+  const u64 asD = lda(&a.s.asw[ea].D);
+  const u64 gwv = lda(&a.s.gw[v]);
+  const uint8_t fl = a.m.flags[v];
+  if (aok && bits(f.D) == asD) atomicMin(&a.s.asw[ea].X, ordkey(f.X));
+  {
+    const bool top = vok && bits(f.d) == gwv;
+    if (top) a.s.g[v] = bits(f.d);
+    const bool win = top && (fl & pch::VF_PSEUDO);
     double th = 0.0;
     if (win) {
       // the incoming angle of an event that wins a pseudo-source vertex
-      th = vq.y >= 0 ? event_angle(a.m, vq.y, xy.x, xy.y) : xy.x;
+      th = f.vq.y >= 0 ? event_angle(a.m, f.vq.y, f.xy.x, f.xy.y) : f.xy.x;
       atomicMin(&a.s.fanth[v], ordkey(th));
     }
-    // the winners go to the fan pass's candidate list, one reservation per
-    // wavefront (lanes that already left the loop take no part)
-    const u64 mask = __ballot(win);
-    if (mask) {
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      u64 base = 0;
-      if (lane_id() == leader) base = atomicAdd(&c->ncand, (u64)__popcll(mask));
-      base = shfl64(base, leader);
+    add_candidate(a, c, win, v, f.d, th);
+  }
+  // the rest (more events than the launch has threads)
+  for (u64 i = t0 + stride; i < na; i += stride) {
+    const int32_t e = a.aev.e[i];
+    const double D = a.aev.D[i];
+    const double X = a.aev.X[i];
+    if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.asw[e].D)) atomicMin(&a.s.asw[e].X, ordkey(X));
+  }
+  for (u64 i = t0 + stride; i - lane_id() < nd; i += stride) {
+    bool win = false;
+    int32_t vi = 0;
+    double d = 0.0, th = 0.0;
+    if (i < nd) {
+      const int2 vq = a.ev[p].vq[i];
+      d = a.ev[p].d[i];
+      const double2 xy = a.ev[p].xy[i];
+      vi = vq.x;
+      const bool top = idx_ok(c, vi, a.m.nv) && bits(d) == lda(&a.s.gw[vi]);
+      if (top) a.s.g[vi] = bits(d);
+      win = top && (a.m.flags[vi] & pch::VF_PSEUDO);
       if (win) {
-        const u64 j = base + (u64)__popcll(mask & ((1ull << lane_id()) - 1ull));
-        if (j < (u64)a.ecap) {
-          a.cand.vq[j] = make_int2(v, -1);
-          a.cand.d[j] = d;
-          a.cand.xy[j] = make_double2(th, 0.0);
-        }
+        th = vq.y >= 0 ? event_angle(a.m, vq.y, xy.x, xy.y) : xy.x;
+        atomicMin(&a.s.fanth[vi], ordkey(th));
       }
     }
+    add_candidate(a, c, win, vi, d, th);
   }
 }
 
@@ -2291,14 +2291,24 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
     f_d = a.cand.d[i0];
     f_th = a.cand.xy[i0].x;
   }
+  int32_t f_e = 0;
+  if (t0 < (u64)a.acap) f_e = a.aev.e[t0];
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ncand, (u64)a.ecap) : 0;
   const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
   const u32 stamp = (u32)c->round;
   const int po = (int)(c->pout & 1);
   // the corners this round's angle events touched take their final values
-  // (the first event pass is over) from the write copy
-  for (u64 i = t0; i < na; i += stride) {
+  // (the first event pass is over) from the write copy; the lane's first
+  // corner is copied together with its first candidate's loads below (the
+  // fans neither read nor write angle_split)
+  const bool f_ok = t0 < na && idx_ok(c, f_e, a.m.nh);
+  u64 f_swD = 0, f_swX = 0;  // the corner's write copy, stored after the fans
+  if (f_ok) {
+    f_swD = a.s.asw[f_e].D;
+    f_swX = a.s.asw[f_e].X;
+  }
+  for (u64 i = t0 + stride; i < na; i += stride) {
     const int32_t e = a.aev.e[i];
     if (idx_ok(c, e, a.m.nh)) a.s.as[e] = a.s.asw[e];
   }
@@ -2335,6 +2345,10 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
       }
     }
     wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, po, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
+  }
+  if (f_ok) {
+    a.s.as[f_e].D = f_swD;
+    a.s.as[f_e].X = f_swX;
   }
   u32 tot[5] = {kept, tiny, ich, fans, notwin};
   block_totals(kmn, kmx, tot);
