@@ -440,7 +440,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["field", "learned"], default="field")
+    ap.add_argument("--workload", choices=["field", "learned", "icosphere"], default="field",
+                    help="field: the bench line; learned: the learned-cutoff comparison; icosphere: only the "
+                         "icosphere leg (for profiling its kernels alone)")
     ap.add_argument("--k", type=int, default=524288, help="windows selected per round (bump grid)")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
@@ -495,6 +497,9 @@ def main():
         return
     if args.workload == "learned":
         print(json.dumps(measure_learned(args, pch, G, torch)), flush=True)
+        return
+    if args.workload == "icosphere":
+        print(json.dumps(measure_icosphere(args, pch, G, torch)), flush=True)
         return
     m = G.config_mesh(3)
     rng = np.random.default_rng(2024)
