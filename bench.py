@@ -204,7 +204,9 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
     kernel = plan_kernel.get(tot["scan_fused"], "k_propagate_fused" if hop_launches == 1 else "k_propagate")
     fp64 = {"bound": "fp64", "achieved": round(tflops, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / FP64_PEAK_TFLOPS, 6), "alg_flop_per_launch": round(flops_per_launch, 1),
-            "counter_flop_per_launch": counter_flops}
+            "counter_flop_per_launch": counter_flops,
+            "counter_basis": "64 lanes x SQ_INSTS_VALU_FLOPS_FP64 per launch (FP64 lane operations issued, "
+                             "FMA as 2), from the committed counter summary of this kernel source"}
     # share of the timed rounds' GPU time per phase
     ptot = sum(phase.values())
     phases = {"ms_per_field": {k: round(v / max(tot["timed_rounds"], 1) * tot["rounds"] / steps, 3)
@@ -213,6 +215,9 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
               "timed_rounds": tot["timed_rounds"]}
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "traffic_basis": "HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scaled by a 512 MiB "
+                             "copy), from the committed counter summary of this kernel source; null when the "
+                             "kernel or the configuration changed since",
             "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "alg_bytes_per_launch": round(bytes_per_launch, 1), "launches": all_launches,
             "timed_launches": tot["propagate_launches"],
@@ -236,9 +241,10 @@ def measure_icosphere(args, pch, G, torch):
         errs.append(float(np.max(np.abs(keep[i].cpu().numpy() - ref) / np.maximum(ref, hbar))))
     mesh.close()
     kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}.get(tot["scan_fused"], "k_propagate_fused")
-    traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch",
-                            "select=1 k=12288 hops=5 fuse_hops=1")
-    roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, None)
+    tag = "select=1 k=12288 hops=5 fuse_hops=1"
+    traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch", tag)
+    cflops = profile_value(f"{kernel}_icosphere7_traffic.md", "fp64_flop_per_launch", tag)
+    roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, cflops)
     return {"workload": "bumpy icosphere, 7 midpoint subdivisions, 327,680 faces, seeded random sources",
             "ms_per_field": round(1000.0 * wall / args.steps, 4), "steps": args.steps,
             "windows_per_s": round(tot["processed"] / wall, 1), "rounds_per_field": tot["rounds"] / args.steps,
