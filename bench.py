@@ -385,7 +385,8 @@ def measure_learned_batched(pch, G, Lr, mlp, torch):
             "learned_batched_vs_adaptive_batched": round(res["adaptive_step"]["ms"] / lb, 3),
             "learned_vs_chord_batched": round((res["chord"]["ms"] + res["chord"]["predict_ms"]) / lb, 3),
             "max_rel_diff_vs_adaptive": diff,
-            "note": "learned and chord times include the predictions of all 512 fields (predict_ms)"}
+            "note": "runs[...].ms is the batched launch alone; the ratios add the predictions of all 512 "
+                    "fields (predict_ms) to the learned and chord launches"}
 
 
 def measure_learned(args, pch, G, torch):
