@@ -555,6 +555,28 @@ __device__ __forceinline__ double event_angle(const DevMesh& m, int q, double px
   return ha.th2 + dev_atan2(cr, dt);
 }
 
+// The half-edge values an incoming angle needs (loaded ahead of the decision
+// to evaluate it), and the angle from them: the same arithmetic as
+// event_angle.
+struct AngleRecipe {
+  double th, L, x2, y2;
+  int k;
+};
+__device__ __forceinline__ AngleRecipe load_recipe(const DevMesh& m, int q) {
+  const int e = q >> 2, k = q & 3;
+  const pch::HalfEdge h = m.hl[e].h;
+  const pch::HalfEdgeAng ha = m.hl[e].a;
+  return AngleRecipe{k == 0 ? ha.th0 : (k == 1 ? ha.th1 : ha.th2), h.L, h.x2, h.y2, k};
+}
+__device__ __forceinline__ double recipe_angle(const AngleRecipe& r, double px, double py) {
+  if (r.k == 0) return r.th - dev_atan2(-py, px);
+  if (r.k == 1) return r.th + dev_atan2(-py, r.L - px);
+  const double ux = -r.x2, uy = -r.y2, wx = px - r.x2, wy = py - r.y2;
+  const double cr = ux * wy - uy * wx;
+  const double dt = ux * wx + uy * wy;
+  return r.th + dev_atan2(cr, dt);
+}
+
 // One corner of a fan of windows from pseudo-source vertex v reached at
 // distance d, the incoming ray's back direction at angular position th
 // (Figure 3(c)). A corner that meets the sector of directions at least pi away
@@ -2193,7 +2215,7 @@ __global__ void __launch_bounds__(kBlock) k_select_propagate_r(RoundArgs a, int 
 // incoming angle among those events.
 // A winning event at a pseudo-source vertex goes to the fan pass's candidate
 // list, one reservation per wavefront (every lane of the wavefront calls it).
-__device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool win, int32_t v, double d, double th) {
+__device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool win, int32_t v, double d) {
   const u64 mask = __ballot(win);
   if (!mask) return;
   const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -2205,7 +2227,6 @@ __device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool w
     if (j < (u64)a.ecap) {
       a.cand.vq[j] = make_int2(v, -1);
       a.cand.d[j] = d;
-      a.cand.xy[j] = make_double2(th, 0.0);
     }
   }
 }
@@ -2216,28 +2237,36 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ndev[p], (u64)a.ecap) : 0;
   const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
+  const u32 stamp = (u32)c->round;
   // The lane's first angle event and first distance event take every load
   // that depends only on their records in one batch: the corner's apex
-  // distance and the vertex's write-copy distance and flags.
+  // distance, the vertex's write-copy distance and flags, and the half-edge
+  // values of the incoming-angle recipe (an event with a recipe names a
+  // pseudo-source vertex; the angle is evaluated for the winners only).
   const bool aok = t0 < na && idx_ok(c, f.e, a.m.nh);
   const bool vok = t0 < nd && idx_ok(c, f.vq.x, a.m.nv);
+  const bool rok = vok && f.vq.y >= 0 && idx_ok(c, f.vq.y >> 2, a.m.nh);
   const int32_t ea = aok ? f.e : 0;
   const int32_t v = vok ? f.vq.x : 0;
   const u64 asD = lda(&a.s.asw[ea].D);
   const u64 gwv = lda(&a.s.gw[v]);
   const uint8_t fl = a.m.flags[v];
+  const AngleRecipe rc = load_recipe(a.m, rok ? f.vq.y : 0);
   if (aok && bits(f.D) == asD) atomicMin(&a.s.asw[ea].X, ordkey(f.X));
   {
     const bool top = vok && bits(f.d) == gwv;
     if (top) a.s.g[v] = bits(f.d);
     const bool win = top && (fl & pch::VF_PSEUDO);
     double th = 0.0;
+    bool first = false;
     if (win) {
-      // the incoming angle of an event that wins a pseudo-source vertex
-      th = f.vq.y >= 0 ? event_angle(a.m, f.vq.y, f.xy.x, f.xy.y) : f.xy.x;
+      // the incoming angle of an event that wins a pseudo-source vertex; the
+      // first winner to claim the vertex this round lists it for its fan
+      th = f.vq.y >= 0 ? recipe_angle(rc, f.xy.x, f.xy.y) : f.xy.x;
       atomicMin(&a.s.fanth[v], ordkey(th));
+      first = atomicMax(&a.s.claim[v], stamp) < stamp;
     }
-    add_candidate(a, c, win, v, f.d, th);
+    add_candidate(a, c, first, v, f.d);
   }
   // the rest (more events than the launch has threads)
   for (u64 i = t0 + stride; i < na; i += stride) {
@@ -2257,13 +2286,13 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
       vi = vq.x;
       const bool top = idx_ok(c, vi, a.m.nv) && bits(d) == lda(&a.s.gw[vi]);
       if (top) a.s.g[vi] = bits(d);
-      win = top && (a.m.flags[vi] & pch::VF_PSEUDO);
-      if (win) {
+      if (top && (a.m.flags[vi] & pch::VF_PSEUDO)) {
         th = vq.y >= 0 ? event_angle(a.m, vq.y, xy.x, xy.y) : xy.x;
         atomicMin(&a.s.fanth[vi], ordkey(th));
+        win = atomicMax(&a.s.claim[vi], stamp) < stamp;
       }
     }
-    add_candidate(a, c, win, vi, d, th);
+    add_candidate(a, c, win, vi, d);
   }
 }
 
@@ -2285,18 +2314,16 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   // the lane's first candidate is loaded together with the round's counters
   // (indices below the capacity are in bounds)
   int32_t f_v = 0;
-  double f_d = 0.0, f_th = 0.0;
+  double f_d = 0.0;
   if (i0 < (u64)a.ecap) {
     f_v = a.cand.vq[i0].x;
     f_d = a.cand.d[i0];
-    f_th = a.cand.xy[i0].x;
   }
   int32_t f_e = 0;
   if (t0 < (u64)a.acap) f_e = a.aev.e[t0];
   const bool active = c->active != 0;
   const u64 nd = active ? min(c->ncand, (u64)a.ecap) : 0;
   const u64 na = active ? min(c->naev, (u64)a.acap) : 0;
-  const u32 stamp = (u32)c->round;
   const int po = (int)(c->pout & 1);
   // the corners this round's angle events touched take their final values
   // (the first event pass is over) from the write copy; the lane's first
@@ -2323,23 +2350,22 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
       if (j0 == 0) {
         v = f_v;
         d = f_d;
-        th = f_th;
       } else {
         v = a.cand.vq[i].x;
         d = a.cand.d[i];
-        th = a.cand.xy[i].x;
       }
       const bool okv = idx_ok(c, v, a.m.nv);
       if (!okv) v = 0;
-      // everything that depends on v only, in one batch of loads
-      const u64 gv = lda(&a.s.g[v]);
+      // a candidate is a vertex that a winning event reached at a
+      // pseudo-source, listed once (claimed in the first pass); its fan starts
+      // from the round's distance with the smallest incoming angle of its
+      // winners
       const u64 fv = lda(&a.s.fanth[v]);
-      const uint8_t fl = a.m.flags[v];
       q0 = a.m.coff[v];
       q1 = a.m.coff[v + 1];
-      if (okv && bits(d) == gv && (fl & pch::VF_PSEUDO) && ordkey(th) == fv &&
-          atomicMax(&a.s.claim[v], stamp) < stamp) {
+      if (okv) {
         a.s.fanth[v] = kAllOnes;
+        th = from_ordkey(fv);
         has = true;
         fans++;
       }
