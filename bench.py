@@ -68,6 +68,7 @@ FLOP_PER_CHILD = 50
 # host core)
 CPU_SAMPLE_WINDOWS = 20_000_000
 GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "bump_grid1024_s2_ich.npz")
+GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "icosphere7_ich.npz")
 
 
 def kernel_source_hash() -> str:
@@ -225,20 +226,22 @@ def roofline_of(tot, phase, hop_launches, wall, steps, traffic, counter_flops):
 
 
 def measure_icosphere(args, pch, G, torch):
-    """The bumpy icosphere (327,680 faces) at its own best setting; two fields
-    checked against ICH."""
-    from oracle import oracle as O
+    """The bumpy icosphere (327,680 faces) at its own best setting; after the
+    timed fields, the fields from the two sources of the stored exact ICH
+    fields are computed with the same options and checked against them."""
     m = G.config_mesh(2)
     rng = np.random.default_rng(2024)
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
     opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=5)
-    wall, tot, phase, hl, keep = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=2)
-    hbar = float(O.lengths(m).mean())
+    wall, tot, phase, hl, _ = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=0)
     errs = []
-    for i in range(2):
-        ref, _ = O.ich(m, [int(srcs[args.warmup + i])])
-        errs.append(float(np.max(np.abs(keep[i].cpu().numpy() - ref) / np.maximum(ref, hbar))))
+    if os.path.exists(GOLDEN_C2):
+        gold = np.load(GOLDEN_C2)
+        hbar = float(gold["mean_edge"])
+        for s, ref in zip(gold["sources"], gold["dist"]):
+            d = pch.geodesic(mesh, [int(s)], **{k: v for k, v in opts.items() if k != "collect_timing"})
+            errs.append(float(np.max(np.abs(d.cpu().numpy() - ref) / np.maximum(ref, hbar))))
     mesh.close()
     kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}.get(tot["scan_fused"], "k_propagate_fused")
     tag = "select=1 k=12288 hops=5 fuse_hops=1"
@@ -249,7 +252,7 @@ def measure_icosphere(args, pch, G, torch):
             "ms_per_field": round(1000.0 * wall / args.steps, 4), "steps": args.steps,
             "windows_per_s": round(tot["processed"] / wall, 1), "rounds_per_field": tot["rounds"] / args.steps,
             "options": {k: v for k, v in opts.items() if k != "collect_timing"},
-            "max_rel_err_vs_oracle": max(errs), "roofline": roof, "phases": phases}
+            "max_rel_err_vs_oracle": max(errs) if errs else None, "roofline": roof, "phases": phases}
 
 
 def measure_batched(args, pch, G, torch):
