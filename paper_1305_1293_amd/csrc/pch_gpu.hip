@@ -1779,15 +1779,18 @@ constexpr int kFuseHops = 6;          // hops that one fused launch carries
 constexpr int kFuseCap = 2 * kBlock;  // windows a hop list in LDS holds
 
 // The pool scan of the fused launches deals the pool in 64-slot chunks,
-// round-robin over the G workgroups: ticket t stands for workgroup slot t % G
-// of deal t / G, in which wave w of the workgroup scans chunk
-// ((t / G) nW + w) G + t % G. The newest windows, which hold most of a
-// round's selected ones, sit together at the end of the pool; dealt this way
-// they spread over every workgroup instead of loading a few with long hop
-// chains. Each workgroup takes ticket blockIdx.x first and then the next free
-// one from a counter, so workgroups whose windows hop little scan more.
-// Called by the whole workgroup (uniformly); returns false once the
-// workgroup's ticket lies past the pool, else sets i to this thread's slot.
+// round-robin over the G workgroups, newest chunks first: ticket t stands for
+// workgroup slot t % G of deal t / G, in which wave w of the workgroup scans
+// chunk M - 1 - (((t / G) nW + w) G + t % G) of the pool's M chunks. The
+// newest windows, which hold most of a round's selected ones, sit together
+// at the end of the pool; dealt this way they spread over every workgroup
+// instead of loading a few with long hop chains, and they are dealt first,
+// so the chunks with the longest hop chains start first and the light ones
+// fill in at the end. Each workgroup takes ticket blockIdx.x first and then
+// the next free one from a counter, so workgroups whose windows hop little
+// scan more. Called by the whole workgroup (uniformly); returns false once
+// the workgroup's ticket lies past the pool, else sets i to this thread's
+// slot (N for a wave whose chunk lies past the pool).
 __device__ __forceinline__ bool scan_ticket(Ctl* c, u64 N, u32 G, u32 nW, bool& first, u32& ticket, u32* s_ticket,
                                             u64& i) {
   if (!first) {
@@ -1797,8 +1800,10 @@ __device__ __forceinline__ bool scan_ticket(Ctl* c, u64 N, u32 G, u32 nW, bool& 
   }
   first = false;
   const u64 deal = ticket / G, slot = ticket % G;
-  if ((deal * nW * G + slot) * kWave >= N) return false;
-  i = ((deal * nW + threadIdx.x / kWave) * G + slot) * kWave + lane_id();
+  const u64 M = (N + kWave - 1) / kWave;
+  if (deal * nW * G + slot >= M) return false;
+  const u64 kc = (deal * nW + threadIdx.x / kWave) * G + slot;
+  i = kc < M ? (M - 1 - kc) * kWave + lane_id() : N;
   return true;
 }
 
