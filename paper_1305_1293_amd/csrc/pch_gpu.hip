@@ -711,11 +711,14 @@ __device__ __forceinline__ double shfl_d(double x, int src) {
 // v at distance d). The wavefront's (fan, corner) pairs are spread over its
 // lanes: an exclusive prefix sum of the fan degrees numbers the pairs and each
 // lane finds the owner of its pair by binary search over the lanes. Windows
-// and events are reserved once per wavefront and step; windows go to pool
+// and events are reserved once per wavefront and step (kBlk: once per
+// workgroup and step, every thread of the workgroup calling it, so that a
+// launch's waves meet at the two counters 4x less often); windows go to pool
 // buffer po, events to event buffer qi. Every lane of the wavefront must call
 // it.
 // The lane's corners are q0 .. q0 + deg - 1 of the CCW corner list (deg = 0
 // when it has no fan).
+template <bool kBlk = false>
 __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, double d, double th, bool full,
                           int po, int qi, u64& kmn, u64& kmx, u32& kept, u32& tiny, u32& ich, u32& defer,
                           u32& notwin) {
@@ -732,7 +735,7 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
   const int base = incl - deg;
   const Pool P = po ? a.pool[1] : a.pool[0];
   const DistEv& E = a.ev[qi];
-  for (int t0 = 0; t0 < total; t0 += kWave) {
+  for (int t0 = 0; kBlk ? __syncthreads_or(t0 < total) : t0 < total; t0 += kWave) {
     const int t = t0 + lane;
     // owner: the largest lane whose base is <= t (lanes with deg 0 share the
     // base of the next lane, so the largest such lane owns the pair)
@@ -755,7 +758,14 @@ __device__ void wave_fans(const RoundArgs& a, bool has, int v, int q0, int deg, 
     const u32 nev = (o.ea ? 1u : 0u) + (o.eb ? 1u : 0u);
     u64 jw, je, jz;
     u32 tw, te, tz;
-    wave_reserve3(&c->npool[po], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, jw, je, jz, tw, te, tz);
+    if constexpr (kBlk) {
+      u64 j3;
+      u32 t3;
+      block_reserve4(&c->npool[po], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, &c->ndev[qi], 0u, jw, je,
+                     jz, j3, tw, te, tz, t3);
+    } else {
+      wave_reserve3(&c->npool[po], o.win ? 1u : 0u, &c->ndev[qi], nev, &c->ndev[qi], 0u, jw, je, jz, tw, te, tz);
+    }
     if (o.win) {
       if (jw < (u64)a.cap) {
         store_window(P, jw, o.b0, o.b1, o.px, o.py, od, o.key, o.e, ov);
@@ -2219,8 +2229,21 @@ __global__ void __launch_bounds__(kBlock) k_select_propagate_r(RoundArgs a, int 
 // geod_dist, and each improved pseudo-source vertex records the smallest
 // incoming angle among those events.
 // A winning event at a pseudo-source vertex goes to the fan pass's candidate
-// list, one reservation per wavefront (every lane of the wavefront calls it).
+// list, one reservation per wavefront (every lane of the wavefront calls it),
+// or with kBlk one per workgroup (every thread of the workgroup calls it).
+template <bool kBlk = false>
 __device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool win, int32_t v, double d) {
+  if constexpr (kBlk) {
+    u64 j, s1, s2, s3;
+    u32 t0, t1, t2, t3;
+    block_reserve4(&c->ncand, win ? 1u : 0u, &c->ncand, 0u, &c->ncand, 0u, &c->ncand, 0u, j, s1, s2, s3, t0, t1, t2,
+                   t3);
+    if (win && j < (u64)a.ecap) {
+      a.cand.vq[j] = make_int2(v, -1);
+      a.cand.d[j] = d;
+    }
+    return;
+  }
   const u64 mask = __ballot(win);
   if (!mask) return;
   const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -2236,6 +2259,7 @@ __device__ __forceinline__ void add_candidate(const RoundArgs& a, Ctl* c, bool w
   }
 }
 
+template <bool kBlk = false>
 __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   const FirstEvents f = first_events(a, p, t0);
@@ -2265,13 +2289,15 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     double th = 0.0;
     bool first = false;
     if (win) {
-      // the incoming angle of an event that wins a pseudo-source vertex; the
-      // first winner to claim the vertex this round lists it for its fan
+      // the first winner to claim a pseudo-source vertex this round lists it
+      // for its fan (the claim is issued first, so that its round trip
+      // overlaps the evaluation of the winner's incoming angle)
+      const u32 old = atomicMax(&a.s.claim[v], stamp);
       th = f.vq.y >= 0 ? recipe_angle(rc, f.xy.x, f.xy.y) : f.xy.x;
       atomicMin(&a.s.fanth[v], ordkey(th));
-      first = atomicMax(&a.s.claim[v], stamp) < stamp;
+      first = old < stamp;
     }
-    add_candidate(a, c, first, v, f.d);
+    add_candidate<kBlk>(a, c, first, v, f.d);
   }
   // the rest (more events than the launch has threads)
   for (u64 i = t0 + stride; i < na; i += stride) {
@@ -2280,7 +2306,8 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
     const double X = a.aev.X[i];
     if (idx_ok(c, e, a.m.nh) && bits(D) == lda(&a.s.asw[e].D)) atomicMin(&a.s.asw[e].X, ordkey(X));
   }
-  for (u64 i = t0 + stride; i - lane_id() < nd; i += stride) {
+  // (wave-uniform trip count; workgroup-uniform with kBlk)
+  for (u64 i = t0 + stride; i - (kBlk ? threadIdx.x : lane_id()) < nd; i += stride) {
     bool win = false;
     int32_t vi = 0;
     double d = 0.0, th = 0.0;
@@ -2292,23 +2319,25 @@ __device__ __forceinline__ void ph_events2(const RoundArgs& a, int p, u64 t0, u6
       const bool top = idx_ok(c, vi, a.m.nv) && bits(d) == lda(&a.s.gw[vi]);
       if (top) a.s.g[vi] = bits(d);
       if (top && (a.m.flags[vi] & pch::VF_PSEUDO)) {
+        const u32 old = atomicMax(&a.s.claim[vi], stamp);
         th = vq.y >= 0 ? event_angle(a.m, vq.y, xy.x, xy.y) : xy.x;
         atomicMin(&a.s.fanth[vi], ordkey(th));
-        win = atomicMax(&a.s.claim[vi], stamp) < stamp;
+        win = old < stamp;
       }
     }
-    add_candidate(a, c, win, vi, d);
+    add_candidate<kBlk>(a, c, win, vi, d);
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_events2(RoundArgs a, int p) {
-  ph_events2(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+  ph_events2<true>(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
 // Second event pass: the corners' final values into angle_split, and one fan
 // per improved pseudo-source vertex: windows into the next pool, deferred
 // endpoint events into geod_dist's write copy and the next round's event
 // buffer.
+template <bool kBlk = false>
 __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u64 stride) {
   Ctl* c = a.ctl;
   // Distance events are dealt round-robin over the launch's wavefronts (event
@@ -2346,7 +2375,9 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
   }
   u64 kmn = kAllOnes, kmx = 0;
   u32 kept = 0, tiny = 0, ich = 0, defer = 0, notwin = 0, fans = 0;
-  for (u64 j0 = 0; w + j0 < nd; j0 += stride) {
+  // (wave-uniform trip count; workgroup-uniform with kBlk)
+  const u64 wl = kBlk ? (t0 - threadIdx.x) / kWave : w;
+  for (u64 j0 = 0; wl + j0 < nd; j0 += stride) {
     const u64 i = j0 + i0;
     bool has = false;
     int v = 0, q0 = 0, q1 = 0;
@@ -2375,7 +2406,8 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
         fans++;
       }
     }
-    wave_fans(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, po, 1 - p, kmn, kmx, kept, tiny, ich, defer, notwin);
+    wave_fans<kBlk>(a, has, v, q0, q1 - q0, d, th, a.full_fan != 0, po, 1 - p, kmn, kmx, kept, tiny, ich, defer,
+                    notwin);
   }
   if (f_ok) {
     a.s.as[f_e].D = f_swD;
@@ -2400,7 +2432,7 @@ __device__ __forceinline__ void ph_events3(const RoundArgs& a, int p, u64 t0, u6
 __global__ void __launch_bounds__(kBlock) k_events3(RoundArgs a, int p) {
   __shared__ int is_last;
   Ctl* c = a.ctl;
-  ph_events3(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
+  ph_events3<true>(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
   // The set-up reads only counters, which every workgroup updates with
   // device-scope atomics and the set-up reads with device-scope atomic loads;
   // waiting until this wavefront's memory operations have completed orders
