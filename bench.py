@@ -168,6 +168,7 @@ def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
             phase[kk] += st["ms_phase"][kk]
         hop_launches = st["hop_launches"]
         tot["scan_fused"] = st["scan_fused"]  # the launch plan (the same every field)
+        tot["fused_workgroups"] = st["fused_workgroups"]
         if i < keep_first:
             keep.append(out.clone())
     torch.cuda.synchronize()
@@ -579,7 +580,8 @@ def main():
                                "first timed field from vertex 0, the others from seeded random vertices",
                    "faces": m.nf, "vertices": m.nv, "k": args.k,
                    "select": ["kth", "adaptive-step"][args.select], "hops": args.hops,
-                   "propagation_launches_per_round": hop_launches},
+                   "propagation_launches_per_round": hop_launches,
+                   "propagation_workgroups": tot["fused_workgroups"]},
         "windows_per_s": round(tot["processed"] / wall, 1),
         "fields_per_s": round(args.steps / wall, 3),
         "windows_per_field": round(tot["processed"] / args.steps, 1),

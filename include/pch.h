@@ -206,6 +206,10 @@ typedef struct {
                                 pool scan inside the propagation launch;
                                 2 = the same with each thread's first
                                 hopping child held in registers */
+  int32_t fused_workgroups;  /* workgroups of the fused plans' propagation
+                                launch: as many as the device holds at once
+                                (the occupancy of that launch times the
+                                compute units); 0 for the partition plan */
 } pch_stats;
 
 /* Exact geodesic distance from the sources (Algorithm 1).

@@ -2117,6 +2117,7 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
     bool have = false;
     double2 wbb = make_double2(0.0, 0.0), wpp = wbb, wsk = wbb;
     int2 wes = make_int2(0, 0);
+    u64 rest = 0;  // the length of this hop's list after the step (hops >= 2)
     if (lvl == 1) {
       u64 i = 0;
       if (!scan_ticket(c, N, (u32)(stride / BS), BS / kWave, first, ticket, &s_ticket, i)) break;
@@ -2186,14 +2187,18 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
         wsk = make_double2(l_sg[lvl - 2][j], 0.0);
         wes = l_es[lvl - 2][j];
       }
-      __syncthreads();  // every thread has its window before the list shrinks
-      if (threadIdx.x == 0) l_n[lvl] = n - take;
+      rest = n - take;
       if (have) n_hop++;
     }
     const int nl = lvl < kTop ? lvl + 1 : kTop;
     const HopList HQ{l_bb[nl - 2], l_pp[nl - 2], l_sg[nl - 2], l_es[nl - 2]};
     prop_window<true, HopList, true, BS>(a, p, x, have, wbb, wpp, wsk, wes, lvl < hops, HQ, &l_n[nl], (u64)BS,
                                          acc, &rw);
+    // The list of this hop shrinks only now: every thread read its length
+    // before the reservation barriers of prop_window, and no thread appends
+    // to it in this step (children go to the list of the next hop; the last
+    // hop appends nothing), so its windows taken above stay intact.
+    if (lvl >= 2 && threadIdx.x == 0) l_n[lvl] = rest;
     // deeper when some lane holds a register window or the next list has
     // windows (the list length is visible after the barrier)
     const int deeper = __syncthreads_or(rw.has ? 1 : 0);
@@ -2215,8 +2220,11 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
   prop_finish(a, p, acc);
 }
 
+// Three workgroups per compute unit hold the four hop lists of the 5-hop
+// instance in LDS; the bound keeps the registers within a third of the file
+// (at most 168 per lane) so that the registers allow three as well.
 template <int NL>
-__global__ void __launch_bounds__(kBlock) k_select_propagate_r(RoundArgs a, int p) {
+__global__ void __launch_bounds__(kBlock, 3) k_select_propagate_r(RoundArgs a, int p) {
   ph_select_propagate<NL, kBlock>(a, p, blockIdx.x * (u64)kBlock + threadIdx.x, (u64)gridDim.x * kBlock);
 }
 
@@ -3760,6 +3768,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
   int64_t prop_n = 0, timed_rounds = 0;
   double phase_ms[4] = {0.0, 0.0, 0.0, 0.0};
   RoundPlan plan_used = kSplit;
+  int fused_wg = 0;
   for (;;) {
     // the hop queues in device memory serve only one launch per hop (fused
     // hops keep their windows in LDS)
@@ -3823,6 +3832,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     // rest (scan_ticket)
     const int fused_blocks = plan == kSplit ? 0 : resident_blocks(a.hops, plan == kScanFusedReg);
     if (fused_blocks > 0) pool_blocks = fused_blocks;
+    fused_wg = fused_blocks;
     int p = 0;
     bool overflow = false;
     for (double& x : phase_ms) x = 0.0;
@@ -3958,6 +3968,7 @@ static pch_status geodesic_core(pch_mesh M, const int32_t* sources, int32_t m, d
     stats->pool_windows = (int64_t)T[C_N];
     stats->selected = (int64_t)host_ctl.xcnt[X_SEL1];
     stats->scan_fused = plan_used == kScanFusedReg ? 2 : (plan_used == kScanFused ? 1 : 0);
+    stats->fused_workgroups = fused_wg;
     stats->delta0 = delta0;
   }
   return PCH_OK;

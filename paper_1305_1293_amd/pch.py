@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
                 ("propagate_launches", ctypes.c_int64), ("delta0", ctypes.c_double),
                 ("hop_launches", ctypes.c_int64), ("ms_phase", ctypes.c_double * 4),
                 ("timed_rounds", ctypes.c_int64), ("pool_windows", ctypes.c_int64), ("selected", ctypes.c_int64),
-                ("scan_fused", ctypes.c_int32)]
+                ("scan_fused", ctypes.c_int32), ("fused_workgroups", ctypes.c_int32)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_}

@@ -333,6 +333,10 @@ def test_full_size_bumpy_icosphere_all_vertices(pch, oracle):
     # step, k = 12288, 5 hops, scan and hops in one launch per round
     d, st, _ = gpu_field(pch, m, [s], k=12288, select_mode=1, hops=5)
     assert st["hop_launches"] == 1 and st["scan_fused"] == 2
+    # the 5-hop launch holds three workgroups per compute unit (LDS and
+    # registers both allow three)
+    import torch
+    assert st["fused_workgroups"] == 3 * torch.cuda.get_device_properties(0).multi_processor_count
     assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7, adaptive step, 5 hops")
     say(f"  adaptive step, 5 hops: rounds {st['rounds']} processed {st['processed']}")
 
