@@ -2161,12 +2161,11 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
     } else {
       // the lane's register window of this hop, else one from the list: the
       // lanes without a register window are ranked and take the list's last
-      // windows in rank order
+      // windows in rank order (s_idle, each wavefront's count of such lanes,
+      // was written before the barrier that ended the previous step)
       const bool idle = !rw.has;
       const u64 m = __ballot(idle);
       const u32 wrank = (u32)__popcll(m & ((1ull << lane) - 1ull));
-      if (lane == 0) s_idle[w] = (u32)__popcll(m);
-      __syncthreads();
       u32 rank = wrank;
       for (int q = 0; q < w; ++q) rank += s_idle[q];
       u32 n_idle = 0;
@@ -2199,6 +2198,10 @@ __device__ __forceinline__ void ph_select_propagate(const RoundArgs& a, int p, u
     // to it in this step (children go to the list of the next hop; the last
     // hop appends nothing), so its windows taken above stay intact.
     if (lvl >= 2 && threadIdx.x == 0) l_n[lvl] = rest;
+    // the lanes without a register window, for the next step's ranking (every
+    // thread read the previous counts before the reservation barriers)
+    const u64 idle_next = __ballot(!rw.has);
+    if (lane == 0) s_idle[w] = (u32)__popcll(idle_next);
     // deeper when some lane holds a register window or the next list has
     // windows (the list length is visible after the barrier)
     const int deeper = __syncthreads_or(rw.has ? 1 : 0);
