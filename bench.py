@@ -234,7 +234,7 @@ def measure_icosphere(args, pch, G, torch):
     rng = np.random.default_rng(2024)
     srcs = rng.choice(m.nv, size=args.warmup + args.steps, replace=False).astype(np.int32)
     mesh = pch.Mesh.from_generated(m)
-    opts = dict(k=12288, collect_timing=args.time_every, select_mode=1, hops=5)
+    opts = dict(k=16384, collect_timing=args.time_every, select_mode=1, hops=5)
     wall, tot, phase, hl, _ = single_field_steps(pch, torch, mesh, srcs, args.warmup, opts, keep_first=0)
     errs = []
     if os.path.exists(GOLDEN_C2):
@@ -245,7 +245,7 @@ def measure_icosphere(args, pch, G, torch):
             errs.append(float(np.max(np.abs(d.cpu().numpy() - ref) / np.maximum(ref, hbar))))
     mesh.close()
     kernel = {2: "k_select_propagate_r", 1: "k_select_propagate"}.get(tot["scan_fused"], "k_propagate_fused")
-    tag = "select=1 k=12288 hops=5 fuse_hops=1"
+    tag = "select=1 k=16384 hops=5 fuse_hops=1"
     traffic = profile_value(f"{kernel}_icosphere7_traffic.md", "hbm_bytes_per_launch", tag)
     cflops = profile_value(f"{kernel}_icosphere7_traffic.md", "fp64_flop_per_launch", tag)
     roof, phases = roofline_of(tot, phase, hl, wall, args.steps, traffic, cflops)
@@ -294,7 +294,7 @@ def measure_batched(args, pch, G, torch):
             tp += t
             t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=k_b, select_mode=1, hops=hops_b))
             ts += t
-            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=12288, select_mode=1, hops=5))
+            t, _ = _timed(torch, lambda: pch.geodesic(dm, [srcs[j]], k=16384, select_mode=1, hops=5))
             tb += t
             f = i * 32 + j
             ref = got[b.offsets[f]:b.offsets[f + 1]]
@@ -313,7 +313,7 @@ def measure_batched(args, pch, G, torch):
                                     "plain_kth": round(plain_ms, 1)},
             "single_field_settings": {
                 "same_rule": "adaptive step with the batch's k and hops (equal results bit for bit)",
-                "best_setting": "adaptive step, k 12288, 5 hops, scan and hops in one launch per round",
+                "best_setting": "adaptive step, k 16384, 5 hops, scan and hops in one launch per round",
                 "plain_kth": "k-th-key selection, one face per round, k per mesh the fastest of 4096..32768 on "
                              "its first source"},
             "sample": "2 sources per mesh timed field by field and scaled to 32",

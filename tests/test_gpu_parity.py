@@ -330,8 +330,8 @@ def test_full_size_bumpy_icosphere_all_vertices(pch, oracle):
     assert_close(d, ref, mean_edge(oracle, m), what="icosphere L7")
     say(f"  rounds {st['rounds']} processed {st['processed']}")
     # the launch configuration of the bench line's icosphere object: adaptive
-    # step, k = 12288, 5 hops, scan and hops in one launch per round
-    d, st, _ = gpu_field(pch, m, [s], k=12288, select_mode=1, hops=5)
+    # step, k = 16384, 5 hops, scan and hops in one launch per round
+    d, st, _ = gpu_field(pch, m, [s], k=16384, select_mode=1, hops=5)
     assert st["hop_launches"] == 1 and st["scan_fused"] == 2
     # the 5-hop launch holds three workgroups per compute unit (LDS and
     # registers both allow three)
