@@ -23,7 +23,14 @@ Prints one JSON line. Besides the headline (ms per field) it carries:
   batched      - 512 fields (16 meshes of 14k-330k faces, 32 sources each)
                  in one persistent launch against the single-field path run
                  field after field, both with the best single-field setting
-                 and with plain k-th-key selection.
+                 and with plain k-th-key selection; its roofline carries the
+                 launch's counter-measured HBM bytes and FP64 operations, and
+                 its cpu_baseline the oracle on all host cores (one whole
+                 ICH field per mesh in a pool of processes, in the same
+                 child after the one-core sample).
+
+--workload icosphere and --workload batched run only that leg (for
+profiling its kernels alone).
 
 --workload learned prints a separate line for the learned selection cutoff:
 the network is trained on 200 fields of bumpy icospheres and sets the
@@ -76,7 +83,7 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def profile_value(name: str, key: str, config_tag: str):
+def profile_value(name: str, key: str, config_tag: str, config_key: str = "bench_config"):
     """A per-launch figure from a committed counter summary, or None when the
     summary is missing or the kernel source or configuration changed since."""
     path = os.path.join(ROOT, "profiles", name)
@@ -84,8 +91,8 @@ def profile_value(name: str, key: str, config_tag: str):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    b = re.search(key + r":\s*([0-9.eE+]+)", text)
-    cfg = re.search(r"bench_config:\s*(.+)", text)
+    b = re.search(r"^" + key + r":\s*([0-9.eE+]+)", text, re.M)
+    cfg = re.search(r"^" + config_key + r":\s*(.+)", text, re.M)
     if not m or not b or not cfg or m.group(1) != kernel_source_hash() or cfg.group(1).strip() != config_tag:
         return None
     return float(b.group(1))
@@ -103,10 +110,22 @@ def host_cpu():
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_child(windows: int):
-    """The CPU-baseline leg (child process): sequential ICH on one core over
-    the first `windows` propagated windows of the bump-grid field from vertex
-    0. Prints one JSON line."""
+def _ich_field_seconds(job):
+    """One whole ICH field of a batch mesh (a worker of the all-core leg)."""
+    from oracle import oracle as O
+    i, m, s = job
+    t = time.perf_counter()
+    _, st = O.ich(m, [s])
+    return i, time.perf_counter() - t, st["processed"]
+
+
+def cpu_child(windows: int, batched: bool):
+    """The CPU-baseline legs (child process, no GPU). First sequential ICH on
+    one core over the first `windows` propagated windows of the bump-grid
+    field from vertex 0; then, with `batched`, whole ICH fields of the batch's
+    16 meshes (the first source of each) in a pool of processes over the host
+    cores, leaving two cores to the GPU process. Prints one JSON line per
+    leg."""
     from oracle import oracle as O
     from paper_1305_1293_amd import meshgen as G
     m = G.config_mesh(3)
@@ -115,18 +134,51 @@ def cpu_child(windows: int):
     _, st = O.ich(m, [0], max_processed=windows)
     el = time.perf_counter() - t
     print(json.dumps({"seconds": el, "processed": st["processed"], **host_cpu()}), flush=True)
+    if not batched:
+        return
+    import multiprocessing as mp
+    del m
+    gens = G.batch_meshes(3)
+    jobs = [(i, g, int(g.meta["sources"][0])) for i, g in enumerate(gens)]
+    jobs.sort(key=lambda j: -j[1].nf)  # largest meshes first
+    workers = max(1, min(len(jobs), len(os.sched_getaffinity(0)) - 2))
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = sorted(pool.map(_ich_field_seconds, jobs, chunksize=1))
+    wall = time.perf_counter() - t
+    print(json.dumps({"workers": workers, "wall_s": wall, "field_s": [r[1] for r in res],
+                      "processed": [r[2] for r in res], "fields_per_mesh": int(gens[0].meta["sources"].size),
+                      **host_cpu()}), flush=True)
 
 
-def start_cpu_child(windows: int):
-    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", str(windows)],
-                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+def start_cpu_child(windows: int, batched: bool):
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", str(windows)]
+    if batched:
+        cmd.append("--cpu-child-batched")
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
 
 
 def finish_cpu_child(proc):
     out, err = proc.communicate(timeout=900)
     if proc.returncode != 0:
         raise RuntimeError(f"CPU-baseline child failed ({proc.returncode}): {err[-2000:]}")
-    return json.loads(out.strip().splitlines()[-1])
+    return [json.loads(x) for x in out.strip().splitlines() if x.startswith("{")]
+
+
+def batched_cpu_baseline(c, batch_ms: float) -> dict:
+    """The all-core oracle leg of the batch: ICH times of one field per mesh,
+    scaled to the 32 fields of each mesh and spread evenly over the pool's
+    processes."""
+    per_mesh = np.asarray(c["field_s"]) * c["fields_per_mesh"]
+    est_ms = 1000.0 * float(per_mesh.sum()) / c["workers"]
+    return {"value": round(est_ms, 1), "unit": "ms", "cores": c["workers"], "kind": "oracle",
+            "nproc": c["nproc"], "cpu_model": c["cpu_model"],
+            "sample": f"sequential ICH, one whole field per mesh (its first source, 16 fields) in a pool of "
+                      f"{c['workers']} processes: {sum(c['field_s']):.1f} s of fields in {c['wall_s']:.1f} s "
+                      f"wall; value = the 512 fields (each mesh's field time x {c['fields_per_mesh']}) spread "
+                      f"evenly over the {c['workers']} processes",
+            "field_s_sum": round(float(sum(c["field_s"])), 2), "wall_s": round(c["wall_s"], 2),
+            "gpu_speedup": round(est_ms / batch_ms, 1) if batch_ms > 0 else None}
 
 
 def _timed(torch, fn):
@@ -137,14 +189,41 @@ def _timed(torch, fn):
     return time.perf_counter() - t, r
 
 
-def batch_roofline(windows_per_s: float) -> dict:
-    """Lower bound of a batched launch's algorithmic HBM rate: per processed
-    window the propagation's reads and one window written (events, fans and
-    the pool scans are not counted)."""
+def batch_config_tag(opts: dict) -> str:
+    return " ".join(f"{k}={int(opts[k])}" for k in ("k", "team_threads", "teams_per_cu", "hops", "gang"))
+
+
+def batch_roofline(fs, seconds: float, leg: str, opts: dict) -> dict:
+    """A batched launch (one dispatch of k_batch) against the HBM and FP64
+    peaks. `achieved` is a lower bound of its algorithmic HBM rate: per
+    processed window the propagation's reads and one window written (events,
+    fans and the pool scans are not counted). `traffic` is the launch's HBM
+    bytes and `fp64.counter_flop_per_launch` its issued FP64 lane operations,
+    both from the committed counter summary of this kernel source and batch
+    configuration (null when either changed since)."""
+    processed, created = float(fs[:, 2].sum()), float(fs[:, 3].sum())
     per_window = PROP_READ_BYTES + WINDOW_BYTES
-    achieved = windows_per_s * per_window / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_window": per_window, "lower_bound": True}
+    achieved = processed * per_window / seconds / 1e9
+    flops = FLOP_PER_WINDOW * processed + FLOP_PER_CHILD * created
+    tag = batch_config_tag(opts)
+    traffic = profile_value("k_batch_c4_traffic.md", leg + "_hbm_bytes_per_launch", tag, "bench_config_" + leg)
+    cflops = profile_value("k_batch_c4_traffic.md", leg + "_fp64_flop_per_launch", tag, "bench_config_" + leg)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_window": per_window, "lower_bound": True,
+           "launch_ms": round(1000.0 * seconds, 3), "traffic": traffic,
+           "traffic_gbs": round(traffic / seconds / 1e9, 1) if traffic else None,
+           "traffic_frac": round(traffic / seconds / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+           "traffic_basis": "HBM bytes of the launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scaled by a 512 MiB "
+                            "copy), from the committed counter summary of this kernel source and options"}
+    tflops = flops / seconds / 1e12
+    out["fp64"] = {"bound": "fp64", "achieved": round(tflops, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tflops / FP64_PEAK_TFLOPS, 6), "alg_flop_per_launch": round(flops, 1),
+                   "counter_flop_per_launch": cflops,
+                   "counter_tflops": round(cflops / seconds / 1e12, 4) if cflops else None,
+                   "counter_frac": round(cflops / seconds / 1e12 / FP64_PEAK_TFLOPS, 6) if cflops else None,
+                   "counter_basis": "64 lanes x SQ_INSTS_VALU_FLOPS_FP64 of the launch (FP64 lane operations "
+                                    "issued, FMA as 2), from the committed counter summary"}
+    return out
 
 
 def single_field_steps(pch, torch, mesh, srcs, warmup, opts, keep_first=0):
@@ -280,7 +359,8 @@ def measure_batched(args, pch, G, torch):
     out, _ = b.run(out)  # first run captures the graph and measures each field's time
     dt, (out, st) = _timed(torch, lambda: b.run(out))
     batch_ms = 1000.0 * dt
-    windows = int(b.field_stats()[:, 2].sum())
+    fstats = b.field_stats()
+    windows = int(fstats[:, 2].sum())
     got = out.cpu().numpy()
     ks = (4096, 8192, 16384, 32768)
     plain_ms, same_ms, best_ms, worst = 0.0, 0.0, 0.0, 0.0
@@ -319,7 +399,7 @@ def measure_batched(args, pch, G, torch):
             "sample": "2 sources per mesh timed field by field and scaled to 32",
             "speedup": {"vs_same_rule": round(same_ms / batch_ms, 3), "vs_best_setting": round(best_ms / batch_ms, 3),
                         "vs_plain_kth": round(plain_ms / batch_ms, 3)},
-            "max_rel_diff_vs_plain": worst, "roofline": batch_roofline(windows / dt)}
+            "max_rel_diff_vs_plain": worst, "roofline": batch_roofline(fstats, dt, "c4", opts)}
 
 
 def measure_concurrent(pch, m, mesh, torch):
@@ -334,11 +414,12 @@ def measure_concurrent(pch, m, mesh, torch):
     dt, (out, st) = _timed(torch, lambda: b.run(out))
     same = all(torch.equal(b.field(out, f), pch.geodesic(mesh, [int(fs[f])], k=12288, select_mode=1, hops=5))
                for f in range(8))
-    windows = int(b.field_stats()[:, 2].sum())
+    fstats = b.field_stats()
+    windows = int(fstats[:, 2].sum())
     b.close()
     return {"fields": int(fs.size), "ms": round(1000.0 * dt, 2), "ms_per_field": round(1000.0 * dt / fs.size, 4),
             "windows_per_s": round(windows / dt, 1), "options": opts, "reruns": int(st["reruns"]),
-            "equal_to_single_field_runs": bool(same), "roofline": batch_roofline(windows / dt)}
+            "equal_to_single_field_runs": bool(same), "roofline": batch_roofline(fstats, dt, "same_mesh", opts)}
 
 
 def measure_learned_batched(pch, G, Lr, mlp, torch):
@@ -451,9 +532,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["field", "learned", "icosphere"], default="field",
-                    help="field: the bench line; learned: the learned-cutoff comparison; icosphere: only the "
-                         "icosphere leg (for profiling its kernels alone)")
+    ap.add_argument("--workload", choices=["field", "learned", "icosphere", "batched"], default="field",
+                    help="field: the bench line; learned: the learned-cutoff comparison; icosphere, batched: "
+                         "only that leg (for profiling its kernels alone)")
     ap.add_argument("--k", type=int, default=524288, help="windows selected per round (bump grid)")
     ap.add_argument("--select", type=int, default=1, help="0: k-th smallest key, 1: adaptive step")
     ap.add_argument("--delta0", type=float, default=0.0, help="first adaptive step (0 = 2x mean edge)")
@@ -474,12 +555,13 @@ def main():
                     help="autotuner cache read before the batched measurement")
     ap.add_argument("--tune-cache-save", default="", help="write the autotuner cache here after a tuning run")
     ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-child-batched", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 5 times (the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.cpu_child:
-        cpu_child(args.cpu_child)
+        cpu_child(args.cpu_child, args.cpu_child_batched)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's fields are "
@@ -488,7 +570,7 @@ def main():
     # the CPU-oracle leg runs beside the GPU legs, started before any GPU call
     child = None
     if args.workload == "field" and not args.no_cpu_baseline and args.copy_bytes == 0:
-        child = start_cpu_child(args.cpu_windows)
+        child = start_cpu_child(args.cpu_windows, not args.no_batched)
 
     import torch
 
@@ -511,6 +593,13 @@ def main():
         return
     if args.workload == "icosphere":
         print(json.dumps(measure_icosphere(args, pch, G, torch)), flush=True)
+        return
+    if args.workload == "batched":
+        mi = G.config_mesh(2)
+        dmi = pch.Mesh.from_generated(mi)
+        print(json.dumps({"batched": measure_batched(args, pch, G, torch),
+                          "same_mesh_concurrent": measure_concurrent(pch, mi, dmi, torch)}), flush=True)
+        dmi.close()
         return
     m = G.config_mesh(3)
     rng = np.random.default_rng(2024)
@@ -552,7 +641,10 @@ def main():
 
     cpu = None
     if child is not None:
-        c = finish_cpu_child(child)
+        legs = finish_cpu_child(child)
+        c = legs[0]
+        if batched is not None and len(legs) > 1:
+            batched["cpu_baseline"] = batched_cpu_baseline(legs[1], batched["ms"])
         full = None
         if os.path.exists(GOLDEN_C3):
             full = int(np.load(GOLDEN_C3)["processed"])
