@@ -546,7 +546,7 @@ def main():
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
     ap.add_argument("--hops-learned", type=int, default=5, help="hops of the learned-cutoff comparison")
     ap.add_argument("--learned-sources", type=int, default=4, help="sources per test mesh (learned workload)")
-    ap.add_argument("--time-every", type=int, default=8,
+    ap.add_argument("--time-every", type=int, default=32,
                     help="time the phases of every n-th round with HIP events")
     ap.add_argument("--cpu-windows", type=int, default=CPU_SAMPLE_WINDOWS,
                     help="windows of the CPU-oracle sample")

@@ -254,17 +254,24 @@ def test_tune_keeps_fields_exact(pch, setup):
 
 def test_full_size_batch_every_field(pch, oracle):
     """The 512-field batch at full size (16 meshes of 14k-330k faces, 32
-    sources each) with the benchmark's options: every field equals its
-    single-field run with the same rule, k and hops bit for bit, and the
-    first field of every mesh is within 1e-9 of ICH."""
+    sources each) with the benchmark's options (the choice the committed
+    tuner cache records for this batch): every field equals its single-field
+    run with the same rule, k and hops bit for bit, and the first field of
+    every mesh is within 1e-9 of ICH."""
+    import os
     import torch
     gens = G.batch_meshes(3)
     meshes = [pch.Mesh.from_generated(m) for m in gens]
     fm = np.repeat(np.arange(len(gens)), 32).astype(np.int32)
     fs = np.concatenate([m.meta["sources"] for m in gens]).astype(np.int32)
-    k, hops = 32768, 4
-    b = pch.Batch(meshes, fm, fs, k=k, team_threads=512, teams_per_cu=1, hops=hops, gang=8)
-    say(f"batch of {b.n_fields} fields on {len(gens)} meshes")
+    cache = os.path.join(os.path.dirname(os.path.abspath(pch.__file__)), "tune_cache.txt")
+    assert os.path.exists(cache)
+    pch.tune_cache_load(cache)
+    b = pch.Batch(meshes, fm, fs, k=32768, team_threads=512, teams_per_cu=1, hops=4, gang=8)
+    chosen, hit = b.tune_cached()
+    k, hops = int(chosen["k"]), int(chosen["hops"])
+    say(f"batch of {b.n_fields} fields on {len(gens)} meshes, cache hit {hit}: k {k} hops {hops} "
+        f"team {chosen['team_threads']} gang {chosen['gang']}")
     out, _ = b.run()
     out, st = b.run(out)  # a graph replay, as timed by the benchmark
     torch.cuda.synchronize()
