@@ -125,7 +125,9 @@ def cpu_child(windows: int, batched: bool):
     one core over the first `windows` propagated windows of the bump-grid
     field from vertex 0; then, with `batched`, whole ICH fields of the batch's
     16 meshes (the first source of each) in a pool of processes over the host
-    cores, leaving two cores to the GPU process. Prints one JSON line per
+    cores, leaving two cores to the GPU process; that leg waits for a line on
+    stdin, which the parent writes once its GPU legs are over, so that the
+    pool does not compete with them for host cores. Prints one JSON line per
     leg."""
     from oracle import oracle as O
     from paper_1305_1293_amd import meshgen as G
@@ -137,6 +139,7 @@ def cpu_child(windows: int, batched: bool):
     print(json.dumps({"seconds": el, "processed": st["processed"], **host_cpu()}), flush=True)
     if not batched:
         return
+    sys.stdin.readline()  # the GPU legs are over (or the parent is gone)
     import multiprocessing as mp
     del m
     gens = G.batch_meshes(3)
@@ -156,11 +159,11 @@ def start_cpu_child(windows: int, batched: bool):
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", str(windows)]
     if batched:
         cmd.append("--cpu-child-batched")
-    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    return subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
 
 
 def finish_cpu_child(proc):
-    out, err = proc.communicate(timeout=900)
+    out, err = proc.communicate(input="go\n", timeout=900)
     if proc.returncode != 0:
         raise RuntimeError(f"CPU-baseline child failed ({proc.returncode}): {err[-2000:]}")
     return [json.loads(x) for x in out.strip().splitlines() if x.startswith("{")]
