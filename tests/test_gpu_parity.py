@@ -394,3 +394,21 @@ def test_round_graph_replays_equal_launch_by_launch(pch, oracle):
     d_ich, _ = oracle.ich(m, [77])
     assert np.max(np.abs(ref[77] - d_ich) / np.maximum(d_ich, mean_edge(oracle, m))) <= 1e-9
     dm.close()
+
+
+@pytest.mark.parametrize("hops", [1, 5])
+def test_degenerate_inputs_gpu(pch, oracle, hops):
+    """Two components (the one without a source stays +inf, with both sources
+    each component takes its own field), a single triangle from each corner,
+    and a repeated source: every field equals ICH at every vertex."""
+    from test_oracle_invariants import _two_components
+    m, na = _two_components()
+    hbar = mean_edge(oracle, m)
+    for srcs in ([3], [3, na + 7], [na + 7, na + 7]):
+        say(f"two components, sources {srcs}, hops {hops}")
+        d, st, _ = gpu_field(pch, m, srcs, k=256, select_mode=1, hops=hops)
+        assert_close(d, oracle.ich(m, srcs)[0], hbar, what=f"two components {srcs}")
+    tri = G.Mesh("triangle", np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.3, 0.8, 0.0]]), np.array([[0, 1, 2]]))
+    for s in range(3):
+        d, st, _ = gpu_field(pch, tri, [s], k=16, hops=hops)
+        assert np.max(np.abs(d - np.linalg.norm(tri.xyz - tri.xyz[s], axis=1))) <= 1e-15, s

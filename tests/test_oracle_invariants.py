@@ -196,3 +196,28 @@ def test_ich_and_replica_agree(oracle, case):
         fin = np.isfinite(d)
         assert np.array_equal(fin, np.isfinite(dr)), kw
         assert np.max(np.abs(d[fin] - dr[fin]) / np.maximum(d[fin], hbar)) < 1e-12, kw
+
+
+def _two_components():
+    a = G.sinusoid_grid(12, seed=0)
+    b = G.jittered_plane(9, seed=3)
+    xyz = np.concatenate([a.xyz, b.xyz + np.array([3.0, 0.0, 0.5])])
+    faces = np.concatenate([a.faces, b.faces + a.nv])
+    return G.Mesh("two_components", xyz, faces), a.nv
+
+
+def test_degenerate_inputs(oracle):
+    """A mesh of two components leaves the one without a source unreachable
+    (+inf) in ICH and the replica, and reaching the other from both sources
+    gives the minimum of the two single fields; on a single triangle the
+    distances are the straight edges."""
+    m, na = _two_components()
+    for d in (oracle.ich(m, [3])[0], oracle.replica(m, [3], k=64)[0]):
+        assert np.isinf(d[na:]).all() and np.isfinite(d[:na]).all()
+    d_both = oracle.ich(m, [3, na + 7])[0]
+    d_a, d_b = oracle.ich(m, [3])[0], oracle.ich(m, [na + 7])[0]
+    assert np.array_equal(d_both, np.minimum(d_a, d_b))
+    tri = G.Mesh("triangle", np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.3, 0.8, 0.0]]), np.array([[0, 1, 2]]))
+    for s in range(3):
+        d = oracle.ich(tri, [s])[0]
+        assert np.allclose(d, np.linalg.norm(tri.xyz - tri.xyz[s], axis=1), rtol=0, atol=1e-15)
