@@ -412,3 +412,18 @@ def test_degenerate_inputs_gpu(pch, oracle, hops):
     for s in range(3):
         d, st, _ = gpu_field(pch, tri, [s], k=16, hops=hops)
         assert np.max(np.abs(d - np.linalg.norm(tri.xyz - tri.xyz[s], axis=1))) <= 1e-15, s
+
+
+def test_metric_only_mesh_matches_coordinates(pch, oracle):
+    """The same bump grid given by coordinates and by its edge lengths only
+    (pch_mesh_create_from_lengths, Section 4.1: the method needs the metric
+    alone): both fields equal ICH at every vertex."""
+    m = G.bump_grid(48, seed=4)
+    he = oracle.lengths(m)
+    mm = G.Mesh("bump48_metric", None, m.faces, he_len=he, nv=m.nv)
+    hbar = mean_edge(oracle, m)
+    ref = oracle.ich(m, [5])[0]
+    for mesh, what in ((m, "coordinates"), (mm, "lengths")):
+        d, st, _ = gpu_field(pch, mesh, [5], k=1024, select_mode=1, hops=5)
+        say(f"{what}: rounds {st['rounds']} processed {st['processed']}")
+        assert_close(d, ref, hbar, what=what)
