@@ -28,7 +28,11 @@ Prints one JSON line. Besides the headline (ms per field) it carries:
                  launch's counter-measured HBM bytes and FP64 operations, and
                  its cpu_baseline the oracle on all host cores (one whole
                  ICH field per mesh in a pool of processes, in the same
-                 child after the one-core sample).
+                 child, after the one-core sample and the GPU legs);
+  learned_batched - the same 512 fields in one launch with the learned
+                 cutoff (the network trained first, on the GPU, on 200 PCH
+                 fields of bumpy icospheres), against the chord-length
+                 ablation, the adaptive step and plain PCH field by field.
 
 --workload icosphere and --workload batched run only that leg (for
 profiling its kernels alone).
@@ -481,9 +485,9 @@ def measure_learned_batched(pch, G, Lr, mlp, torch):
                     "fields (predict_ms) to the learned and chord launches"}
 
 
-def measure_learned(args, pch, G, torch):
-    """Learned selection cutoff on the 1024 x 1024 bump grids against the same
-    rule without the network and the other selection rules."""
+def train_network(pch, G, torch):
+    """The cutoff network trained on the GPU with the library's kernels on 200
+    exact fields of bumpy icospheres that PCH itself computes."""
     from paper_1305_1293_amd import learned as Lr
     train, test = G.learned_cutoff_sets(4)
     t0 = time.perf_counter()
@@ -491,7 +495,16 @@ def measure_learned(args, pch, G, torch):
     mlp = pch.MLP(7)
     losses = Lr.train(mlp, data, epochs=6, batch=16384, lr=2e-3, log_every=50)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    info = {"samples": int(data.feats.shape[0]), "seconds": round(time.perf_counter() - t0, 2),
+            "loss_first": losses[0], "loss_last": losses[-1]}
+    return mlp, test, info
+
+
+def measure_learned(args, pch, G, torch):
+    """Learned selection cutoff on the 1024 x 1024 bump grids against the same
+    rule without the network and the other selection rules."""
+    from paper_1305_1293_amd import learned as Lr
+    mlp, test, training = train_network(pch, G, torch)
     k, hops = args.k_learned, args.hops_learned
     names = ("learned", "chord", "adaptive_step", "kth")
     rows = {n: [] for n in names}
@@ -530,8 +543,7 @@ def measure_learned(args, pch, G, torch):
             "windows_per_field": {n: float(mean[n][2]) for n in names},
             "max_rel_diff_vs_learned": err,
             "batched": batched,
-            "training": {"samples": int(data.feats.shape[0]), "seconds": round(train_s, 2),
-                         "loss_first": losses[0], "loss_last": losses[-1]}}
+            "training": training}
 
 
 def main():
@@ -550,6 +562,8 @@ def main():
                     help="1: all hops of a round in one propagation launch (hops <= 6); 0: one launch per hop")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
     ap.add_argument("--no-icosphere", action="store_true", help="skip the icosphere measurement")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-cutoff batched leg of the bench line (training included)")
     ap.add_argument("--ico-steps", type=int, default=100, help="timed fields of the icosphere leg")
     ap.add_argument("--k-learned", type=int, default=131072, help="k of the learned-cutoff comparison")
     ap.add_argument("--hops-learned", type=int, default=5, help="hops of the learned-cutoff comparison")
@@ -646,6 +660,12 @@ def main():
         dmi = pch.Mesh.from_generated(mi)
         concurrent = measure_concurrent(pch, mi, dmi, torch)
         dmi.close()
+    learned_batched = None
+    if not args.no_batched and not args.no_learned:
+        from paper_1305_1293_amd import learned as Lr
+        print("bench: learned cutoff, batched", file=sys.stderr, flush=True)
+        mlp, _, training = train_network(pch, G, torch)
+        learned_batched = dict(measure_learned_batched(pch, G, Lr, mlp, torch), training=training)
 
     cpu = None
     if child is not None:
@@ -693,6 +713,7 @@ def main():
         "icosphere": ico,
         "batched": batched,
         "same_mesh_concurrent": concurrent,
+        "learned_batched": learned_batched,
     }
     print(json.dumps(line), flush=True)
     mesh.close()
