@@ -119,11 +119,16 @@ def batch_predictions(mlp, gens: Sequence, field_mesh, field_source, offsets, ch
     lengths (the same rule without the network). Returns a device float
     tensor for Batch(..., predicted=...)."""
     import torch
-    out = torch.empty(int(offsets[-1]), dtype=torch.float32, device="cuda")
+    n = int(offsets[-1])
+    feats = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+    base = torch.empty(n, dtype=torch.float32, device="cuda")
     xyz = [torch.from_numpy(g.xyz).to("cuda") for g in gens]
     frames = [frame_of(g) for g in gens]
+    # every field's features straight into its slice of one buffer, then one
+    # network pass over all of them (each sample's prediction depends on its
+    # own features only)
     for f, (mi, s) in enumerate(zip(field_mesh, field_source)):
         c, r = frames[int(mi)]
-        feats, base = pch.MLP.features(xyz[int(mi)], int(s), c, r)
-        out[int(offsets[f]):int(offsets[f + 1])] = base if chord else mlp.forward(feats, base)
-    return out
+        o0, o1 = int(offsets[f]), int(offsets[f + 1])
+        pch.MLP.features(xyz[int(mi)], int(s), c, r, feats=feats[o0:o1], base=base[o0:o1])
+    return base if chord else mlp.forward(feats, base)

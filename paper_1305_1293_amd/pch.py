@@ -461,20 +461,33 @@ class MLP:
         _check(_mlp_lib().pch_mlp_set_params(self.handle, p.ctypes.data))
 
     @staticmethod
-    def features(xyz_dev, source: int, center, radius: float, stream=None):
+    def features(xyz_dev, source: int, center, radius: float, stream=None, feats=None, base=None):
+        """Features [nv, 7] and chord lengths [nv] of one field; feats and
+        base may be given (contiguous float32 device views of those shapes,
+        for instance slices of one buffer holding many fields)."""
         import torch
         nv = int(xyz_dev.shape[0])
-        feats = torch.empty((nv, 7), dtype=torch.float32, device=xyz_dev.device)
-        base = torch.empty(nv, dtype=torch.float32, device=xyz_dev.device)
+        if feats is None:
+            feats = torch.empty((nv, 7), dtype=torch.float32, device=xyz_dev.device)
+        if base is None:
+            base = torch.empty(nv, dtype=torch.float32, device=xyz_dev.device)
+        if tuple(feats.shape) != (nv, 7) or tuple(base.shape) != (nv,) or not (feats.is_contiguous()
+                                                                              and base.is_contiguous()):
+            raise ValueError("feats must be a contiguous [nv, 7] and base a contiguous [nv] float32 tensor")
+        if feats.dtype != torch.float32 or base.dtype != torch.float32:
+            raise ValueError("feats and base must be float32")
         c = np.ascontiguousarray(center, dtype=np.float64)
         _check(_mlp_lib().pch_mlp_features(xyz_dev.data_ptr(), nv, int(source), c.ctypes.data, float(radius),
                                            feats.data_ptr(), base.data_ptr(), _stream_handle(stream)))
         return feats, base
 
-    def forward(self, feats, base, stream=None):
+    def forward(self, feats, base, stream=None, out=None):
         import torch
         n = int(feats.shape[0])
-        out = torch.empty(n, dtype=torch.float32, device=feats.device)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=feats.device)
+        if tuple(out.shape) != (n,) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of the samples' count")
         _check(_mlp_lib().pch_mlp_forward(self.handle, feats.data_ptr(), base.data_ptr(), n, out.data_ptr(),
                                           _stream_handle(stream)))
         return out
